@@ -1,0 +1,154 @@
+"""Pins of the CPU oracle against things other than itself (no GPU).
+
+* hand-derived fixtures (tests/golden/reach_fixtures.json, stream_fixtures.json)
+* the closed form for N independent cyclic L-state processes
+* brute-force product enumeration with distance relaxation (oracle/brute.py),
+  an independent algorithm, on >= 100 seeded tiny guarded models, capped and not
+* an O(n^2) pure-Python definition of sequential find-or-put on small streams
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from oracle.brute import brute
+from oracle.closed_form import cyclic_capped, cyclic_level_counts, cyclic_summary
+
+from conftest import load_golden, model_from_fixture, result_fields
+
+
+@pytest.mark.parametrize("fx", load_golden("reach_fixtures.json")["fixtures"], ids=lambda f: f["name"])
+def test_reach_golden(fx):
+    m = model_from_fixture(fx)
+    for case in fx["cases"]:
+        want = {k: case[k] for k in ("total", "level_counts", "edges", "deadlocks", "capped")}
+        want["n_levels"] = len(case["level_counts"])
+        got = result_fields(oracle.reach(m, cap=case["cap"]))
+        assert got == want, (fx["name"], case["cap"])
+        assert result_fields(brute(m, cap=case["cap"])) == want, (fx["name"], case["cap"])
+
+
+@pytest.mark.parametrize("N,L", [(1, 1), (1, 5), (2, 2), (2, 3), (3, 4), (4, 8), (5, 3), (2, 16), (6, 2)])
+def test_reach_closed_form(N, L):
+    m = gen.cyclic_model(N, L)
+    assert result_fields(oracle.reach(m, cap=0)) == cyclic_summary(N, L)
+    total = L ** N
+    for cap in sorted({1, 2, max(1, total // 3), max(1, total - 1), total}):
+        assert result_fields(oracle.reach(m, cap=cap)) == cyclic_capped(N, L, cap), cap
+
+
+def test_closed_form_sanity():
+    # the inclusion-exclusion formula against direct counting of digit sums
+    for N, L in [(2, 3), (3, 4), (4, 8), (3, 5)]:
+        direct = np.bincount([sum(x) for x in itertools.product(range(L), repeat=N)])
+        assert cyclic_level_counts(N, L) == direct.tolist()
+
+
+def _tiny_models(n, seed0=1234):
+    rng = np.random.default_rng(seed0)
+    for i in range(n):
+        P = int(rng.integers(1, 4))
+        L = int(rng.integers(1, 5))
+        S = int(rng.integers(0, 3))
+        D = int(rng.integers(1, 4))
+        K = int(rng.integers(1, 4))
+        yield gen.guarded_model(1000 + i, P, L, S, D if S else 1, K)
+
+
+def test_brute_vs_oracle_random_models():
+    n_capped = 0
+    rng = np.random.default_rng(7)
+    for m in _tiny_models(160):
+        full = brute(m, cap=0)
+        assert result_fields(oracle.reach(m, cap=0)) == full, m.describe()
+        cap = int(rng.integers(1, full["total"] + 2))
+        b = brute(m, cap=cap)
+        n_capped += b["capped"]
+        assert result_fields(oracle.reach(m, cap=cap)) == b, (m.describe(), cap)
+    assert n_capped >= 40
+
+
+def test_brute_vs_oracle_state_sets():
+    for m in itertools.islice(_tiny_models(60, seed0=99), 60):
+        b = brute(m, cap=0, with_states=True)
+        r = oracle.reach(m, cap=0, keep_states=True)
+        got = sorted(map(tuple, r.states.tolist()))
+        want = sorted(map(tuple, b["states"].tolist()))
+        assert got == want
+        # BFS order: the oracle's rows come level by level
+        dist = {tuple(s): int(d) for s, d in zip(b["states"].tolist(), b["dist"])}
+        levels = [dist[tuple(s)] for s in r.states.tolist()]
+        assert levels == sorted(levels)
+
+
+def test_successors_by_hand():
+    fx = [f for f in load_golden("reach_fixtures.json")["fixtures"] if f["name"] == "one_shot_lock"][0]
+    m = model_from_fixture(fx)
+    assert oracle.successors(m, [0, 0, 0]).tolist() == [[1, 0, 0], [0, 1, 0]]
+    assert oracle.successors(m, [1, 1, 0]).tolist() == [[2, 1, 1], [1, 2, 1]]
+    assert oracle.successors(m, [2, 0, 1]).tolist() == []
+
+
+@pytest.mark.parametrize("fx", load_golden("stream_fixtures.json")["fixtures"], ids=lambda f: f["name"])
+def test_stream_golden(fx):
+    seen, ids, d = oracle.stream(np.array(fx["rows"], dtype=np.uint32))
+    assert seen.tolist() == fx["seen"] and ids.tolist() == fx["id"] and d == fx["distinct"]
+
+
+def _stream_by_definition(rows):
+    seen, ids, firsts = [], [], []
+    for k, r in enumerate(rows):
+        hit = [j for j in range(k) if rows[j] == r]
+        seen.append(1 if hit else 0)
+        if hit:
+            ids.append(ids[hit[0]])
+        else:
+            ids.append(len(firsts))
+            firsts.append(k)
+    return seen, ids, len(firsts)
+
+
+@pytest.mark.parametrize("W,pool,n", [(1, 5, 40), (2, 30, 200), (4, 200, 300), (16, 50, 150), (32, 3, 20)])
+def test_stream_vs_definition(W, pool, n):
+    rng = np.random.default_rng(W * 1000 + pool)
+    base = rng.integers(0, 4, size=(pool, W)).astype(np.uint32)
+    rows = base[rng.integers(0, pool, size=n)]
+    seen, ids, d = oracle.stream(rows)
+    s2, i2, d2 = _stream_by_definition([tuple(r) for r in rows.tolist()])
+    assert seen.tolist() == s2 and ids.tolist() == i2 and d == d2
+
+
+def test_digest_properties():
+    rows = gen.words(5, 64 * 16).reshape(64, 16)
+    d = oracle.digest(rows)
+    assert oracle.digest(rows[::-1].copy()) == d                      # order-independent
+    flipped = rows.copy()
+    flipped[3, 7] ^= 1
+    assert oracle.digest(flipped) != d                                 # sensitive to one bit
+    assert oracle.digest(rows[:63].copy())[0] == 63
+
+
+def test_generators_deterministic_and_in_range():
+    a = gen.guarded_model(42, 12, 16, 4, 10, 3)
+    b = gen.guarded_model(42, 12, 16, 4, 10, 3)
+    c = gen.guarded_model(43, 12, 16, 4, 10, 3)
+    assert np.array_equal(a.trans, b.trans) and not np.array_equal(a.trans, c.trans)
+    t = a.trans.reshape(-1, 5)
+    assert t[:, 0].max() < 16 and t[:, 1].max() < 4 and t[:, 2].max() < 10
+    assert t[:, 3].max() < 4 and t[:, 4].max() < 10
+    rows, order = gen.dup_stream(7, 1000, 16, 2)
+    assert np.array_equal(np.bincount(order, minlength=1000), np.full(1000, 2))
+    r2, o2 = gen.dup_stream(7, 1000, 16, 2)
+    assert np.array_equal(rows, r2) and np.array_equal(order, o2)
+    # xorshift64 (13, 7, 17) from seed 1: first outputs by the definition
+    x, out = 1, []
+    for _ in range(4):
+        x ^= (x << 13) & 0xFFFFFFFFFFFFFFFF
+        x ^= x >> 7
+        x ^= (x << 17) & 0xFFFFFFFFFFFFFFFF
+        out.append(x)
+    assert gen.xs64(1, 4).tolist() == out
+    p = gen.permutation(3, 1000)
+    assert sorted(p.tolist()) == list(range(1000))
