@@ -1,0 +1,276 @@
+#!/usr/bin/env python3
+"""Benchmark of the lockless find-or-put table on one MI355X.
+
+Headline step (the raw find-or-put workload): a stream of 2^26 state vectors
+of 16 x uint32, 2^25 distinct rows each occurring twice in a seeded shuffled
+order (50 % exact duplicates), inserted into an empty 2^28-slot table with one
+batched find-or-put call.  A step = clear the table + the find-or-put pass;
+the value is find-or-put operations per second over the timed steps, with the
+inputs already resident in HBM.
+
+Extra legs in the same JSON line:
+  roofline     : the find-or-put kernel's algorithmic bytes per launch over its
+                 average duration (HIP events on the launch stream), against
+                 the 8 TB/s HBM peak; hardware traffic from committed rocprofv3
+                 counter summaries when they match the current kernel source.
+  probes       : measured ceilings: random 128-B line reads (per lane and
+                 8-lane cooperative) and random 64-bit CAS throughput.
+  bfs          : level-synchronous BFS of the 12-process x 16-local synthetic
+                 model capped at 2^27 states (states/s, edges/s).
+  cpu_baseline : the CPU oracle (sequential find-or-put) timed on a bounded
+                 prefix of the same stream, one host thread.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "states/sec and find-or-put ops/sec at 1 GPU; % of HBM random-access roofline"
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+FOP_SOURCES = ["paper_1004_2772_amd/csrc/lhs_device.h", "paper_1004_2772_amd/csrc/lhs_table.hip"]
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def source_sha(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def fop_bytes_per_op(W):
+    """Algorithmic bytes of one find-or-put: input row, one 128-B slot line,
+    one row of data (written if new, compared if seen), seen byte + index."""
+    return 4 * W + 128 + 4 * W + 1 + 4
+
+
+def load_traffic(kernel, workload, n_launch_ops):
+    """Hardware bytes per launch from a committed counter summary, or None
+    if it is missing or was taken on different kernel source."""
+    path = os.path.join(PROFILES, f"{kernel}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None, None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha") != source_sha(FOP_SOURCES) or t.get("ops_per_launch") != n_launch_ops:
+        return None, t
+    return int(t["fetch_bytes"] + t["write_bytes"]), t
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--distinct", type=int, default=1 << 25, help="distinct rows (each twice)")
+    ap.add_argument("--table-log2", type=int, default=28)
+    ap.add_argument("--batch", type=int, default=0, help="rows per call (0 = whole stream)")
+    ap.add_argument("--no-bfs", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-probes", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true", help="also run the copy probe (counter calibration)")
+    ap.add_argument("--bfs-cap", type=int, default=1 << 27)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 25)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures a single GPU; this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1004_2772_amd as lhs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    lhs.lib()   # fails loudly if the HIP library is missing
+
+    W = gen.STREAM_W
+    n_distinct = args.distinct
+    n = 2 * n_distinct
+    batch = args.batch or n
+    log(f"generating stream: {n} rows of {W} words ({n_distinct} distinct)")
+    rows, order = gen.stream_workload(n_distinct=n_distinct, W=W)
+    rows_d = torch.from_numpy(rows.view(np.int32)).to(dev)
+    order_d = torch.from_numpy(order.astype(np.int64)).to(dev)
+    states_d = rows_d.index_select(0, order_d)          # input resident in HBM
+    del rows_d, order_d
+    seen_d = torch.empty(n, dtype=torch.uint8, device=dev)
+    idx_d = torch.empty(n, dtype=torch.int32, device=dev)
+    table = lhs.Table(1 << args.table_log2, W)
+    torch.cuda.synchronize()
+
+    kernel_events = []
+
+    def step(record):
+        table.clear()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for lo in range(0, n, batch):
+            hi = min(n, lo + batch)
+            table.find_or_put(states_d[lo:hi], seen_d[lo:hi], idx_d[lo:hi])
+        e1.record(stream)
+        if record:
+            kernel_events.append((e0, e1))
+
+    for i in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    table.check()
+    log(f"warmup done ({args.warmup} steps)")
+
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.time()
+    t0.record(stream)
+    for i in range(args.steps):
+        step(True)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.time() - wall0
+    total_ms = t0.elapsed_time(t1)
+    ms_per_step = total_ms / args.steps
+    kern_ms = sum(a.elapsed_time(b) for a, b in kernel_events) / len(kernel_events)
+    n_launch = (n + batch - 1) // batch
+    launch_ms = kern_ms / n_launch
+    table.check()
+    new = int((seen_d == 0).sum().item())
+    stored = table.count()
+    ok = new == n_distinct and stored == n_distinct and int((seen_d > 1).sum().item()) == 0
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, find-or-put {kern_ms:.3f} ms, "
+        f"new={new} stored={stored} ok={ok}")
+    info = table.info()
+
+    ops_per_s = n / (ms_per_step / 1e3)
+    bpo = fop_bytes_per_op(W)
+    launch_ops = min(batch, n)
+    achieved = bpo * launch_ops / (launch_ms / 1e3) / 1e9
+    traffic, tinfo = load_traffic("k_find_or_put", "stream2p26", launch_ops)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_find_or_put", "avg_launch_ms": round(launch_ms, 4),
+                "algorithmic_bytes_per_op": bpo, "ops_per_launch": launch_ops}
+    if tinfo is not None:
+        roofline["traffic_source"] = os.path.basename(tinfo.get("summary", ""))
+        if traffic:
+            roofline["traffic_over_algorithmic"] = round(traffic / (bpo * launch_ops), 3)
+
+    out = {
+        "metric": METRIC, "value": round(ops_per_s, 1), "unit": "find-or-put ops/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"find-or-put stream: {n} rows of {W} x uint32 ({n_distinct} distinct, "
+                               f"each twice, shuffled), table 2^{args.table_log2} slots, "
+                               f"{n_launch} call(s) per step",
+                   "ops": n, "distinct": n_distinct, "state_words": W,
+                   "table_slots": 1 << args.table_log2, "batch": launch_ops,
+                   "load_factor": round(n_distinct / (1 << args.table_log2), 4)},
+        "roofline": roofline,
+        "checks": {"new_equals_distinct": ok, "wait_hits": info["wait_hits"],
+                   "cas_failures": info["cas_failures"]},
+        "wall_s_timed": round(wall, 3),
+    }
+
+    if not args.no_probes:
+        sink = torch.zeros(1, dtype=torch.int64, device=dev)
+        buf = torch.empty(1 << 32, dtype=torch.int32, device=dev)     # 16 GiB
+        probes = {}
+        for lanes in (1, 8):
+            reads = 1 << 27
+            lhs.probe_random_lines(buf, lanes, reads, 1, sink)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            lhs.probe_random_lines(buf, lanes, reads, 2, sink)
+            b.record(stream)
+            torch.cuda.synchronize()
+            probes[f"random_128B_lines_{lanes}lane_GBs"] = round(reads * 128 / (a.elapsed_time(b) / 1e3) / 1e9, 1)
+        del buf
+        slots = torch.zeros(1 << 28, dtype=torch.int64, device=dev)
+        ops = 1 << 26
+        lhs.probe_random_cas(slots, ops, 3, sink)
+        slots.zero_()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        lhs.probe_random_cas(slots, ops, 4, sink)
+        b.record(stream)
+        torch.cuda.synchronize()
+        probes["random_cas64_Gops"] = round(ops / (a.elapsed_time(b) / 1e3) / 1e9, 3)
+        del slots
+        probes["fop_frac_of_random_line_1lane"] = round(
+            achieved / probes["random_128B_lines_1lane_GBs"], 4)
+        out["probes"] = probes
+        log(f"probes: {probes}")
+
+    if args.calib_copy:
+        src = torch.empty(1 << 28, dtype=torch.int32, device=dev)        # 1 GiB
+        dst = torch.empty_like(src)
+        lhs.probe_copy(dst, src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = src.numel() * 4
+        del src, dst
+
+    if not args.no_bfs:
+        m = gen.big_model(cap=args.bfs_cap)
+        runs = []
+        res = None
+        for i in range(1 + max(1, min(args.steps, 3))):
+            w0 = time.time()
+            res = lhs.reach_explore(m, table=table)
+            if i:
+                runs.append((res.gpu_ms, time.time() - w0))
+            log(f"bfs run {i}: {res.total} states, {res.n_levels} levels, {res.gpu_ms:.1f} ms")
+        gms = sorted(r[0] for r in runs)[len(runs) // 2]
+        bfs = {"workload": f"BFS of G(seed={m.seed}, P=12, L=16, S=4, D={m.D}, K=3), "
+                           f"level-prefix cap {args.bfs_cap}, table 2^{args.table_log2}",
+               "states": res.total, "levels": res.n_levels, "edges": res.edges,
+               "deadlocks": res.deadlocks, "capped": res.capped, "median_ms": round(gms, 2),
+               "states_per_s": round(res.total / (gms / 1e3), 1),
+               "edges_per_s": round(res.edges / (gms / 1e3), 1), "wait_hits": res.wait_hits}
+        golden = os.path.join(ROOT, "tests", "golden", "big_model.json")
+        if os.path.exists(golden) and args.bfs_cap == 1 << 27:
+            with open(golden) as f:
+                g = json.load(f)
+            bfs["matches_oracle_counts"] = (g["level_counts"] == res.level_counts and
+                                            g["edges"] == res.edges and g["deadlocks"] == res.deadlocks)
+        out["bfs"] = bfs
+
+    table.close()
+    del states_d, seen_d, idx_d
+
+    if not args.no_cpu:
+        import oracle
+        S = min(args.cpu_sample, n)
+        sample = gen.gather(rows, order[:S])
+        c0 = time.time()
+        _, _, d = oracle.stream(sample)
+        cdt = time.time() - c0
+        out["cpu_baseline"] = {"value": round(S / cdt, 1), "unit": "find-or-put ops/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"first {S} rows of the same stream ({d} distinct), "
+                                         f"sequential std::unordered_map find-or-put, {cdt:.1f} s"}
+        log(f"cpu baseline: {S / cdt:.0f} ops/s over {S} rows")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * lhs — lockless GPU state storage and level-synchronous reachability for
+ * MI355X (gfx950).  Plain C ABI: no C++ or framework types cross it.
+ *
+ * Paper: A. Laarman, J. van de Pol, M. Weber, "Boosting Multi-Core
+ * Reachability Performance with Shared Hash Tables".
+ *
+ * Conventions for every call below
+ *   - Return value: lhs_status; LHS_OK (0) on success.  Argument errors are
+ *     detected on the host before any device work is queued (LHS_EINVAL) and
+ *     leave the table untouched.
+ *   - "device" pointers are HIP device allocations (e.g. a torch tensor's
+ *     data_ptr() on the current device); "host" pointers are ordinary host
+ *     memory.  The caller keeps ownership of every buffer it passes in; the
+ *     library owns what it allocates and frees it in the matching destroy/free
+ *     call.
+ *   - hip_stream is a hipStream_t (NULL = the null stream).  Calls that take
+ *     a stream are asynchronous on it unless documented otherwise.
+ *   - Device-side failures (table full, a spin that exceeded its bound) are
+ *     sticky in the table and are reported by lhs_check().
+ */
+#ifndef LHS_H
+#define LHS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lhs_status {
+    LHS_OK = 0,
+    LHS_EINVAL = 1,   /* bad argument (checked on the host)                    */
+    LHS_ENOMEM = 2,   /* device or host allocation failed                      */
+    LHS_EFULL = 3,    /* a find-or-put probed every line without a free slot   */
+    LHS_ESTALL = 4,   /* a wait on a slot being written exceeded its bound     */
+    LHS_EDEVICE = 5,  /* a HIP runtime call failed                             */
+    LHS_EBUDGET = 6,  /* a request does not fit the server's memory budget     */
+    LHS_ENOTFOUND = 7,/* unknown ticket                                        */
+    LHS_EAGAIN = 8    /* result not ready yet (non-blocking poll)              */
+} lhs_status;
+
+/* Human-readable name of a status code (static storage). */
+const char *lhs_strerror(lhs_status s);
+
+/* ------------------------------------------------------------------------
+ * Table: one shared, lockless, open-addressing set of fixed-width vectors.
+ *
+ * Design (section "Hash Table Design"): open addressing; probing walks the
+ * 128-byte line (16 eight-byte slots) that holds the home slot, starting at
+ * the home slot and wrapping inside the line ("walking the line",
+ * Algorithm 4), then moves to another line by double hashing; vectors live in
+ * a separate data array indexed by slot; each slot memoises the vector's hash
+ * and carries write/done status; 2^n slots so the index is the low hash
+ * bits; empty = 0; slots are claimed with a 64-bit compare-and-swap
+ * (Algorithm 2).  The table never resizes and allocates nothing after
+ * lhs_create (requirements listed in "Requirements on the State Storage").
+ * ---------------------------------------------------------------------- */
+typedef struct lhs_table lhs_table;
+
+/* Create a table on the current HIP device.
+ *   capacity    : number of slots, a power of two in [16, 2^32].
+ *   state_words : vector width W in 32-bit words, in [1, 32].
+ * Allocates capacity*8 bytes of slots (zeroed) plus capacity*W*4 bytes of
+ * vector data, once.  *out receives the handle (owned by the caller, freed by
+ * lhs_destroy).  Errors: LHS_EINVAL, LHS_ENOMEM, LHS_EDEVICE. */
+lhs_status lhs_create(uint64_t capacity, uint32_t state_words, lhs_table **out);
+
+/* Free the table and everything it allocated.  NULL is accepted. The caller
+ * must not have work on the table in flight. */
+lhs_status lhs_destroy(lhs_table *t);
+
+/* Empty the table (all slots to 0) and clear its sticky error and counters,
+ * asynchronously on hip_stream. */
+lhs_status lhs_clear(lhs_table *t, void *hip_stream);
+
+/* Batched find-or-put (Algorithm 3, "find-or-put").
+ *   d_states : device, n rows of state_words uint32 each, row-major, read only.
+ *   n        : number of rows (0 is a no-op); at most 2^32 - 1.
+ *   d_seen   : device, n bytes out.  1 = the vector was already stored
+ *              ("seen", the paper's output), 0 = this call inserted it,
+ *              0xFF = the operation failed (see lhs_check).
+ *   d_index  : device, n uint32 out (may be NULL): the slot holding the
+ *              vector.  Equal vectors always get equal indices; the index
+ *              also addresses the vector's row in the data array.
+ * Within one call the order of operations is unspecified: when a batch holds
+ * a vector several times and it was not stored before, exactly one of those
+ * rows reports 0.  Calls on one table may run concurrently on several
+ * streams (the table is lockless).  Asynchronous on hip_stream. */
+lhs_status lhs_find_or_put(lhs_table *t, const uint32_t *d_states, uint64_t n,
+                           uint8_t *d_seen, uint32_t *d_index, void *hip_stream);
+
+/* Wait for the last stream used with the table, then return its sticky
+ * device error (LHS_EFULL / LHS_ESTALL) or LHS_OK. */
+lhs_status lhs_check(lhs_table *t);
+
+/* Number of stored (completely written) vectors.  Synchronous. */
+lhs_status lhs_count(lhs_table *t, uint64_t *out);
+
+/* Copy every stored vector to host memory, in ascending slot order.
+ *   h_states : host, room for max_rows * state_words uint32 (may be NULL
+ *              to only count).
+ *   h_index  : host, room for max_rows uint32 (may be NULL): slot of each row.
+ *   *n_rows  : number of stored vectors (also when it exceeds max_rows, in
+ *              which case nothing is copied and LHS_EINVAL is returned).
+ * Synchronous; uses temporary device memory.  For checks, not the hot path. */
+lhs_status lhs_dump(lhs_table *t, uint32_t *h_states, uint32_t *h_index,
+                    uint64_t max_rows, uint64_t *n_rows);
+
+/* Copy the raw slot words (capacity uint64) to host memory.  Slot encoding:
+ * 0 = empty; bit 63 = claimed; bit 62 = vector written ("done"); bits 61..0
+ * = the low 62 bits of the vector's 64-bit hash.  Synchronous. */
+lhs_status lhs_dump_slots(lhs_table *t, uint64_t *h_slots);
+
+typedef struct lhs_info {
+    uint64_t capacity;     /* slots                                          */
+    uint32_t state_words;  /* W                                              */
+    uint32_t line_slots;   /* slots per probed line (16)                     */
+    uint64_t hash_seed;    /* seed of the 64-bit vector hash                 */
+    uint64_t wait_hits;    /* waits on a slot still being written (the
+                              paper's write-busy "lock" hits)                */
+    uint64_t cas_failures; /* lost claims of an empty slot                   */
+    uint32_t error;        /* sticky lhs_status of device failures           */
+    uint32_t reserved;
+} lhs_info;
+
+/* Table geometry and device counters (synchronises the last stream). */
+lhs_status lhs_get_info(lhs_table *t, lhs_info *out);
+
+/* ------------------------------------------------------------------------
+ * Reachability (Algorithm 1, "Reachability analysis") as level-synchronous
+ * BFS on the GPU: every level expands the whole frontier with the model's
+ * next-state function, inserts every successor with find-or-put and queues
+ * the ones that were new; levels are exact BFS distances.
+ * ---------------------------------------------------------------------- */
+
+#define REACH_NONE 0xFFFFFFFFu
+
+/* One guarded transition of a process (asynchronous interleaving): from the
+ * process's current local state it fires when guard_var == REACH_NONE or
+ * shared[guard_var] == guard_val (read on the source state); it sets the
+ * process's local state to target and, when eff_var != REACH_NONE,
+ * shared[eff_var] = eff_val. */
+typedef struct reach_trans {
+    uint32_t target;
+    uint32_t guard_var;
+    uint32_t guard_val;
+    uint32_t eff_var;
+    uint32_t eff_val;
+} reach_trans;
+
+/* A model in host memory.  State vector: n_procs local states followed by
+ * n_shared shared values, W = n_procs + n_shared words (1..32).
+ *   trans      : [n_procs][n_locals][trans_per_local] transitions.
+ *   init       : W words, the initial state s0.
+ *   state_cap  : 0 = explore to exhaustion; otherwise keep the longest prefix
+ *                of BFS levels whose cumulative state count is <= state_cap
+ *                (the first level that would exceed it is discarded and the
+ *                result is flagged capped).
+ * Limits: n_locals <= 65535, targets < n_locals, n_shared <= 254,
+ * guard/effect values <= 65535, trans_per_local <= 16. */
+typedef struct reach_model {
+    uint32_t n_procs;
+    uint32_t n_locals;
+    uint32_t n_shared;
+    uint32_t trans_per_local;
+    const reach_trans *trans;
+    const uint32_t *init;
+    uint64_t state_cap;
+} reach_model;
+
+typedef struct reach_opts {
+    uint64_t capacity;    /* table slots (power of two); 0 = automatic        */
+    uint32_t max_levels;  /* bound on the number of levels; 0 = 1<<20          */
+    uint32_t flags;       /* REACH_F_* below                                   */
+    lhs_table *table;     /* optional caller-created table (W must match); it
+                             is cleared first and keeps the result set, so it
+                             can be dumped afterwards.  NULL = internal table. */
+    void *hip_stream;     /* stream for all device work                        */
+} reach_opts;
+
+#define REACH_F_NONE 0u
+#define REACH_F_HOST_LOOP 1u   /* one launch per level, host reads counters    */
+
+typedef struct reach_result {
+    uint64_t total_states;  /* |kept levels|                                   */
+    uint64_t edges;         /* successors generated by the expanded levels     */
+    uint64_t deadlocks;     /* expanded states without successors              */
+    uint64_t wait_hits;     /* waits on slots being written (informational)    */
+    uint64_t *level_counts; /* n_levels entries, library-allocated             */
+    uint32_t n_levels;
+    int32_t capped;         /* 1 if state_cap cut a level off                  */
+    double gpu_ms;          /* device time of the exploration                  */
+} reach_result;
+
+/* Explore m.  r is filled on LHS_OK; free it with reach_result_free.
+ * Synchronous (returns when the exploration is complete). */
+lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result *r);
+
+/* Free what reach_explore / reach_explore_batch allocated in r. */
+void reach_result_free(reach_result *r);
+
+/* ------------------------------------------------------------------------
+ * Measurement probes (ceilings for the roofline of find-or-put).
+ * All asynchronous on hip_stream; d_sink is a device uint64 the kernels may
+ * write to keep their loads alive.
+ * ---------------------------------------------------------------------- */
+
+/* n_reads reads of uniformly random 128-byte-aligned lines of d_buf
+ * (buf_bytes / 128 must be a power of two, d_buf 128-byte aligned), each line
+ * read by one lane (lanes_per_line = 1, 8 x 16-byte loads) or by eight lanes
+ * (lanes_per_line = 8, one 16-byte load each). */
+lhs_status lhs_probe_random_lines(const void *d_buf, uint64_t buf_bytes, uint32_t lanes_per_line,
+                                  uint64_t n_reads, uint64_t seed, uint64_t *d_sink,
+                                  void *hip_stream);
+
+/* n_ops 64-bit compare-and-swap operations (0 -> random value with bit 63
+ * set) at uniformly random slots of d_slots (n_slots a power of two). */
+lhs_status lhs_probe_random_cas(uint64_t *d_slots, uint64_t n_slots, uint64_t n_ops,
+                                uint64_t seed, uint64_t *d_sink, void *hip_stream);
+
+/* Streaming copy of `bytes` (multiple of 16, 16-byte aligned pointers): the
+ * reference kernel for calibrating hardware traffic counters. */
+lhs_status lhs_probe_copy(void *d_dst, const void *d_src, uint64_t bytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LHS_H */

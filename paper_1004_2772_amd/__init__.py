@@ -1,0 +1,261 @@
+"""Python binding of the lhs C-ABI library (liblhs.so, HIP for gfx950).
+
+Argument marshalling only: every step of find-or-put and of the BFS runs in
+the library's kernels.  torch supplies device memory and streams; buffers are
+passed as ``tensor.data_ptr()`` and streams as their ``hipStream_t`` handle.
+The names follow the C header ``include/lhs.h``.
+
+The library must be built (``python -m paper_1004_2772_amd.build``); importing
+a missing library raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblhs.so")
+
+STATUS = {0: "LHS_OK", 1: "LHS_EINVAL", 2: "LHS_ENOMEM", 3: "LHS_EFULL", 4: "LHS_ESTALL",
+          5: "LHS_EDEVICE", 6: "LHS_EBUDGET", 7: "LHS_ENOTFOUND", 8: "LHS_EAGAIN"}
+REACH_NONE = 0xFFFFFFFF
+REACH_F_HOST_LOOP = 1
+
+#: every symbol include/lhs.h declares
+EXPORTS = ["lhs_strerror", "lhs_create", "lhs_destroy", "lhs_clear", "lhs_find_or_put",
+           "lhs_check", "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info",
+           "reach_explore", "reach_result_free",
+           "lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_copy"]
+
+
+class LhsError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        self.status = status
+        self.name = STATUS.get(status, f"status {status}")
+        super().__init__(f"{where}: {self.name}" if where else self.name)
+
+
+class LhsInfo(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_uint64), ("state_words", ctypes.c_uint32),
+                ("line_slots", ctypes.c_uint32), ("hash_seed", ctypes.c_uint64),
+                ("wait_hits", ctypes.c_uint64), ("cas_failures", ctypes.c_uint64),
+                ("error", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class ReachModel(ctypes.Structure):
+    _fields_ = [("n_procs", ctypes.c_uint32), ("n_locals", ctypes.c_uint32),
+                ("n_shared", ctypes.c_uint32), ("trans_per_local", ctypes.c_uint32),
+                ("trans", ctypes.c_void_p), ("init", ctypes.c_void_p),
+                ("state_cap", ctypes.c_uint64)]
+
+
+class ReachOpts(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_uint64), ("max_levels", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("table", ctypes.c_void_p),
+                ("hip_stream", ctypes.c_void_p)]
+
+
+class ReachResultC(ctypes.Structure):
+    _fields_ = [("total_states", ctypes.c_uint64), ("edges", ctypes.c_uint64),
+                ("deadlocks", ctypes.c_uint64), ("wait_hits", ctypes.c_uint64),
+                ("level_counts", ctypes.POINTER(ctypes.c_uint64)), ("n_levels", ctypes.c_uint32),
+                ("capped", ctypes.c_int32), ("gpu_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load liblhs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1004_2772_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        u64, u32, p, st = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
+        L.lhs_strerror.argtypes = [st]
+        L.lhs_strerror.restype = ctypes.c_char_p
+        L.lhs_create.argtypes = [u64, u32, ctypes.POINTER(p)]
+        L.lhs_destroy.argtypes = [p]
+        L.lhs_clear.argtypes = [p, p]
+        L.lhs_find_or_put.argtypes = [p, p, u64, p, p, p]
+        L.lhs_check.argtypes = [p]
+        L.lhs_count.argtypes = [p, ctypes.POINTER(u64)]
+        L.lhs_dump.argtypes = [p, p, p, u64, ctypes.POINTER(u64)]
+        L.lhs_dump_slots.argtypes = [p, p]
+        L.lhs_get_info.argtypes = [p, ctypes.POINTER(LhsInfo)]
+        L.reach_explore.argtypes = [ctypes.POINTER(ReachModel), ctypes.POINTER(ReachOpts),
+                                    ctypes.POINTER(ReachResultC)]
+        L.reach_result_free.argtypes = [ctypes.POINTER(ReachResultC)]
+        L.reach_result_free.restype = None
+        L.lhs_probe_random_lines.argtypes = [p, u64, u32, u64, u64, p, p]
+        L.lhs_probe_random_cas.argtypes = [p, u64, u64, u64, p, p]
+        L.lhs_probe_copy.argtypes = [p, p, u64, p]
+        for name in ("lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_copy",
+                     "lhs_create", "lhs_destroy", "lhs_clear", "lhs_find_or_put", "lhs_check",
+                     "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info", "reach_explore"):
+            getattr(L, name).restype = st
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise LhsError(rc, where)
+
+
+def _stream_handle(stream) -> int | None:
+    """hipStream_t of a torch stream (None -> torch's current stream)."""
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _ptr(x) -> int | None:
+    """Device/host address of a torch tensor or numpy array (None passes through)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        assert x.flags["C_CONTIGUOUS"]
+        return x.ctypes.data
+    assert x.is_contiguous()
+    return x.data_ptr()
+
+
+class Table:
+    """A lockless find-or-put table on the current HIP device."""
+
+    def __init__(self, capacity: int, state_words: int):
+        h = ctypes.c_void_p()
+        _check(lib().lhs_create(capacity, state_words, ctypes.byref(h)), "lhs_create")
+        self.handle = h
+        self.capacity = capacity
+        self.W = state_words
+
+    def close(self):
+        if self.handle:
+            lib().lhs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def clear(self, stream=None):
+        _check(lib().lhs_clear(self.handle, _stream_handle(stream)), "lhs_clear")
+
+    def find_or_put(self, states, seen, index=None, stream=None):
+        """states: device tensor [n, W] (32-bit); seen: device uint8 [n];
+        index: device 32-bit [n] or None.  Asynchronous on ``stream``."""
+        n = states.shape[0] if states.dim() == 2 else 0
+        if states.dim() != 2 or states.shape[1] != self.W or states.element_size() != 4:
+            raise ValueError("states must be a [n, W] tensor of 32-bit words")
+        if seen.numel() < n or seen.element_size() != 1:
+            raise ValueError("seen must hold n bytes")
+        if index is not None and (index.numel() < n or index.element_size() != 4):
+            raise ValueError("index must hold n 32-bit words")
+        _check(lib().lhs_find_or_put(self.handle, _ptr(states), n, _ptr(seen), _ptr(index),
+                                     _stream_handle(stream)), "lhs_find_or_put")
+
+    def check(self):
+        _check(lib().lhs_check(self.handle), "lhs_check")
+
+    def count(self) -> int:
+        c = ctypes.c_uint64()
+        _check(lib().lhs_count(self.handle, ctypes.byref(c)), "lhs_count")
+        return c.value
+
+    def dump(self):
+        """(rows u32 [n, W], slots u32 [n]) of every stored vector, by slot."""
+        n = ctypes.c_uint64()
+        _check(lib().lhs_dump(self.handle, None, None, 0, ctypes.byref(n)), "lhs_dump")
+        rows = np.empty((n.value, self.W), dtype=np.uint32)
+        idx = np.empty(n.value, dtype=np.uint32)
+        if n.value:
+            _check(lib().lhs_dump(self.handle, _ptr(rows), _ptr(idx), n.value, ctypes.byref(n)),
+                   "lhs_dump")
+        return rows, idx
+
+    def dump_slots(self) -> np.ndarray:
+        out = np.empty(self.capacity, dtype=np.uint64)
+        _check(lib().lhs_dump_slots(self.handle, _ptr(out)), "lhs_dump_slots")
+        return out
+
+    def info(self) -> dict:
+        i = LhsInfo()
+        _check(lib().lhs_get_info(self.handle, ctypes.byref(i)), "lhs_get_info")
+        return {f: getattr(i, f) for f, _ in LhsInfo._fields_}
+
+
+@dataclasses.dataclass
+class ReachResult:
+    total: int
+    n_levels: int
+    level_counts: list
+    edges: int
+    deadlocks: int
+    capped: bool
+    wait_hits: int
+    gpu_ms: float
+
+
+def _model_struct(model, cap):
+    """ReachModel over model.trans [P, L, K, 5] and model.init (kept alive by caller)."""
+    trans = np.ascontiguousarray(model.trans, dtype=np.uint32)
+    if trans.shape != (model.P, model.L, model.K, 5):
+        raise ValueError("trans must be [P, L, K, 5]")
+    init = np.ascontiguousarray(model.init, dtype=np.uint32)
+    if init.shape != (model.P + model.S,):
+        raise ValueError("init must have P + S words")
+    m = ReachModel(model.P, model.L, model.S, model.K, trans.ctypes.data, init.ctypes.data,
+                   model.cap if cap is None else cap)
+    return m, (trans, init)
+
+
+def reach_explore(model, cap: int | None = None, capacity: int = 0, table: Table | None = None,
+                  stream=None, max_levels: int = 0, flags: int = 0) -> ReachResult:
+    """Level-synchronous BFS of ``model`` on the GPU (synchronous).
+
+    model: object with P, L, S, K, trans [P, L, K, 5] (uint32, 0xFFFFFFFF = none),
+    init [P + S]; cap overrides model.cap (0 = none)."""
+    m, keep = _model_struct(model, cap)
+    o = ReachOpts(capacity, max_levels, flags, table.handle if table else None,
+                  _stream_handle(stream))
+    r = ReachResultC()
+    _check(lib().reach_explore(ctypes.byref(m), ctypes.byref(o), ctypes.byref(r)), "reach_explore")
+    try:
+        levels = [int(r.level_counts[i]) for i in range(r.n_levels)]
+        return ReachResult(total=r.total_states, n_levels=r.n_levels, level_counts=levels,
+                           edges=r.edges, deadlocks=r.deadlocks, capped=bool(r.capped),
+                           wait_hits=r.wait_hits, gpu_ms=r.gpu_ms)
+    finally:
+        lib().reach_result_free(ctypes.byref(r))
+        del keep
+
+
+def probe_random_lines(buf, lanes_per_line: int, n_reads: int, seed: int, sink, stream=None):
+    _check(lib().lhs_probe_random_lines(_ptr(buf), buf.numel() * buf.element_size(), lanes_per_line,
+                                        n_reads, seed, _ptr(sink), _stream_handle(stream)),
+           "lhs_probe_random_lines")
+
+
+def probe_random_cas(slots, n_ops: int, seed: int, sink, stream=None):
+    _check(lib().lhs_probe_random_cas(_ptr(slots), slots.numel(), n_ops, seed, _ptr(sink),
+                                      _stream_handle(stream)), "lhs_probe_random_cas")
+
+
+def probe_copy(dst, src, stream=None):
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() >= nbytes
+    _check(lib().lhs_probe_copy(_ptr(dst), _ptr(src), nbytes, _stream_handle(stream)), "lhs_probe_copy")

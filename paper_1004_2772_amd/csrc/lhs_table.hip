@@ -1,0 +1,382 @@
+// The lockless table: lifecycle, batched find-or-put and inspection.
+//
+// Memory layout in HBM (section "Hash Table Design": separated data, 2^n
+// table, memoised hash, empty = 0):
+//   bucket : uint64[capacity]            8 B/slot, 16 slots per 128-B line
+//   data   : uint32[capacity][W]         row of slot i at data + i*W
+//   status : DevStatus                   sticky error + counters
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+using namespace lhs;
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr uint64_t kDefaultSeed = 0x5851F42D4C957F2Dull;
+constexpr uint32_t kMaxGrid = 1u << 19;
+// A find-or-put gives up with EFULL after probing this many lines (or every
+// line of a smaller table).
+constexpr uint32_t kMaxRounds = 1u << 16;
+
+// A vector staged in LDS (row of W words).
+struct LdsRow {
+    const uint32_t *r;
+    __device__ __forceinline__ uint32_t get(uint32_t i) const { return r[i]; }
+};
+
+// Batched find-or-put: one operation per lane.  A workgroup stages a tile of
+// 256 consecutive input rows into LDS with coalesced loads (rows padded to an
+// odd stride so that lanes reading different rows hit different banks),
+// then every lane hashes its row and runs find_or_put.
+__global__ __launch_bounds__(kBlock) void k_find_or_put(TableView t, const uint32_t *__restrict__ in,
+                                                        uint64_t n, uint8_t *__restrict__ seen,
+                                                        uint32_t *__restrict__ index,
+                                                        uint32_t magicW) {
+    extern __shared__ uint32_t tile[];
+    const uint32_t W = t.W, stride = W | 1u;
+    LaneCounters cnt;
+    for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < n;
+         base += (uint64_t)gridDim.x * kBlock) {
+        const uint32_t rows = (uint32_t)min<uint64_t>(kBlock, n - base);
+        const uint32_t words = rows * W;
+        const uint32_t *src = in + base * W;
+        __syncthreads();
+        for (uint32_t f = threadIdx.x; f < words; f += kBlock) {
+            const uint32_t r = W == 1 ? f : __umulhi(f, magicW);
+            tile[r * stride + (f - r * W)] = src[f];
+        }
+        __syncthreads();
+        if (threadIdx.x < rows) {
+            const LdsRow v{tile + threadIdx.x * stride};
+            const uint64_t h = hash_vec(v, W, t.seed);
+            uint32_t slot, code;
+            find_or_put(t, v, h, slot, code, cnt);
+            seen[base + threadIdx.x] = code == kSeen ? 1 : (code == kNew ? 0 : 0xFF);
+            if (index)
+                index[base + threadIdx.x] = slot;
+        }
+    }
+    flush_counters(t.status, cnt);
+}
+
+__global__ void k_zero_u64(uint64_t *p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+__global__ void k_zero_status(DevStatus *st) {
+    st->error = 0;
+    st->wait_hits = 0;
+    st->cas_failures = 0;
+}
+
+// Per-block count of done slots.  Block b covers lines [b*256, b*256+256),
+// thread i one line.
+__global__ __launch_bounds__(kBlock) void k_count_done(const uint64_t *bucket, uint64_t lines,
+                                                       uint32_t *block_counts) {
+    __shared__ uint32_t part[kBlock / 64];
+    const uint64_t line = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    uint32_t c = 0;
+    if (line < lines) {
+        const uint4 *lp = reinterpret_cast<const uint4 *>(bucket + line * kLineSlots);
+        for (uint32_t q = 0; q < kLineSlots / 2; ++q) {
+            const uint4 x = lp[q];
+            c += (x.y >> 30) == 3u;   // OCC and DONE
+            c += (x.w >> 30) == 3u;
+        }
+    }
+    c = wave_sum(c);
+    if (__lane_id() == 0)
+        part[threadIdx.x / 64] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int w = 0; w < kBlock / 64; ++w)
+            s += part[w];
+        block_counts[blockIdx.x] = s;
+    }
+}
+
+// Ordered gather of done slots: block b writes its rows starting at
+// offsets[b], in ascending slot order.
+__global__ __launch_bounds__(kBlock) void k_gather_done(const uint64_t *bucket, const uint32_t *data,
+                                                        uint32_t W, uint64_t lines,
+                                                        const uint64_t *offsets,
+                                                        uint32_t *out_rows, uint32_t *out_idx) {
+    __shared__ uint32_t scan[kBlock];
+    const uint64_t line = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    uint32_t mask = 0;
+    if (line < lines) {
+        const uint4 *lp = reinterpret_cast<const uint4 *>(bucket + line * kLineSlots);
+        for (uint32_t q = 0; q < kLineSlots / 2; ++q) {
+            const uint4 x = lp[q];
+            mask |= (uint32_t)((x.y >> 30) == 3u) << (2 * q);
+            mask |= (uint32_t)((x.w >> 30) == 3u) << (2 * q + 1);
+        }
+    }
+    // inclusive scan of per-thread counts (Hillis-Steele; small)
+    scan[threadIdx.x] = __popc(mask);
+    __syncthreads();
+    for (uint32_t d = 1; d < kBlock; d <<= 1) {
+        const uint32_t v = threadIdx.x >= d ? scan[threadIdx.x - d] : 0;
+        __syncthreads();
+        scan[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint64_t pos = offsets[blockIdx.x] + scan[threadIdx.x] - __popc(mask);
+    while (mask) {
+        const uint32_t k = __builtin_ctz(mask);
+        mask &= mask - 1;
+        const uint64_t slot = line * kLineSlots + k;
+        if (out_idx)
+            out_idx[pos] = (uint32_t)slot;
+        if (out_rows)
+            for (uint32_t i = 0; i < W; ++i)
+                out_rows[pos * W + i] = data[slot * W + i];
+        ++pos;
+    }
+}
+
+uint32_t grid_for(uint64_t items, uint32_t per_block) {
+    const uint64_t b = (items + per_block - 1) / per_block;
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(b, kMaxGrid));
+}
+
+// Per-block done counts and their exclusive prefix (host).  Returns total.
+lhs_status done_offsets(lhs_table *t, std::vector<uint64_t> &offsets, uint32_t **d_counts_out,
+                        uint64_t *total) {
+    const uint64_t lines = t->capacity / kLineSlots;
+    const uint32_t blocks = (uint32_t)((lines + kBlock - 1) / kBlock);
+    uint32_t *d_counts = nullptr;
+    LHS_HIP(hipMalloc(&d_counts, blocks * sizeof(uint32_t)));
+    hipLaunchKernelGGL(k_count_done, dim3(blocks), dim3(kBlock), 0, t->last_stream, t->bucket, lines,
+                       d_counts);
+    std::vector<uint32_t> counts(blocks);
+    if (hipMemcpyAsync(counts.data(), d_counts, blocks * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                       t->last_stream) != hipSuccess ||
+        hipStreamSynchronize(t->last_stream) != hipSuccess) {
+        (void)hipFree(d_counts);
+        return LHS_EDEVICE;
+    }
+    offsets.resize(blocks);
+    uint64_t acc = 0;
+    for (uint32_t b = 0; b < blocks; ++b) {
+        offsets[b] = acc;
+        acc += counts[b];
+    }
+    *total = acc;
+    if (d_counts_out)
+        *d_counts_out = d_counts;
+    else
+        (void)hipFree(d_counts);
+    return LHS_OK;
+}
+
+}  // namespace
+
+namespace lhs {
+
+lhs_status launch_find_or_put(lhs_table *t, const uint32_t *d_states, uint64_t n, uint8_t *d_seen,
+                              uint32_t *d_index, hipStream_t s) {
+    if (!n)
+        return LHS_OK;
+    const size_t lds = (size_t)kBlock * (t->W | 1u) * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_find_or_put, dim3(grid_for(n, kBlock)), dim3(kBlock), lds, s, view(t),
+                       d_states, n, d_seen, d_index, div_magic(t->W));
+    return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
+}
+
+lhs_status launch_zero_u64(uint64_t *p, uint64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(n, kBlock * 8)), dim3(kBlock), 0, s, p, n);
+    return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
+}
+
+lhs_status read_status(lhs_table *t, DevStatus *out) {
+    LHS_HIP(hipStreamSynchronize(t->last_stream));
+    LHS_HIP(hipMemcpy(out, t->status, sizeof(DevStatus), hipMemcpyDeviceToHost));
+    return LHS_OK;
+}
+
+}  // namespace lhs
+
+extern "C" {
+
+const char *lhs_strerror(lhs_status s) {
+    switch (s) {
+    case LHS_OK: return "LHS_OK";
+    case LHS_EINVAL: return "LHS_EINVAL: invalid argument";
+    case LHS_ENOMEM: return "LHS_ENOMEM: out of memory";
+    case LHS_EFULL: return "LHS_EFULL: table full (every line probed)";
+    case LHS_ESTALL: return "LHS_ESTALL: wait on a slot being written exceeded its bound";
+    case LHS_EDEVICE: return "LHS_EDEVICE: HIP runtime error";
+    case LHS_EBUDGET: return "LHS_EBUDGET: request exceeds the memory budget";
+    case LHS_ENOTFOUND: return "LHS_ENOTFOUND: unknown ticket";
+    case LHS_EAGAIN: return "LHS_EAGAIN: not ready";
+    }
+    return "LHS_?: unknown status";
+}
+
+lhs_status lhs_create(uint64_t capacity, uint32_t state_words, lhs_table **out) {
+    if (!out || !is_pow2(capacity) || capacity < kLineSlots || capacity > (1ull << 32) ||
+        state_words < 1 || state_words > 32)
+        return LHS_EINVAL;
+    *out = nullptr;
+    lhs_table *t = new (std::nothrow) lhs_table();
+    if (!t)
+        return LHS_ENOMEM;
+    t->capacity = capacity;
+    t->W = state_words;
+    t->lines = (uint32_t)(capacity / kLineSlots);
+    t->max_rounds = std::min<uint32_t>(t->lines, kMaxRounds);
+    t->seed = kDefaultSeed;
+    if (hipGetDevice(&t->device) != hipSuccess) {
+        delete t;
+        return LHS_EDEVICE;
+    }
+    if (hipMalloc(&t->bucket, capacity * sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc(&t->data, capacity * (uint64_t)state_words * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&t->status, sizeof(DevStatus)) != hipSuccess) {
+        (void)hipGetLastError();
+        lhs_destroy(t);
+        return LHS_ENOMEM;
+    }
+    if (lhs_clear(t, nullptr) != LHS_OK || hipStreamSynchronize(nullptr) != hipSuccess) {
+        lhs_destroy(t);
+        return LHS_EDEVICE;
+    }
+    *out = t;
+    return LHS_OK;
+}
+
+lhs_status lhs_destroy(lhs_table *t) {
+    if (!t)
+        return LHS_OK;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(t->bucket);
+    (void)hipFree(t->data);
+    (void)hipFree(t->status);
+    (void)hipFree(t->frontier[0]);
+    (void)hipFree(t->frontier[1]);
+    (void)hipFree(t->level);
+    if (t->level_host)
+        (void)hipHostFree(t->level_host);
+    delete t;
+    return LHS_OK;
+}
+
+lhs_status lhs_clear(lhs_table *t, void *hip_stream) {
+    if (!t)
+        return LHS_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    t->last_stream = s;
+    if (launch_zero_u64(t->bucket, t->capacity, s) != LHS_OK)
+        return LHS_EDEVICE;
+    hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(1), 0, s, t->status);
+    return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
+}
+
+lhs_status lhs_find_or_put(lhs_table *t, const uint32_t *d_states, uint64_t n, uint8_t *d_seen,
+                           uint32_t *d_index, void *hip_stream) {
+    if (!t || n >= (1ull << 32) || (n && (!d_states || !d_seen)))
+        return LHS_EINVAL;
+    t->last_stream = (hipStream_t)hip_stream;
+    return launch_find_or_put(t, d_states, n, d_seen, d_index, (hipStream_t)hip_stream);
+}
+
+lhs_status lhs_check(lhs_table *t) {
+    if (!t)
+        return LHS_EINVAL;
+    DevStatus st;
+    lhs_status rc = read_status(t, &st);
+    if (rc != LHS_OK)
+        return rc;
+    return (lhs_status)st.error;
+}
+
+lhs_status lhs_count(lhs_table *t, uint64_t *out) {
+    if (!t || !out)
+        return LHS_EINVAL;
+    std::vector<uint64_t> offsets;
+    return done_offsets(t, offsets, nullptr, out);
+}
+
+lhs_status lhs_dump(lhs_table *t, uint32_t *h_states, uint32_t *h_index, uint64_t max_rows,
+                    uint64_t *n_rows) {
+    if (!t || !n_rows)
+        return LHS_EINVAL;
+    std::vector<uint64_t> offsets;
+    uint64_t total = 0;
+    lhs_status rc = done_offsets(t, offsets, nullptr, &total);
+    if (rc != LHS_OK)
+        return rc;
+    *n_rows = total;
+    if (total > max_rows)
+        return (h_states || h_index) ? LHS_EINVAL : LHS_OK;
+    if (!total || (!h_states && !h_index))
+        return LHS_OK;
+    uint64_t *d_off = nullptr;
+    uint32_t *d_rows = nullptr, *d_idx = nullptr;
+    const uint64_t lines = t->capacity / kLineSlots;
+    const uint32_t blocks = (uint32_t)offsets.size();
+    hipStream_t s = t->last_stream;
+    rc = LHS_EDEVICE;
+    if (hipMalloc(&d_off, blocks * sizeof(uint64_t)) == hipSuccess &&
+        (!h_states || hipMalloc(&d_rows, total * t->W * sizeof(uint32_t)) == hipSuccess) &&
+        (!h_index || hipMalloc(&d_idx, total * sizeof(uint32_t)) == hipSuccess) &&
+        hipMemcpyAsync(d_off, offsets.data(), blocks * sizeof(uint64_t), hipMemcpyHostToDevice, s) ==
+            hipSuccess) {
+        hipLaunchKernelGGL(k_gather_done, dim3(blocks), dim3(kBlock), 0, s, t->bucket, t->data, t->W,
+                           lines, d_off, d_rows, d_idx);
+        bool ok = hipGetLastError() == hipSuccess;
+        if (ok && h_states)
+            ok = hipMemcpyAsync(h_states, d_rows, total * t->W * sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, s) == hipSuccess;
+        if (ok && h_index)
+            ok = hipMemcpyAsync(h_index, d_idx, total * sizeof(uint32_t), hipMemcpyDeviceToHost, s) ==
+                 hipSuccess;
+        if (ok)
+            ok = hipStreamSynchronize(s) == hipSuccess;
+        rc = ok ? LHS_OK : LHS_EDEVICE;
+    } else {
+        (void)hipGetLastError();
+        rc = LHS_ENOMEM;
+    }
+    (void)hipFree(d_off);
+    (void)hipFree(d_rows);
+    (void)hipFree(d_idx);
+    return rc;
+}
+
+lhs_status lhs_dump_slots(lhs_table *t, uint64_t *h_slots) {
+    if (!t || !h_slots)
+        return LHS_EINVAL;
+    LHS_HIP(hipStreamSynchronize(t->last_stream));
+    LHS_HIP(hipMemcpy(h_slots, t->bucket, t->capacity * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    return LHS_OK;
+}
+
+lhs_status lhs_get_info(lhs_table *t, lhs_info *out) {
+    if (!t || !out)
+        return LHS_EINVAL;
+    DevStatus st;
+    lhs_status rc = read_status(t, &st);
+    if (rc != LHS_OK)
+        return rc;
+    std::memset(out, 0, sizeof(*out));
+    out->capacity = t->capacity;
+    out->state_words = t->W;
+    out->line_slots = kLineSlots;
+    out->hash_seed = t->seed;
+    out->wait_hits = st.wait_hits;
+    out->cas_failures = st.cas_failures;
+    out->error = st.error;
+    return LHS_OK;
+}
+
+}  // extern "C"

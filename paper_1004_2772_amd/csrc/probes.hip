@@ -1,0 +1,120 @@
+// Roofline probes: the memory-system ceilings the find-or-put kernel is
+// measured against.
+//   random lines : uniformly random 128-byte-aligned lines of a large buffer,
+//                  read either by one lane (8 x 16 B, the find-or-put access
+//                  pattern) or by 8 cooperating lanes (16 B each).
+//   random CAS   : 64-bit compare-and-swap at uniformly random slots.
+//   copy         : a plain streaming copy, the reference for hardware
+//                  traffic counters.
+// Indices come from the SplitMix64 output function applied to a counter
+// (Steele, Lea, Flood, "Fast splittable pseudorandom number generators", 2014).
+#include "internal.h"
+
+namespace {
+
+__device__ __forceinline__ uint64_t splitmix(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_probe_lines_lane(const uint4 *buf, uint64_t n_lines,
+                                                          uint64_t n_reads, uint64_t seed,
+                                                          uint64_t *sink) {
+    uint32_t acc = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_reads;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t line = splitmix(seed ^ i) & (n_lines - 1);
+        const uint4 *p = buf + line * 8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint4 x = p[q];
+            acc ^= x.x ^ x.y ^ x.z ^ x.w;
+        }
+    }
+    if (acc == 0x9E3779B9u)
+        sink[0] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_probe_lines_coop(const uint4 *buf, uint64_t n_lines,
+                                                          uint64_t n_reads, uint64_t seed,
+                                                          uint64_t *sink) {
+    uint32_t acc = 0;
+    const uint32_t sub = threadIdx.x & 7u;
+    for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3; i < n_reads;
+         i += ((uint64_t)gridDim.x * blockDim.x) >> 3) {
+        const uint64_t line = splitmix(seed ^ i) & (n_lines - 1);
+        const uint4 x = buf[line * 8 + sub];
+        acc ^= x.x ^ x.y ^ x.z ^ x.w;
+    }
+    if (acc == 0x9E3779B9u)
+        sink[0] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_probe_cas(uint64_t *slots, uint64_t n_slots, uint64_t n_ops,
+                                                   uint64_t seed, uint64_t *sink) {
+    uint32_t won = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_ops;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t r = splitmix(seed ^ i);
+        uint64_t expected = 0;
+        won += __hip_atomic_compare_exchange_strong(slots + (r & (n_slots - 1)), &expected,
+                                                    r | (1ull << 63), __ATOMIC_RELAXED,
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (won == 0xFFFFFFFFu)
+        sink[0] = won;
+}
+
+__global__ __launch_bounds__(256) void k_probe_copy(uint4 *dst, const uint4 *src, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+uint32_t probe_grid(uint64_t items) {
+    const uint64_t b = (items + 255) / 256;
+    return (uint32_t)(b < 8192 ? (b ? b : 1) : 8192);
+}
+
+}  // namespace
+
+extern "C" {
+
+lhs_status lhs_probe_random_lines(const void *d_buf, uint64_t buf_bytes, uint32_t lanes_per_line,
+                                  uint64_t n_reads, uint64_t seed, uint64_t *d_sink,
+                                  void *hip_stream) {
+    const uint64_t n_lines = buf_bytes / 128;
+    if (!d_buf || !d_sink || !lhs::is_pow2(n_lines) || (lanes_per_line != 1 && lanes_per_line != 8) ||
+        ((uintptr_t)d_buf & 127))
+        return LHS_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (lanes_per_line == 1)
+        hipLaunchKernelGGL(k_probe_lines_lane, dim3(probe_grid(n_reads)), dim3(256), 0, s,
+                           (const uint4 *)d_buf, n_lines, n_reads, seed, d_sink);
+    else
+        hipLaunchKernelGGL(k_probe_lines_coop, dim3(probe_grid(n_reads * 8)), dim3(256), 0, s,
+                           (const uint4 *)d_buf, n_lines, n_reads, seed, d_sink);
+    return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
+}
+
+lhs_status lhs_probe_random_cas(uint64_t *d_slots, uint64_t n_slots, uint64_t n_ops, uint64_t seed,
+                                uint64_t *d_sink, void *hip_stream) {
+    if (!d_slots || !d_sink || !lhs::is_pow2(n_slots))
+        return LHS_EINVAL;
+    hipLaunchKernelGGL(k_probe_cas, dim3(probe_grid(n_ops)), dim3(256), 0, (hipStream_t)hip_stream,
+                       d_slots, n_slots, n_ops, seed, d_sink);
+    return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
+}
+
+lhs_status lhs_probe_copy(void *d_dst, const void *d_src, uint64_t bytes, void *hip_stream) {
+    if (!d_dst || !d_src || (bytes & 15) || ((uintptr_t)d_dst & 15) || ((uintptr_t)d_src & 15))
+        return LHS_EINVAL;
+    const uint64_t n = bytes / 16;
+    hipLaunchKernelGGL(k_probe_copy, dim3(probe_grid(n)), dim3(256), 0, (hipStream_t)hip_stream,
+                       (uint4 *)d_dst, (const uint4 *)d_src, n);
+    return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
+}
+
+}  // extern "C"

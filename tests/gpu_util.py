@@ -1,0 +1,104 @@
+"""Helpers for the GPU parity tests (host side only)."""
+import numpy as np
+
+MASK64 = (1 << 64) - 1
+OCC = np.uint64(1 << 63)
+DONE = np.uint64(1 << 62)
+MEMO = np.uint64((1 << 62) - 1)
+
+
+def dev_u32(a):
+    """numpy uint32 array -> contiguous int32 CUDA tensor with the same bits."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()
+
+
+def _rotl(x, r):
+    return (x << np.uint64(r)) | (x >> np.uint64(64 - r))
+
+
+def table_hash(rows: np.ndarray, seed: int) -> np.ndarray:
+    """The table's 64-bit vector hash, re-implemented on the host from its
+    definition (MurmurHash3 x64 block mixing over 64-bit word pairs, the
+    length xor, fmix64).  Used only to check slot invariants."""
+    rows = np.ascontiguousarray(rows, dtype=np.uint32)
+    n, W = rows.shape
+    c1, c2 = np.uint64(0x87c37b91114253d5), np.uint64(0x4cf5ad432745937f)
+    with np.errstate(over="ignore"):
+        h = np.full(n, seed, dtype=np.uint64)
+        i = 0
+        while i + 1 < W:
+            k = rows[:, i].astype(np.uint64) | (rows[:, i + 1].astype(np.uint64) << np.uint64(32))
+            k = _rotl(k * c1, 31) * c2
+            h = _rotl(h ^ k, 27) * np.uint64(5) + np.uint64(0x52dce729)
+            i += 2
+        if i < W:
+            k = rows[:, i].astype(np.uint64)
+            h ^= _rotl(k * c1, 31) * c2
+        h ^= np.uint64(W * 4)
+        h ^= h >> np.uint64(33)
+        h *= np.uint64(0xff51afd7ed558ccd)
+        h ^= h >> np.uint64(33)
+        h *= np.uint64(0xc4ceb9fe1a85ec53)
+        h ^= h >> np.uint64(33)
+    return h
+
+
+def check_table_invariants(table):
+    """Invariants of a table between calls (figure of bucket states and the
+    probe sequence): every non-empty slot is done; each slot's memo is its
+    row's hash; every slot in front of a stored row on that row's probe
+    sequence is non-empty (otherwise a later lookup would insert it again);
+    no vector is stored twice."""
+    info = table.info()
+    slots = table.dump_slots()
+    rows, idx = table.dump()
+    nonempty = slots != 0
+    assert np.all((slots[nonempty] & (OCC | DONE)) == (OCC | DONE)), "claimed slot not done"
+    assert int(nonempty.sum()) == len(idx)
+    h = table_hash(rows, info["hash_seed"])
+    assert np.array_equal(slots[idx] & MEMO, h & MEMO), "memo differs from the row hash"
+    assert len(np.unique(rows, axis=0)) == len(rows), "duplicate vector"
+    lines = info["capacity"] // 16
+    line = (h >> np.uint64(4)) & np.uint64(lines - 1)
+    start = h & np.uint64(15)
+    step = (h >> np.uint64(32)) | np.uint64(1)
+    pending = np.ones(len(idx), dtype=bool)
+    target = idx.astype(np.uint64)
+    for _ in range(lines):
+        if not pending.any():
+            break
+        for k in range(16):
+            slot = line * np.uint64(16) + ((start + np.uint64(k)) & np.uint64(15))
+            hit = pending & (slot == target)
+            before = pending & ~hit
+            assert np.all(slots[slot[before].astype(np.int64)] != 0), "empty slot ahead of a stored row"
+            pending &= ~hit
+        with np.errstate(over="ignore"):
+            line = (line + step) & np.uint64(lines - 1)
+    assert not pending.any(), "stored row not on its probe sequence"
+    return rows, idx
+
+
+def check_stream_batches(o_id, n_distinct, seen, index, bounds):
+    """GPU batch results vs the sequential oracle.
+
+    For every distinct value: its first batch (in stream order) must report it
+    new exactly once; every occurrence in later batches must report seen; all
+    occurrences get one index; different values get different indices."""
+    o_id = np.asarray(o_id)
+    n = len(o_id)
+    batch = np.zeros(n, dtype=np.int64)
+    for b, (lo, hi) in enumerate(bounds):
+        batch[lo:hi] = b
+    assert bounds[-1][1] == n
+    assert not np.any(seen == 0xFF), "failed operation"
+    _, first_pos = np.unique(o_id, return_index=True)
+    first_batch = batch[first_pos][o_id]
+    later = batch > first_batch
+    assert np.all(seen[later] == 1), "value from an earlier batch reported new"
+    news = np.bincount(o_id[seen == 0], minlength=n_distinct)
+    assert np.all(news == 1), "a value was not reported new exactly once"
+    idx_of = index[first_pos]
+    assert np.array_equal(index, idx_of[o_id]), "equal vectors got different indices"
+    assert len(np.unique(idx_of)) == n_distinct, "different vectors share an index"

@@ -1,0 +1,89 @@
+"""The C-ABI library loads and exports every declared symbol; host-side
+argument validation fails before any device call (no GPU needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+import paper_1004_2772_amd as lhs
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "lhs.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:lhs_status|void|const char \*)\s*\**(\w+)\s*\(", src, re.M)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(lhs.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", lhs.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (\w+)$", out, re.M))
+    missing = [s for s in _declared() if s not in exported]
+    assert not missing, missing
+    L = lhs.lib()
+    for s in _declared():
+        assert hasattr(L, s)
+
+
+def test_strerror():
+    L = lhs.lib()
+    for code, name in lhs.STATUS.items():
+        assert L.lhs_strerror(code).decode().startswith(name)
+
+
+@pytest.mark.parametrize("cap,W", [(0, 4), (15, 4), (24, 4), (1 << 33, 4), (1 << 16, 0), (1 << 16, 33)])
+def test_create_rejects_bad_geometry(cap, W):
+    h = ctypes.c_void_p()
+    assert lhs.lib().lhs_create(cap, W, ctypes.byref(h)) == 1
+    assert not h.value
+
+
+def test_null_handles_rejected():
+    L = lhs.lib()
+    n = ctypes.c_uint64()
+    assert L.lhs_find_or_put(None, None, 0, None, None, None) == 1
+    assert L.lhs_check(None) == 1
+    assert L.lhs_count(None, ctypes.byref(n)) == 1
+    assert L.lhs_dump(None, None, None, 0, ctypes.byref(n)) == 1
+    assert L.lhs_clear(None, None) == 1
+    assert L.lhs_destroy(None) == 0
+
+
+def _bad_models():
+    import gen
+    good = gen.guarded_model(1, 3, 4, 2, 3, 2)
+    yield "no procs", dict(P=0)
+    yield "too wide", dict(P=20, S=13)
+    yield "K too large", dict(K=17)
+    t = good.trans.copy()
+    t[0, 0, 0, 0] = 4          # target >= L
+    yield "target out of range", dict(trans=t)
+    t = good.trans.copy()
+    t[0, 0, 0, 1] = 2          # guard var >= S
+    yield "guard var out of range", dict(trans=t)
+    t = good.trans.copy()
+    t[0, 0, 0, 3] = 5          # effect var >= S
+    yield "effect var out of range", dict(trans=t)
+    t = good.trans.copy()
+    t[0, 0, 0, 4] = 1 << 16    # effect value too large
+    yield "effect value too large", dict(trans=t)
+
+
+@pytest.mark.parametrize("name,patch", list(_bad_models()), ids=[n for n, _ in _bad_models()])
+def test_reach_rejects_bad_models(name, patch):
+    import gen
+    g = gen.guarded_model(1, 3, 4, 2, 3, 2)
+    P, L, S, K = patch.get("P", 3), 4, patch.get("S", 2), patch.get("K", 2)
+    trans = np.ascontiguousarray(patch.get("trans", g.trans), dtype=np.uint32)
+    init = np.zeros(max(P + S, 1), dtype=np.uint32)
+    m = lhs.ReachModel(P, L, S, K, trans.ctypes.data, init.ctypes.data, 0)
+    r = lhs.ReachResultC()
+    assert lhs.lib().reach_explore(ctypes.byref(m), None, ctypes.byref(r)) == 1

@@ -1,0 +1,115 @@
+"""Batched find-or-put on the GPU vs the sequential CPU oracle (bit-exact)."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+from gpu_util import check_stream_batches, check_table_invariants, dev_u32
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lhs():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1004_2772_amd
+    return paper_1004_2772_amd
+
+
+def _run_stream(lhs, table, stream, batch):
+    import torch
+    n = len(stream)
+    dev = dev_u32(stream)
+    seen = torch.empty(n, dtype=torch.uint8, device="cuda")
+    idx = torch.empty(n, dtype=torch.int32, device="cuda")
+    bounds = []
+    for lo in range(0, n, batch):
+        hi = min(n, lo + batch)
+        table.find_or_put(dev[lo:hi], seen[lo:hi], idx[lo:hi])
+        bounds.append((lo, hi))
+    table.check()
+    return seen.cpu().numpy(), idx.cpu().numpy().view(np.uint32), bounds
+
+
+@pytest.mark.parametrize("W", [1, 2, 3, 4, 5, 8, 16, 17, 31, 32])
+@pytest.mark.parametrize("batch", [257, 1000, 1 << 30])
+def test_stream_parity(lhs, W, batch):
+    print(f"\n[fop] W={W} batch={batch}", flush=True)
+    rows, order = gen.dup_stream(100 + W, 3000, W, 3)
+    stream = gen.gather(rows, order)
+    o_seen, o_id, distinct = oracle.stream(stream)
+    with lhs.Table(1 << 14, W) as t:
+        seen, idx, bounds = _run_stream(lhs, t, stream, batch)
+        check_stream_batches(o_id, distinct, seen, idx, bounds)
+        assert t.count() == distinct
+        got, _ = check_table_invariants(t)
+    assert oracle.digest(got) == oracle.digest(rows[np.unique(o_id)]) or \
+        oracle.digest(got) == oracle.digest(np.unique(stream, axis=0))
+
+
+def test_small_alphabet_many_collisions(lhs):
+    # W=2 vectors over a 40x40 grid: heavy in-batch duplication
+    print("\n[fop] small alphabet", flush=True)
+    rng = np.random.default_rng(5)
+    stream = rng.integers(0, 40, size=(200_000, 2)).astype(np.uint32)
+    o_seen, o_id, distinct = oracle.stream(stream)
+    with lhs.Table(1 << 12, 2) as t:
+        seen, idx, bounds = _run_stream(lhs, t, stream, 50_000)
+        check_stream_batches(o_id, distinct, seen, idx, bounds)
+        check_table_invariants(t)
+
+
+def test_one_vector_many_copies(lhs):
+    print("\n[fop] 2^20 copies of one vector", flush=True)
+    stream = np.tile(np.arange(16, dtype=np.uint32), (1 << 20, 1))
+    with lhs.Table(1 << 16, 16) as t:
+        seen, idx, bounds = _run_stream(lhs, t, stream, 1 << 20)
+        assert int((seen == 0).sum()) == 1 and int((seen == 1).sum()) == (1 << 20) - 1
+        assert len(np.unique(idx)) == 1
+        assert t.count() == 1
+        print("wait_hits", t.info()["wait_hits"], "cas_failures", t.info()["cas_failures"])
+
+
+def test_full_table_and_clear(lhs):
+    print("\n[fop] capacity-16 table", flush=True)
+    rows = gen.words(77, 17 * 4).reshape(17, 4)
+    with lhs.Table(16, 4) as t:
+        seen, idx, _ = _run_stream(lhs, t, rows[:16], 1 << 30)
+        assert np.all(seen == 0) and sorted(idx.tolist()) == list(range(16))
+        seen, idx, _ = _run_stream(lhs, t, rows[:16], 1 << 30)     # all present now
+        assert np.all(seen == 1)
+        import torch
+        dev = dev_u32(rows[16:])
+        s = torch.empty(1, dtype=torch.uint8, device="cuda")
+        t.find_or_put(dev, s)
+        with pytest.raises(lhs.LhsError) as e:
+            t.check()
+        assert e.value.name == "LHS_EFULL"
+        assert int(s.cpu()[0]) == 0xFF
+        t.clear()
+        t.check()
+        assert t.count() == 0
+
+
+def test_high_fill(lhs):
+    # 4000 distinct vectors in 4096 slots (97.7 % fill), then every one again
+    print("\n[fop] high fill", flush=True)
+    rows = np.unique(gen.words(9, 4100 * 8).reshape(4100, 8), axis=0)[:4000]
+    with lhs.Table(1 << 12, 8) as t:
+        seen, idx, _ = _run_stream(lhs, t, rows, 1 << 30)
+        assert np.all(seen == 0)
+        seen2, idx2, _ = _run_stream(lhs, t, rows, 1000)
+        assert np.all(seen2 == 1) and np.array_equal(idx, idx2)
+        assert t.count() == 4000
+        check_table_invariants(t)
+
+
+def test_empty_batch(lhs):
+    import torch
+    with lhs.Table(1 << 10, 4) as t:
+        t.find_or_put(torch.empty((0, 4), dtype=torch.int32, device="cuda"),
+                      torch.empty(0, dtype=torch.uint8, device="cuda"))
+        t.check()
+        assert t.count() == 0

@@ -1,0 +1,109 @@
+"""GPU level-synchronous BFS vs the CPU oracle: reachable set, per-level
+counts, edges and deadlocks must match exactly."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from oracle.closed_form import cyclic_summary
+
+from conftest import load_golden, model_from_fixture, result_fields
+from gpu_util import check_table_invariants
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lhs():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1004_2772_amd
+    return paper_1004_2772_amd
+
+
+def _capacity_for(states):
+    # room for the kept states plus the overshoot of a discarded level
+    return 1 << max(10, (2 * states + (1 << 16)).bit_length())
+
+
+def _gpu(lhs, m, cap=None, capacity=None):
+    cap = m.cap if cap is None else cap
+    if capacity is None:
+        capacity = _capacity_for(cap if cap else 1 << 20)
+    with lhs.Table(capacity, m.W) as t:
+        r = lhs.reach_explore(m, cap=cap, table=t)
+        rows, _ = check_table_invariants(t)
+    return r, rows
+
+
+def _compare(lhs, m, cap=None, capacity=None):
+    want = oracle.reach(m, cap=cap)
+    if capacity is None:
+        capacity = _capacity_for(max(want.total, cap or 0))
+    got, rows = _gpu(lhs, m, cap, capacity)
+    assert result_fields(got) == result_fields(want), m.describe()
+    assert oracle.digest(rows) == want.digest
+    return got
+
+
+def test_tiny_cyclic(lhs):
+    print("\n[reach] cyclic 4x8", flush=True)
+    m = gen.tiny_cyclic()
+    got = _compare(lhs, m, capacity=1 << 16)
+    assert result_fields(got) == cyclic_summary(4, 8)
+
+
+@pytest.mark.parametrize("fx", load_golden("reach_fixtures.json")["fixtures"], ids=lambda f: f["name"])
+def test_golden(lhs, fx):
+    m = model_from_fixture(fx)
+    for case in fx["cases"]:
+        print(f"\n[reach] {fx['name']} cap={case['cap']}", flush=True)
+        want = {k: case[k] for k in ("total", "level_counts", "edges", "deadlocks", "capped")}
+        want["n_levels"] = len(case["level_counts"])
+        got, _ = _gpu(lhs, m, cap=case["cap"], capacity=1 << 12)
+        assert result_fields(got) == want
+
+
+def _random_models(n, seed):
+    rng = np.random.default_rng(seed)
+    for i in range(n):
+        P = int(rng.integers(1, 9))
+        S = int(rng.integers(0, min(9, 33 - P)))
+        L = int(rng.integers(2, 9))
+        D = int(rng.integers(2, 6))
+        K = int(rng.integers(1, 4))
+        yield gen.guarded_model(7000 + i, P, L, S, D if S else 1, K)
+
+
+def test_random_models(lhs):
+    rng = np.random.default_rng(11)
+    for m in _random_models(40, 3):
+        print(f"\n[reach] {m.describe()}", flush=True)
+        full = oracle.reach(m, cap=200_001)
+        cap = 0 if not full.capped else 200_000
+        _compare(lhs, m, cap=cap)
+        if full.total > 10:
+            _compare(lhs, m, cap=int(rng.integers(1, full.total)))
+
+
+@pytest.mark.parametrize("cap", [1 << 12, 1 << 16, 1 << 19])
+def test_big_model_capped(lhs, cap):
+    print(f"\n[reach] big model cap={cap}", flush=True)
+    m = gen.big_model(cap=cap)
+    got = _compare(lhs, m)
+    assert got.capped
+
+
+@pytest.mark.parametrize("W", [4, 7, 16, 32])
+def test_width_range(lhs, W):
+    print(f"\n[reach] width {W}", flush=True)
+    P = min(W - 1, 12) if W > 1 else 1
+    m = gen.guarded_model(31 + W, P, 6, W - P, 4, 3)
+    _compare(lhs, m, cap=100_000)
+
+
+def test_repeatable(lhs):
+    m = gen.big_model(cap=1 << 15)
+    a, _ = _gpu(lhs, m)
+    b, _ = _gpu(lhs, m)
+    assert result_fields(a) == result_fields(b)
