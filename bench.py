@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true", help="also run the copy probe (counter calibration)")
     ap.add_argument("--bfs-cap", type=int, default=1 << 27)
     ap.add_argument("--cpu-sample", type=int, default=1 << 25)
+    ap.add_argument("--tps", type=int, default=0, help="lanes per operation (0 = library default)")
+    ap.add_argument("--sweep-tps", action="store_true", help="also time every threads-per-state value")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -115,6 +117,8 @@ def main():
     seen_d = torch.empty(n, dtype=torch.uint8, device=dev)
     idx_d = torch.empty(n, dtype=torch.int32, device=dev)
     table = lhs.Table(1 << args.table_log2, W)
+    if args.tps:
+        table.set_threads_per_state(args.tps)
     torch.cuda.synchronize()
 
     kernel_events = []
@@ -160,6 +164,28 @@ def main():
         f"new={new} stored={stored} ok={ok}")
     info = table.info()
 
+    def time_fop(tps, reps=3):
+        table.set_threads_per_state(tps)
+        ts = []
+        for _ in range(reps):
+            table.clear()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            table.find_or_put(states_d, seen_d, idx_d)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        table.check()
+        return sorted(ts)[len(ts) // 2]
+
+    sweep = {}
+    if args.sweep_tps:
+        for tps in (1, 4, 8, 16):
+            ms = time_fop(tps)
+            sweep[str(tps)] = {"fop_ms": round(ms, 3), "fop_Gops": round(n / ms / 1e6, 3)}
+            log(f"tps={tps}: find-or-put {ms:.3f} ms")
+        table.set_threads_per_state(info["threads_per_state"])
+
     ops_per_s = n / (ms_per_step / 1e3)
     bpo = fop_bytes_per_op(W)
     launch_ops = min(batch, n)
@@ -188,6 +214,7 @@ def main():
         "roofline": roofline,
         "checks": {"new_equals_distinct": ok, "wait_hits": info["wait_hits"],
                    "cas_failures": info["cas_failures"]},
+        "threads_per_state": info["threads_per_state"],
         "wall_s_timed": round(wall, 3),
     }
 
@@ -252,7 +279,16 @@ def main():
                 g = json.load(f)
             bfs["matches_oracle_counts"] = (g["level_counts"] == res.level_counts and
                                             g["edges"] == res.edges and g["deadlocks"] == res.deadlocks)
+        if args.sweep_tps:
+            for tps in (1, 4, 8, 16):
+                table.set_threads_per_state(tps)
+                r = lhs.reach_explore(m, table=table)
+                sweep[str(tps)]["bfs_ms"] = round(r.gpu_ms, 2)
+                log(f"tps={tps}: bfs {r.gpu_ms:.1f} ms")
+            table.set_threads_per_state(info["threads_per_state"])
         out["bfs"] = bfs
+    if sweep:
+        out["tps_sweep"] = sweep
 
     table.close()
     del states_d, seen_d, idx_d

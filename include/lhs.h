@@ -90,6 +90,12 @@ lhs_status lhs_clear(lhs_table *t, void *hip_stream);
 lhs_status lhs_find_or_put(lhs_table *t, const uint32_t *d_states, uint64_t n,
                            uint8_t *d_seen, uint32_t *d_index, void *hip_stream);
 
+/* Number of GPU lanes that cooperate on one find-or-put: 1, 4, 8 or 16 (a
+ * group of G lanes loads a 128-byte slot line as one coalesced access, 16/G
+ * slots per lane).  Affects speed only; results are identical for every
+ * value.  Applies to later calls on the table (find-or-put and BFS). */
+lhs_status lhs_set_threads_per_state(lhs_table *t, uint32_t tps);
+
 /* Wait for the last stream used with the table, then return its sticky
  * device error (LHS_EFULL / LHS_ESTALL) or LHS_OK. */
 lhs_status lhs_check(lhs_table *t);
@@ -121,7 +127,7 @@ typedef struct lhs_info {
                               paper's write-busy "lock" hits)                */
     uint64_t cas_failures; /* lost claims of an empty slot                   */
     uint32_t error;        /* sticky lhs_status of device failures           */
-    uint32_t reserved;
+    uint32_t threads_per_state; /* lanes cooperating on one operation        */
 } lhs_info;
 
 /* Table geometry and device counters (synchronises the last stream). */

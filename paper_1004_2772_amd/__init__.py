@@ -26,6 +26,7 @@ REACH_F_HOST_LOOP = 1
 
 #: every symbol include/lhs.h declares
 EXPORTS = ["lhs_strerror", "lhs_create", "lhs_destroy", "lhs_clear", "lhs_find_or_put",
+           "lhs_set_threads_per_state",
            "lhs_check", "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info",
            "reach_explore", "reach_result_free",
            "lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_copy"]
@@ -42,7 +43,7 @@ class LhsInfo(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_uint64), ("state_words", ctypes.c_uint32),
                 ("line_slots", ctypes.c_uint32), ("hash_seed", ctypes.c_uint64),
                 ("wait_hits", ctypes.c_uint64), ("cas_failures", ctypes.c_uint64),
-                ("error", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("error", ctypes.c_uint32), ("threads_per_state", ctypes.c_uint32)]
 
 
 class ReachModel(ctypes.Structure):
@@ -83,6 +84,7 @@ def lib() -> ctypes.CDLL:
         L.lhs_clear.argtypes = [p, p]
         L.lhs_find_or_put.argtypes = [p, p, u64, p, p, p]
         L.lhs_check.argtypes = [p]
+        L.lhs_set_threads_per_state.argtypes = [p, u32]
         L.lhs_count.argtypes = [p, ctypes.POINTER(u64)]
         L.lhs_dump.argtypes = [p, p, p, u64, ctypes.POINTER(u64)]
         L.lhs_dump_slots.argtypes = [p, p]
@@ -96,6 +98,7 @@ def lib() -> ctypes.CDLL:
         L.lhs_probe_copy.argtypes = [p, p, u64, p]
         for name in ("lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_copy",
                      "lhs_create", "lhs_destroy", "lhs_clear", "lhs_find_or_put", "lhs_check",
+                     "lhs_set_threads_per_state",
                      "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info", "reach_explore"):
             getattr(L, name).restype = st
         _lib = L
@@ -170,6 +173,9 @@ class Table:
 
     def check(self):
         _check(lib().lhs_check(self.handle), "lhs_check")
+
+    def set_threads_per_state(self, tps: int):
+        _check(lib().lhs_set_threads_per_state(self.handle, tps), "lhs_set_threads_per_state")
 
     def count(self) -> int:
         c = ctypes.c_uint64()

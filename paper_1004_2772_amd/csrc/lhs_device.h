@@ -1,11 +1,25 @@
 // Device-side core of the lockless table: slot encoding, the vector hash and
-// the per-lane find-or-put (Algorithm 3 with walking-the-line, Algorithm 4).
+// find-or-put (Algorithm 3 with walking-the-line, Algorithm 4) executed by a
+// group of G cooperating lanes per operation.
 //
 // Slot (64 bits): 0 = empty; bit 63 OCC = claimed; bit 62 DONE = the vector
 // has been written to the data array; bits 61..0 = memoised hash (the low 62
 // bits of h1).  A slot goes empty -> claimed(memo) -> done(memo) and never
 // changes again (figure "State diagram of buckets"): a slot seen non-empty
 // keeps its memo forever, which is what makes a stale snapshot of a line safe.
+//
+// Memory ordering on gfx950 (8 XCDs, one L2 each).  The paper's requirement
+// (section on the algorithm's memory-model needs): the vector must not be
+// written before its slot is claimed, and a reader that sees DONE must see
+// the whole vector.  Here:
+//  * the claim is a 64-bit agent-scope CAS; the row is written only by the
+//    winner, after the CAS returned (control dependency);
+//  * row words are written and read with agent-scope atomic accesses, which
+//    are coherent across the XCDs' L2 caches (no write-back or invalidate of
+//    whole caches is needed for them);
+//  * the publisher waits for its row stores to complete (vmcnt(0)) before
+//    storing DONE; a reader issues its row loads only after its load of the
+//    slot returned DONE.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -45,6 +59,38 @@ struct TableView {
     uint32_t max_rounds;     // lines probed before EFULL
     DevStatus *status;
 };
+
+__device__ __forceinline__ uint32_t mbcnt(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// ---- coherent (agent-scope) accesses --------------------------------------
+__device__ __forceinline__ uint64_t ld_coherent(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_coherent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coherent(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coherent(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until this wavefront's outstanding vector memory operations completed
+// (s_waitcnt vmcnt(0)); the signal fences keep the compiler from moving
+// memory accesses across it.
+__device__ __forceinline__ void wait_vm_complete() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+// Compiler-level acquire after observing DONE (the hardware already orders
+// the dependent loads after the observed load).
+__device__ __forceinline__ void after_done_observed() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 __device__ __forceinline__ uint64_t rotl64(uint64_t x, int r) {
     return (x << r) | (x >> (64 - r));
@@ -92,36 +138,124 @@ __device__ __forceinline__ uint32_t rotr16(uint32_t m, uint32_t r) {
     return ((m >> r) | (m << (16 - r))) & 0xFFFFu;
 }
 
-template <class Vec>
-__device__ __forceinline__ void write_row(uint32_t *row, const Vec &v, uint32_t W) {
-    if ((W & 3u) == 0) {
-        uint4 *r4 = reinterpret_cast<uint4 *>(row);
-        for (uint32_t i = 0; i < W; i += 4)
-            r4[i >> 2] = make_uint4(v.get(i), v.get(i + 1), v.get(i + 2), v.get(i + 3));
+// Spread the low 16/S bits of x so that bit i lands on bit i*S (S = 1, 2, 4).
+template <uint32_t S>
+__device__ __forceinline__ uint32_t spread(uint32_t x) {
+    if constexpr (S == 1) {
+        return x;
+    } else if constexpr (S == 2) {
+        x = (x | (x << 4)) & 0x0F0Fu;
+        x = (x | (x << 2)) & 0x3333u;
+        return (x | (x << 1)) & 0x5555u;
     } else {
-        for (uint32_t i = 0; i < W; ++i)
-            row[i] = v.get(i);
+        static_assert(S == 4, "slots per lane");
+        x = (x | (x << 6)) & 0x0303u;
+        return (x | (x << 3)) & 0x1111u;
     }
 }
 
-template <class Vec>
-__device__ __forceinline__ bool row_equals(const uint32_t *row, const Vec &v, uint32_t W) {
-    uint32_t diff = 0;
-    if ((W & 3u) == 0) {
-        const uint4 *r4 = reinterpret_cast<const uint4 *>(row);
-        for (uint32_t i = 0; i < W; i += 4) {
-            const uint4 x = r4[i >> 2];
-            diff |= (x.x ^ v.get(i)) | (x.y ^ v.get(i + 1)) | (x.z ^ v.get(i + 2)) |
-                    (x.w ^ v.get(i + 3));
+// Lane geometry of a group of G consecutive lanes of a wavefront.
+template <int G>
+struct Group {
+    uint32_t sub, gbase;
+    __device__ __forceinline__ Group() {
+        const uint32_t lane = __lane_id();
+        sub = lane & (G - 1);
+        gbase = lane - sub;
+    }
+    __device__ __forceinline__ bool leader() const { return sub == 0; }
+    // this group's G bits of a wavefront ballot
+    __device__ __forceinline__ uint32_t bits(uint64_t ballot) const {
+        return (uint32_t)(ballot >> gbase) & (uint32_t)((1ull << G) - 1);
+    }
+    __device__ __forceinline__ bool all(bool x) const {
+        if constexpr (G == 1)
+            return x;
+        return bits(__ballot(x)) == (uint32_t)((1ull << G) - 1);
+    }
+    __device__ __forceinline__ uint64_t from_leader(uint64_t v) const {
+        if constexpr (G == 1)
+            return v;
+        const uint32_t lo = __shfl((uint32_t)v, (int)gbase, 64);
+        const uint32_t hi = __shfl((uint32_t)(v >> 32), (int)gbase, 64);
+        return ((uint64_t)hi << 32) | lo;
+    }
+};
+
+// Snapshot of one 128-byte line: masks of empty slots and of slots whose
+// memo equals `memo` (any status), bit i = slot i of the line.  The G lanes of
+// a group load 16/G contiguous slots each (one coalesced 128-byte access per
+// group).
+template <int G>
+__device__ __forceinline__ void line_masks(const Group<G> &g, const uint64_t *line_ptr, uint64_t memo,
+                                           uint32_t &empty, uint32_t &match) {
+    constexpr uint32_t SPL = kLineSlots / G;
+    uint64_t s[SPL];
+    if constexpr (SPL == 1) {
+        s[0] = line_ptr[g.sub];
+    } else {
+        const uint4 *p = reinterpret_cast<const uint4 *>(line_ptr + g.sub * SPL);
+#pragma unroll
+        for (uint32_t q = 0; q < SPL / 2; ++q) {
+            const uint4 x = p[q];
+            s[2 * q] = ((uint64_t)x.y << 32) | x.x;
+            s[2 * q + 1] = ((uint64_t)x.w << 32) | x.z;
+        }
+    }
+    uint32_t e = 0, m = 0;
+    if constexpr (G == 1) {
+#pragma unroll
+        for (uint32_t i = 0; i < SPL; ++i) {
+            e |= (uint32_t)(s[i] == 0) << i;
+            m |= (uint32_t)((s[i] & ~kDone) == memo) << i;
         }
     } else {
-        for (uint32_t i = 0; i < W; ++i)
-            diff |= row[i] ^ v.get(i);
+#pragma unroll
+        for (uint32_t i = 0; i < SPL; ++i) {
+            e |= spread<SPL>(g.bits(__ballot(s[i] == 0))) << i;
+            m |= spread<SPL>(g.bits(__ballot((s[i] & ~kDone) == memo))) << i;
+        }
     }
-    return diff == 0;
+    empty = e;
+    match = m;
 }
 
-// One find-or-put per lane.
+// Row write by the group: 64-bit coherent stores when W is even (rows are
+// 8-byte aligned), 32-bit otherwise; lane `sub` takes every G-th piece.
+template <int G, class Vec>
+__device__ __forceinline__ void write_row(const Group<G> &g, uint32_t *row, const Vec &v, uint32_t W) {
+    if ((W & 1u) == 0) {
+        uint64_t *r2 = reinterpret_cast<uint64_t *>(row);
+        for (uint32_t j = g.sub; j < W / 2; j += G)
+            st_coherent(r2 + j, (uint64_t)v.get(2 * j) | ((uint64_t)v.get(2 * j + 1) << 32));
+    } else {
+        for (uint32_t i = g.sub; i < W; i += G)
+            st_coherent(row + i, v.get(i));
+    }
+}
+
+template <int G, class Vec>
+__device__ __forceinline__ bool row_equals(const Group<G> &g, const uint32_t *row, const Vec &v,
+                                           uint32_t W) {
+    uint32_t diff = 0;
+    if ((W & 1u) == 0) {
+        const uint64_t *r2 = reinterpret_cast<const uint64_t *>(row);
+        for (uint32_t j = g.sub; j < W / 2; j += G) {
+            const uint64_t x = ld_coherent(r2 + j);
+            diff |= ((uint32_t)x ^ v.get(2 * j)) | ((uint32_t)(x >> 32) ^ v.get(2 * j + 1));
+        }
+    } else {
+        for (uint32_t i = g.sub; i < W; i += G)
+            diff |= ld_coherent(row + i) ^ v.get(i);
+    }
+    return g.all(diff == 0);
+}
+
+// One find-or-put per group of G lanes (G = 1, 4, 8 or 16).
+//
+// All lanes of the wavefront call this together; `active`, `v` and `h` are
+// uniform within a group, and every decision below is taken from
+// group-uniform values, so the G lanes of a group always run the same path.
 //
 // The probe sequence of a vector with hash h: home line (h >> 4) & line_mask,
 // start slot h & 15 inside it; the line is examined in walk order
@@ -134,24 +268,25 @@ __device__ __forceinline__ bool row_equals(const uint32_t *row, const Vec &v, ui
 // Per line one 128-byte snapshot is taken.  Candidates are, in walk order, the
 // snapshot's empty slots and the slots whose memo equals ours.  Slots that
 // are claimed with another memo are skipped: they are immutable.
-//  - empty candidate: CAS(0 -> OCC|memo).  Won: write the row, then publish
-//    OCC|DONE|memo with release semantics; result "new".  Lost: the CAS
-//    returned the slot's value; if its memo is ours it becomes a match
-//    candidate, otherwise walk on.
-//  - match candidate: acquire-load the slot until DONE (a bounded wait, the
-//    paper's write-busy "lock"), then compare the stored row; equal means
-//    "seen", otherwise walk on.
+//  - empty candidate: the group leader CASes 0 -> OCC|memo.  Won: the group
+//    writes the row, waits for the stores, and the leader stores
+//    OCC|DONE|memo; result "new".  Lost: the CAS returned the slot's value;
+//    if its memo is ours it becomes a match candidate, otherwise walk on.
+//  - match candidate: load the slot until DONE (a bounded wait, the paper's
+//    write-busy "lock"), then compare the stored row; equal means "seen",
+//    otherwise walk on.
 //
 // SIMT forward progress: every loop iteration runs the claim phase (CAS,
 // row write, publish) for all lanes before the wait phase of any lane, and
-// nothing waits between a claim and its publish.  A lane that waits on a slot
-// claimed by a lane of its own wavefront therefore finds it already
+// nothing waits between a claim and its publish.  A group that waits on a
+// slot claimed by a group of its own wavefront therefore finds it already
 // published; a claim made by another wavefront is published without that
 // wavefront waiting on anything first.
-template <class Vec>
-__device__ __forceinline__ void find_or_put(const TableView &t, const Vec &v, uint64_t h,
+template <int G, class Vec>
+__device__ __forceinline__ void find_or_put(const TableView &t, const Vec &v, uint64_t h, bool active,
                                             uint32_t &out_slot, uint32_t &out_code,
                                             LaneCounters &cnt) {
+    const Group<G> g;
     const uint64_t memo = kOcc | (h & kMemoMask);
     const uint32_t start = (uint32_t)h & (kLineSlots - 1);
     const uint32_t step = (uint32_t)(h >> 32) | 1u;
@@ -161,26 +296,19 @@ __device__ __forceinline__ void find_or_put(const TableView &t, const Vec &v, ui
     bool have_line = false;
     out_slot = kNoSlot;
     out_code = kFull;
+    if (!active)
+        return;
 
     while (true) {
         if (!have_line) {
             if (rounds == t.max_rounds) {
                 out_code = kFull;
-                set_error(t.status, 3u /* LHS_EFULL */);
+                if (g.leader())
+                    set_error(t.status, 3u /* LHS_EFULL */);
                 break;
             }
-            const uint4 *lp = reinterpret_cast<const uint4 *>(t.bucket + (uint64_t)line * kLineSlots);
-            uint32_t e = 0, m = 0;
-#pragma unroll
-            for (uint32_t q = 0; q < kLineSlots / 2; ++q) {
-                const uint4 x = lp[q];
-                const uint64_t s0 = ((uint64_t)x.y << 32) | x.x;
-                const uint64_t s1 = ((uint64_t)x.w << 32) | x.z;
-                e |= (uint32_t)(s0 == 0) << (2 * q);
-                e |= (uint32_t)(s1 == 0) << (2 * q + 1);
-                m |= (uint32_t)((s0 & ~kDone) == memo) << (2 * q);
-                m |= (uint32_t)((s1 & ~kDone) == memo) << (2 * q + 1);
-            }
+            uint32_t e, m;
+            line_masks<G>(g, t.bucket + (uint64_t)line * kLineSlots, memo, e, m);
             empty = rotr16(e, start);
             cand = rotr16(e | m, start);
             have_line = true;
@@ -195,47 +323,329 @@ __device__ __forceinline__ void find_or_put(const TableView &t, const Vec &v, ui
         cand &= cand - 1;
         const uint32_t slot = line * kLineSlots + ((start + k) & (kLineSlots - 1));
         uint64_t *bp = t.bucket + slot;
+        uint32_t *row = t.data + (uint64_t)slot * t.W;
         bool match = ((empty >> k) & 1u) == 0;
         bool finished = false;
 
         // ---- claim phase ------------------------------------------------
         if (!match) {
-            uint64_t expected = 0;
-            if (__hip_atomic_compare_exchange_strong(bp, &expected, memo, __ATOMIC_RELAXED,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                write_row(t.data + (uint64_t)slot * t.W, v, t.W);
-                __hip_atomic_store(bp, memo | kDone, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t old = 0;
+            if (g.leader())
+                __hip_atomic_compare_exchange_strong(bp, &old, memo, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            old = g.from_leader(old);
+            if (old == 0) {
+                write_row<G>(g, row, v, t.W);
+                wait_vm_complete();
+                if (g.leader())
+                    st_coherent(bp, memo | kDone);
                 out_slot = slot;
                 out_code = kNew;
                 finished = true;
             } else {
-                ++cnt.cas_failures;
-                match = (expected & ~kDone) == memo;
+                cnt.cas_failures += g.leader();
+                match = (old & ~kDone) == memo;
             }
         }
         // ---- wait + compare phase --------------------------------------
         if (match && !finished) {
-            uint64_t cur = __hip_atomic_load(bp, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t cur = ld_coherent(bp);
+            if (!(cur & kDone)) {
+                cnt.waits += g.leader();
+                uint32_t spins = 0;
+                while (!(cur & kDone) && ++spins < kSpinLimit) {
+                    __builtin_amdgcn_s_sleep(2);
+                    cur = ld_coherent(bp);
+                }
+            }
+            if (!(cur & kDone)) {
+                out_code = kStall;
+                if (g.leader())
+                    set_error(t.status, 4u /* LHS_ESTALL */);
+                finished = true;
+            } else {
+                after_done_observed();
+                if (row_equals<G>(g, row, v, t.W)) {
+                    out_slot = slot;
+                    out_code = kSeen;
+                    finished = true;
+                }
+            }
+        }
+        if (finished)
+            break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One operation per lane with wavefront-cooperative memory accesses.
+//
+// Every lane owns one find-or-put (64 operations in flight per wavefront),
+// but the random 128-byte slot lines and the vector rows are moved by the
+// whole wavefront: the lanes that need a line (or a row) this iteration are
+// compacted into a list in LDS, and eight lanes serve each listed line (16
+// bytes each, one coalesced access per line) or row (8 bytes each).  Results
+// come back through the same per-wavefront LDS area.  The helpers need the
+// owner's vector: `Vec` has a two-word descriptor any lane can decode.
+
+struct WaveScratch {         // one per wavefront, in LDS
+    uint32_t idx[64];        // listed line / slot per rank
+    uint32_t aux[64];        // second word (row descriptor y)
+    uint64_t key[64];        // memo per rank (line snapshots)
+    uint32_t desc[64];       // row descriptor x per rank
+    uint8_t res[64 * 8];     // per (rank, helper lane) result bits
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Masks (bit i = slot i of the line) of empty, memo-matching and done slots
+// for every lane with `need`; other lanes only help.  Wavefront-uniform call.
+__device__ __forceinline__ void coop_line_masks(WaveScratch *ws, const uint64_t *bucket, bool need,
+                                                uint32_t line, uint64_t memo, uint32_t &empty,
+                                                uint32_t &match, uint32_t &done) {
+    const uint32_t lane = __lane_id();
+    const uint64_t nmask = __ballot(need);
+    const uint32_t nn = (uint32_t)__popcll(nmask);
+    const uint32_t rank = mbcnt(nmask);
+    if (need) {
+        ws->idx[rank] = line;
+        ws->key[rank] = memo;
+    }
+    wave_lds_sync();
+    const uint32_t c = lane & 7u;
+    uint4 x[8];
+#pragma unroll
+    for (uint32_t q = 0; q < 8; ++q) {
+        const uint32_t i = q * 8 + (lane >> 3);
+        if (i < nn)
+            x[q] = reinterpret_cast<const uint4 *>(bucket + (uint64_t)ws->idx[i] * kLineSlots)[c];
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < 8; ++q) {
+        const uint32_t i = q * 8 + (lane >> 3);
+        if (i < nn) {
+            const uint64_t s0 = ((uint64_t)x[q].y << 32) | x[q].x;
+            const uint64_t s1 = ((uint64_t)x[q].w << 32) | x[q].z;
+            const uint64_t mk = ws->key[i];
+            const uint32_t b = (uint32_t)(s0 == 0) | ((uint32_t)(s1 == 0) << 1) |
+                               ((uint32_t)((s0 & ~kDone) == mk) << 2) |
+                               ((uint32_t)((s1 & ~kDone) == mk) << 3) |
+                               ((uint32_t)(s0 >> 62) & 1u) << 4 | (((uint32_t)(s1 >> 62) & 1u) << 5);
+            ws->res[i * 8 + c] = (uint8_t)b;
+        }
+    }
+    wave_lds_sync();
+    if (need) {
+        const uint2 r = reinterpret_cast<const uint2 *>(ws->res)[rank];
+        uint32_t e = 0, m = 0, d = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) {
+            const uint32_t b = ((k < 4 ? r.x : r.y) >> (8 * (k & 3))) & 0xFFu;
+            e |= (b & 3u) << (2 * k);
+            m |= ((b >> 2) & 3u) << (2 * k);
+            d |= ((b >> 4) & 3u) << (2 * k);
+        }
+        empty = e;
+        match = m;
+        done = d;
+    }
+    wave_lds_sync();
+}
+
+// Write the rows of every lane with `go` (slot, descriptor); eight lanes per
+// row, 64-bit coherent stores when W is even, 32-bit otherwise.
+template <class Vec>
+__device__ __forceinline__ void coop_write_rows(WaveScratch *ws, const uint32_t *smem, uint32_t *data,
+                                                uint32_t W, bool go, uint32_t slot, uint2 d) {
+    const uint32_t lane = __lane_id();
+    const uint64_t gm = __ballot(go);
+    const uint32_t ng = (uint32_t)__popcll(gm);
+    const uint32_t rank = mbcnt(gm);
+    if (go) {
+        ws->idx[rank] = slot;
+        ws->desc[rank] = d.x;
+        ws->aux[rank] = d.y;
+    }
+    wave_lds_sync();
+    const uint32_t c = lane & 7u;
+    for (uint32_t i0 = 0; i0 < ng; i0 += 8) {
+        const uint32_t i = i0 + (lane >> 3);
+        if (i < ng) {
+            const Vec v = Vec::decode(smem, make_uint2(ws->desc[i], ws->aux[i]));
+            uint32_t *row = data + (uint64_t)ws->idx[i] * W;
+            if ((W & 1u) == 0) {
+                uint64_t *r2 = reinterpret_cast<uint64_t *>(row);
+                for (uint32_t j = c; j < W / 2; j += 8)
+                    st_coherent(r2 + j, (uint64_t)v.get(2 * j) | ((uint64_t)v.get(2 * j + 1) << 32));
+            } else {
+                for (uint32_t j = c; j < W; j += 8)
+                    st_coherent(row + j, v.get(j));
+            }
+        }
+    }
+    wave_lds_sync();
+}
+
+// Compare the stored rows of every lane with `go` against its vector;
+// returns equality for those lanes.  Same layout as coop_write_rows.
+template <class Vec>
+__device__ __forceinline__ bool coop_rows_equal(WaveScratch *ws, const uint32_t *smem,
+                                                const uint32_t *data, uint32_t W, bool go,
+                                                uint32_t slot, uint2 d) {
+    const uint32_t lane = __lane_id();
+    const uint64_t gm = __ballot(go);
+    const uint32_t ng = (uint32_t)__popcll(gm);
+    const uint32_t rank = mbcnt(gm);
+    if (go) {
+        ws->idx[rank] = slot;
+        ws->desc[rank] = d.x;
+        ws->aux[rank] = d.y;
+    }
+    wave_lds_sync();
+    const uint32_t c = lane & 7u;
+    for (uint32_t i0 = 0; i0 < ng; i0 += 8) {
+        const uint32_t i = i0 + (lane >> 3);
+        uint32_t diff = 0;
+        if (i < ng) {
+            const Vec v = Vec::decode(smem, make_uint2(ws->desc[i], ws->aux[i]));
+            const uint32_t *row = data + (uint64_t)ws->idx[i] * W;
+            if ((W & 1u) == 0) {
+                const uint64_t *r2 = reinterpret_cast<const uint64_t *>(row);
+                for (uint32_t j = c; j < W / 2; j += 8) {
+                    const uint64_t x = ld_coherent(r2 + j);
+                    diff |= ((uint32_t)x ^ v.get(2 * j)) | ((uint32_t)(x >> 32) ^ v.get(2 * j + 1));
+                }
+            } else {
+                for (uint32_t j = c; j < W; j += 8)
+                    diff |= ld_coherent(row + j) ^ v.get(j);
+            }
+            ws->res[i * 8 + c] = diff != 0;
+        }
+    }
+    wave_lds_sync();
+    bool eq = false;
+    if (go) {
+        const uint2 r = reinterpret_cast<const uint2 *>(ws->res)[rank];
+        eq = (r.x | r.y) == 0;
+    }
+    wave_lds_sync();
+    return eq;
+}
+
+// One find-or-put per lane, memory moved cooperatively (see above).  The
+// probe sequence, walk order, claim/publish protocol and the SIMT
+// forward-progress structure (claim phase, then publish, then waits, in every
+// iteration) are those of the group variant.  Additionally a match candidate
+// whose snapshot (or failed CAS) already showed DONE is compared without
+// re-reading its slot: DONE never goes away, and the row loads are coherent
+// and issued after that observation completed.
+//
+// All 64 lanes must call this together (inactive lanes only help).  `d` is
+// the lane's vector descriptor (Vec::decode(smem, d) rebuilds it in any lane).
+template <class Vec>
+__device__ __forceinline__ void find_or_put_wave(const TableView &t, WaveScratch *ws,
+                                                 const uint32_t *smem, uint2 d, uint64_t h,
+                                                 bool active, uint32_t &out_slot,
+                                                 uint32_t &out_code, LaneCounters &cnt) {
+    const uint64_t memo = kOcc | (h & kMemoMask);
+    const uint32_t start = (uint32_t)h & (kLineSlots - 1);
+    const uint32_t step = (uint32_t)(h >> 32) | 1u;
+    uint32_t line = (uint32_t)(h >> 4) & t.line_mask;
+    uint32_t rounds = 0, cand = 0, empty = 0, donem = 0;
+    bool have_line = false, finished = !active;
+    out_slot = kNoSlot;
+    out_code = kFull;
+
+    while (__ballot(!finished)) {
+        // ---- line snapshots for the lanes that need one -------------------
+        if (!finished && !have_line && rounds == t.max_rounds) {
+            out_code = kFull;
+            set_error(t.status, 3u /* LHS_EFULL */);
+            finished = true;
+        }
+        const bool need = !finished && !have_line;
+        if (__ballot(need)) {
+            uint32_t e = 0, m = 0, dn = 0;
+            coop_line_masks(ws, t.bucket, need, line, memo, e, m, dn);
+            if (need) {
+                empty = rotr16(e, start);
+                cand = rotr16(e | m, start);
+                donem = rotr16(dn, start);
+                have_line = true;
+            }
+        }
+        // ---- next candidate in walk order ---------------------------------
+        uint32_t kind = 0, slot = 0;     // kind: 0 none, 1 empty, 2 match
+        bool known_done = false;
+        if (!finished) {
+            if (cand == 0) {
+                have_line = false;
+                ++rounds;
+                line = (line + step) & t.line_mask;
+            } else {
+                const uint32_t k = __builtin_ctz(cand);
+                cand &= cand - 1;
+                slot = line * kLineSlots + ((start + k) & (kLineSlots - 1));
+                kind = ((empty >> k) & 1u) ? 1u : 2u;
+                known_done = (donem >> k) & 1u;
+            }
+        }
+        // ---- claim phase ----------------------------------------------------
+        bool won = false;
+        if (kind == 1) {
+            uint64_t old = 0;
+            __hip_atomic_compare_exchange_strong(t.bucket + slot, &old, memo, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (old == 0) {
+                won = true;
+            } else {
+                ++cnt.cas_failures;
+                kind = (old & ~kDone) == memo ? 2u : 0u;
+                known_done = (old & kDone) != 0;
+            }
+        }
+        if (__ballot(won)) {
+            coop_write_rows<Vec>(ws, smem, t.data, t.W, won, slot, d);
+            wait_vm_complete();
+            if (won) {
+                st_coherent(t.bucket + slot, memo | kDone);
+                out_slot = slot;
+                out_code = kNew;
+                finished = true;
+            }
+        }
+        // ---- wait phase (only slots not yet seen done) ----------------------
+        if (kind == 2 && !known_done) {
+            uint64_t cur = ld_coherent(t.bucket + slot);
             if (!(cur & kDone)) {
                 ++cnt.waits;
                 uint32_t spins = 0;
                 while (!(cur & kDone) && ++spins < kSpinLimit) {
                     __builtin_amdgcn_s_sleep(2);
-                    cur = __hip_atomic_load(bp, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    cur = ld_coherent(t.bucket + slot);
                 }
             }
             if (!(cur & kDone)) {
                 out_code = kStall;
                 set_error(t.status, 4u /* LHS_ESTALL */);
                 finished = true;
-            } else if (row_equals(t.data + (uint64_t)slot * t.W, v, t.W)) {
+                kind = 0;
+            }
+        }
+        // ---- compare phase --------------------------------------------------
+        const bool cmp = kind == 2;
+        if (__ballot(cmp)) {
+            after_done_observed();
+            const bool eq = coop_rows_equal<Vec>(ws, smem, t.data, t.W, cmp, slot, d);
+            if (cmp && eq) {
                 out_slot = slot;
                 out_code = kSeen;
                 finished = true;
             }
         }
-        if (finished)
-            break;
     }
 }
 

@@ -22,23 +22,39 @@ constexpr uint32_t kMaxGrid = 1u << 19;
 // A find-or-put gives up with EFULL after probing this many lines (or every
 // line of a smaller table).
 constexpr uint32_t kMaxRounds = 1u << 16;
+constexpr uint32_t kDefaultTps = 8;
 
-// A vector staged in LDS (row of W words).
+// A vector staged in LDS (row of W words); descriptor x = word offset of
+// the row from the LDS base.
 struct LdsRow {
     const uint32_t *r;
     __device__ __forceinline__ uint32_t get(uint32_t i) const { return r[i]; }
+    __device__ __forceinline__ static LdsRow decode(const uint32_t *smem, uint2 d) {
+        return LdsRow{smem + d.x};
+    }
 };
 
-// Batched find-or-put: one operation per lane.  A workgroup stages a tile of
-// 256 consecutive input rows into LDS with coalesced loads (rows padded to an
-// odd stride so that lanes reading different rows hit different banks),
-// then every lane hashes its row and runs find_or_put.
+// Batched find-or-put.  A workgroup takes a tile of 256 consecutive input
+// rows: it stages them into LDS with coalesced loads (rows padded to an odd
+// stride so that lanes reading different rows hit different banks), hashes
+// each row with one lane, then runs find-or-put.  G == 1: one operation per
+// lane with wavefront-cooperative line and row accesses (256 operations in
+// flight per workgroup).  G > 1: one group of G lanes per operation (256/G in
+// flight, G rounds per tile).  Results go through LDS so that seen/index are
+// written coalesced.
+template <int G>
 __global__ __launch_bounds__(kBlock) void k_find_or_put(TableView t, const uint32_t *__restrict__ in,
                                                         uint64_t n, uint8_t *__restrict__ seen,
                                                         uint32_t *__restrict__ index,
                                                         uint32_t magicW) {
-    extern __shared__ uint32_t tile[];
+    extern __shared__ uint32_t smem[];
     const uint32_t W = t.W, stride = W | 1u;
+    uint32_t *tile = smem;                                          // kBlock x stride
+    uint64_t *hs = reinterpret_cast<uint64_t *>(tile + kBlock * stride);
+    uint32_t *res_slot = reinterpret_cast<uint32_t *>(hs + kBlock);
+    uint32_t *res_code = res_slot + kBlock;
+    constexpr uint32_t NG = kBlock / G;
+    const uint32_t tid = threadIdx.x, gi = tid / G;
     LaneCounters cnt;
     for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < n;
          base += (uint64_t)gridDim.x * kBlock) {
@@ -46,19 +62,41 @@ __global__ __launch_bounds__(kBlock) void k_find_or_put(TableView t, const uint3
         const uint32_t words = rows * W;
         const uint32_t *src = in + base * W;
         __syncthreads();
-        for (uint32_t f = threadIdx.x; f < words; f += kBlock) {
+        for (uint32_t f = tid; f < words; f += kBlock) {
             const uint32_t r = W == 1 ? f : __umulhi(f, magicW);
             tile[r * stride + (f - r * W)] = src[f];
         }
         __syncthreads();
-        if (threadIdx.x < rows) {
-            const LdsRow v{tile + threadIdx.x * stride};
-            const uint64_t h = hash_vec(v, W, t.seed);
+        if (tid < rows)
+            hs[tid] = hash_vec(LdsRow{tile + tid * stride}, W, t.seed);
+        __syncthreads();
+        if constexpr (G == 1) {
+            __shared__ WaveScratch ws[kBlock / 64];
+            const bool active = tid < rows;
             uint32_t slot, code;
-            find_or_put(t, v, h, slot, code, cnt);
-            seen[base + threadIdx.x] = code == kSeen ? 1 : (code == kNew ? 0 : 0xFF);
+            find_or_put_wave<LdsRow>(t, &ws[tid / 64], smem, make_uint2(tid * stride, 0u),
+                                     hs[active ? tid : 0], active, slot, code, cnt);
+            res_slot[tid] = slot;
+            res_code[tid] = code;
+        } else {
+            for (uint32_t r = 0; r < G; ++r) {
+                const uint32_t op = r * NG + gi;
+                const bool active = op < rows;
+                const uint32_t o = active ? op : 0;
+                uint32_t slot, code;
+                find_or_put<G>(t, LdsRow{tile + o * stride}, hs[o], active, slot, code, cnt);
+                if (active && (tid & (G - 1)) == 0) {
+                    res_slot[op] = slot;
+                    res_code[op] = code;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < rows) {
+            const uint32_t code = res_code[tid];
+            seen[base + tid] = code == kSeen ? 1 : (code == kNew ? 0 : 0xFF);
             if (index)
-                index[base + threadIdx.x] = slot;
+                index[base + tid] = res_slot[tid];
         }
     }
     flush_counters(t.status, cnt);
@@ -186,9 +224,17 @@ lhs_status launch_find_or_put(lhs_table *t, const uint32_t *d_states, uint64_t n
                               uint32_t *d_index, hipStream_t s) {
     if (!n)
         return LHS_OK;
-    const size_t lds = (size_t)kBlock * (t->W | 1u) * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_find_or_put, dim3(grid_for(n, kBlock)), dim3(kBlock), lds, s, view(t),
-                       d_states, n, d_seen, d_index, div_magic(t->W));
+    const size_t lds = (size_t)kBlock * ((t->W | 1u) + 2 + 2) * sizeof(uint32_t);
+    const dim3 grid(grid_for(n, kBlock)), block(kBlock);
+    const TableView v = view(t);
+    const uint32_t mw = div_magic(t->W);
+    switch (t->tps) {
+    case 1: hipLaunchKernelGGL(k_find_or_put<1>, grid, block, lds, s, v, d_states, n, d_seen, d_index, mw); break;
+    case 4: hipLaunchKernelGGL(k_find_or_put<4>, grid, block, lds, s, v, d_states, n, d_seen, d_index, mw); break;
+    case 8: hipLaunchKernelGGL(k_find_or_put<8>, grid, block, lds, s, v, d_states, n, d_seen, d_index, mw); break;
+    case 16: hipLaunchKernelGGL(k_find_or_put<16>, grid, block, lds, s, v, d_states, n, d_seen, d_index, mw); break;
+    default: return LHS_EINVAL;
+    }
     return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
 }
 
@@ -235,6 +281,7 @@ lhs_status lhs_create(uint64_t capacity, uint32_t state_words, lhs_table **out) 
     t->lines = (uint32_t)(capacity / kLineSlots);
     t->max_rounds = std::min<uint32_t>(t->lines, kMaxRounds);
     t->seed = kDefaultSeed;
+    t->tps = kDefaultTps;
     if (hipGetDevice(&t->device) != hipSuccess) {
         delete t;
         return LHS_EDEVICE;
@@ -287,6 +334,13 @@ lhs_status lhs_find_or_put(lhs_table *t, const uint32_t *d_states, uint64_t n, u
         return LHS_EINVAL;
     t->last_stream = (hipStream_t)hip_stream;
     return launch_find_or_put(t, d_states, n, d_seen, d_index, (hipStream_t)hip_stream);
+}
+
+lhs_status lhs_set_threads_per_state(lhs_table *t, uint32_t tps) {
+    if (!t || (tps != 1 && tps != 4 && tps != 8 && tps != 16))
+        return LHS_EINVAL;
+    t->tps = tps;
+    return LHS_OK;
 }
 
 lhs_status lhs_check(lhs_table *t) {
@@ -372,6 +426,7 @@ lhs_status lhs_get_info(lhs_table *t, lhs_info *out) {
     out->capacity = t->capacity;
     out->state_words = t->W;
     out->line_slots = kLineSlots;
+    out->threads_per_state = t->tps;
     out->hash_seed = t->seed;
     out->wait_hits = st.wait_hits;
     out->cas_failures = st.cas_failures;

@@ -23,7 +23,8 @@ constexpr int kBlock = 256;
 constexpr uint32_t kQueue = 512;   // LDS successor ring (2 passes of 256)
 
 // Successor of an LDS row: row with s[p] = target and, if ew != NONE,
-// s[ew] = ev (ew already offset by P).
+// s[ew] = ev (ew already offset by P).  Descriptor: x = row word offset from
+// the LDS base | p << 16 | ew << 24 (0xFF = no effect), y = target | ev << 16.
 struct SuccVec {
     const uint32_t *row;
     uint32_t p, target, ew, ev;
@@ -33,29 +34,45 @@ struct SuccVec {
         x = i == ew ? ev : x;
         return x;
     }
+    __device__ __forceinline__ static SuccVec decode(const uint32_t *smem, uint2 d) {
+        const uint32_t ew = d.x >> 24;
+        return SuccVec{smem + (d.x & 0xFFFFu), (d.x >> 16) & 0xFFu, d.y & 0xFFFFu,
+                       ew == 0xFFu ? 0xFFFFFFFFu : ew, d.y >> 16};
+    }
 };
 
-__device__ __forceinline__ uint32_t mbcnt(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+// LDS layout of k_expand (32-bit words):
+//   tile     [kBlock][W|1]  frontier states of the current tile
+//   queue    [kQueue]       enabled (state, process, transition) triples
+//   succ_cnt [kBlock]       successors per tile state (edges, deadlocks)
+//   hq       [kBlock] u64   hash of each successor of the current pass
+//   d0, d1   [kBlock]       packed successor descriptors of the pass
+__host__ __device__ constexpr uint32_t expand_lds_words(uint32_t W) {
+    return kBlock * (W | 1u) + kQueue + kBlock + 2 * kBlock + 2 * kBlock;
 }
 
-// Expand frontier[0, n_front).  Requires blockDim.x == kBlock.
+// Expand frontier[0, n_front) (one BFS level).  Requires blockDim.x == kBlock.
 // limit: the level aborts once more than `limit` new states were appended.
+template <int G>
 __global__ __launch_bounds__(kBlock) void k_expand(TableView t, ModelView m,
                                                    const uint32_t *__restrict__ front,
                                                    uint32_t n_front, uint32_t *__restrict__ next,
                                                    LevelCounters *lc, uint32_t limit) {
     extern __shared__ uint32_t smem[];
-    uint32_t *tile = smem;                              // kBlock rows, stride W|1
     const uint32_t W = m.W, stride = W | 1u;
-    uint32_t *queue = tile + kBlock * stride;           // kQueue entries
-    uint32_t *succ_cnt = queue + kQueue;                // kBlock per-state counts
+    uint32_t *tile = smem;
+    uint32_t *queue = tile + kBlock * stride;
+    uint32_t *succ_cnt = queue + kQueue;
+    uint64_t *hq = reinterpret_cast<uint64_t *>(succ_cnt + kBlock);   // 8-byte aligned
+    uint32_t *d0 = reinterpret_cast<uint32_t *>(hq + kBlock);
+    uint32_t *d1 = d0 + kBlock;
     __shared__ uint32_t s_tail, s_abort;
 
+    constexpr uint32_t NG = kBlock / G;
     LaneCounters cnt;
     unsigned long long my_edges = 0, my_dead = 0;
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, gi = tid / G;
+    const bool leader = (tid & (G - 1)) == 0;
     const uint32_t PK = m.P * m.K;
 
     for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < n_front;
@@ -68,6 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_expand(TableView t, ModelView m,
         }
         succ_cnt[tid] = 0;
         if (tid < rows) {
+            // rows of earlier levels were published by earlier launches
             const uint64_t slot = front[base + tid];
             const uint32_t *src = t.data + slot * W;
             uint32_t *dst = tile + tid * stride;
@@ -128,36 +146,53 @@ __global__ __launch_bounds__(kBlock) void k_expand(TableView t, ModelView m,
             }
             if (tail == head)
                 break;
-            // ---- one pass of find-or-put over up to kBlock successors -----
+            // ---- one pass over up to kBlock successors ---------------------
+            // (a) one lane per successor: decode and hash
             const uint32_t take = min(tail - head, (uint32_t)kBlock);
-            bool is_new = false;
-            uint32_t slot = kNoSlot;
             if (tid < take) {
                 const uint32_t e = queue[(head + tid) & (kQueue - 1)];
                 const uint32_t st = e & 0xFFu, p = (e >> 8) & 0xFFu, k = e >> 16;
                 const uint32_t *row = tile + st * stride;
                 const uint2 tr = m.trans[((uint64_t)p * m.L + row[p]) * m.K + k];
                 const uint32_t evar = tr.x >> 24;
-                const SuccVec v{row, p, tr.x & 0xFFFFu, evar == 0xFFu ? 0xFFFFFFFFu : m.P + evar,
-                                tr.y >> 16};
-                const uint64_t h = hash_vec(v, W, t.seed);
-                uint32_t code;
-                find_or_put(t, v, h, slot, code, cnt);
-                is_new = code == kNew;
+                const uint32_t ew = evar == 0xFFu ? 0xFFu : m.P + evar;
+                const SuccVec v{row, p, tr.x & 0xFFFFu, ew == 0xFFu ? 0xFFFFFFFFu : ew, tr.y >> 16};
+                hq[tid] = hash_vec(v, W, t.seed);
+                d0[tid] = (st * stride) | (p << 16) | (ew << 24);
+                d1[tid] = (tr.x & 0xFFFFu) | ((tr.y >> 16) << 16);
             }
-            // ---- frontier compaction: ballot + prefix + one atomic per wave
-            const uint64_t nm = __ballot(is_new);
-            if (nm) {
-                uint32_t wbase = 0;
-                const uint32_t wn = (uint32_t)__popcll(nm);
-                if (__lane_id() == 0) {
-                    wbase = atomicAdd(&lc->n_next, wn);
-                    if ((uint64_t)wbase + wn > limit)
-                        __hip_atomic_store(&lc->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            // (b) find-or-put of every successor (G == 1: one lane each with
+            //     wavefront-cooperative memory accesses; G > 1: one group of
+            //     G lanes each), then ballot/prefix compaction of the new ones
+            //     into next[]
+            for (uint32_t r = 0; r < G; ++r) {
+                const uint32_t q = r * NG + gi;
+                const bool active = q < take;
+                const uint32_t o = active ? q : 0;
+                const uint2 dsc = make_uint2(d0[o], d1[o]);
+                uint32_t slot, code;
+                if constexpr (G == 1) {
+                    __shared__ WaveScratch ws[kBlock / 64];
+                    find_or_put_wave<SuccVec>(t, &ws[tid / 64], smem, dsc, hq[o], active, slot, code,
+                                              cnt);
+                } else {
+                    find_or_put<G>(t, SuccVec::decode(smem, dsc), hq[o], active, slot, code, cnt);
                 }
-                wbase = __shfl(wbase, 0, 64);
-                if (is_new)
-                    next[wbase + mbcnt(nm)] = slot;
+                const bool is_new = active && leader && code == kNew;
+                const uint64_t nm = __ballot(is_new);
+                if (nm) {
+                    uint32_t wbase = 0;
+                    const uint32_t wn = (uint32_t)__popcll(nm);
+                    if (__lane_id() == 0) {
+                        wbase = atomicAdd(&lc->n_next, wn);
+                        if ((uint64_t)wbase + wn > limit)
+                            __hip_atomic_store(&lc->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    wbase = __shfl(wbase, 0, 64);
+                    if (is_new)
+                        next[wbase + mbcnt(nm)] = slot;
+                }
             }
             head += take;
             __syncthreads();
@@ -253,7 +288,23 @@ ModelView model_view(const reach_model *m, const uint2 *d_trans) {
 }
 
 size_t expand_lds_bytes(uint32_t W) {
-    return ((size_t)kBlock * (W | 1u) + kQueue + kBlock) * sizeof(uint32_t);
+    return (size_t)expand_lds_words(W) * sizeof(uint32_t);
+}
+
+lhs_status launch_expand(lhs_table *t, const TableView &tv, const ModelView &mv, const uint32_t *front,
+                         uint32_t n_front, uint32_t *next, LevelCounters *lc, uint32_t limit,
+                         hipStream_t s) {
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((n_front + kBlock - 1) / kBlock, 1u << 16);
+    const size_t lds = expand_lds_bytes(mv.W);
+    const dim3 grid(std::max(blocks, 1u)), block(kBlock);
+    switch (t->tps) {
+    case 1: hipLaunchKernelGGL(k_expand<1>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit); break;
+    case 4: hipLaunchKernelGGL(k_expand<4>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit); break;
+    case 8: hipLaunchKernelGGL(k_expand<8>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit); break;
+    case 16: hipLaunchKernelGGL(k_expand<16>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit); break;
+    default: return LHS_EINVAL;
+    }
+    return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
 }
 
 lhs_status ensure_bfs_buffers(lhs_table *t) {
@@ -300,16 +351,14 @@ lhs_status explore_host_loop(lhs_table *t, const reach_model *m, const uint2 *d_
     uint64_t total = 1, edges = 0, dead = 0;
     uint32_t n_cur = 1, cur = 0;
     int capped = 0;
-    const size_t lds = expand_lds_bytes(mv.W);
     while (true) {
         uint32_t limit = 0xFFFFFFFFu;
         if (m->state_cap)
             limit = (uint32_t)std::min<uint64_t>(m->state_cap - total, 0xFFFFFFFFull);
         hipLaunchKernelGGL(k_zero_level, dim3(1), dim3(1), 0, s, t->level);
-        const uint32_t blocks = (uint32_t)std::min<uint64_t>((n_cur + kBlock - 1) / kBlock, 1u << 16);
-        hipLaunchKernelGGL(k_expand, dim3(blocks), dim3(kBlock), lds, s, tv, mv, t->frontier[cur],
-                           n_cur, t->frontier[cur ^ 1], t->level, limit);
-        LHS_HIP(hipGetLastError());
+        rc = launch_expand(t, tv, mv, t->frontier[cur], n_cur, t->frontier[cur ^ 1], t->level, limit, s);
+        if (rc != LHS_OK)
+            return rc;
         LHS_HIP(hipMemcpyAsync(t->level_host, t->level, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
         LHS_HIP(hipStreamSynchronize(s));
         DevStatus st;

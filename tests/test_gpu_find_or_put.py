@@ -33,14 +33,19 @@ def _run_stream(lhs, table, stream, batch):
     return seen.cpu().numpy(), idx.cpu().numpy().view(np.uint32), bounds
 
 
+TPS = [1, 4, 8, 16]
+
+
+@pytest.mark.parametrize("tps", TPS)
 @pytest.mark.parametrize("W", [1, 2, 3, 4, 5, 8, 16, 17, 31, 32])
 @pytest.mark.parametrize("batch", [257, 1000, 1 << 30])
-def test_stream_parity(lhs, W, batch):
-    print(f"\n[fop] W={W} batch={batch}", flush=True)
+def test_stream_parity(lhs, W, batch, tps):
+    print(f"\n[fop] W={W} batch={batch} tps={tps}", flush=True)
     rows, order = gen.dup_stream(100 + W, 3000, W, 3)
     stream = gen.gather(rows, order)
     o_seen, o_id, distinct = oracle.stream(stream)
     with lhs.Table(1 << 14, W) as t:
+        t.set_threads_per_state(tps)
         seen, idx, bounds = _run_stream(lhs, t, stream, batch)
         check_stream_batches(o_id, distinct, seen, idx, bounds)
         assert t.count() == distinct
@@ -49,22 +54,26 @@ def test_stream_parity(lhs, W, batch):
         oracle.digest(got) == oracle.digest(np.unique(stream, axis=0))
 
 
-def test_small_alphabet_many_collisions(lhs):
+@pytest.mark.parametrize("tps", TPS)
+def test_small_alphabet_many_collisions(lhs, tps):
     # W=2 vectors over a 40x40 grid: heavy in-batch duplication
-    print("\n[fop] small alphabet", flush=True)
+    print(f"\n[fop] small alphabet tps={tps}", flush=True)
     rng = np.random.default_rng(5)
     stream = rng.integers(0, 40, size=(200_000, 2)).astype(np.uint32)
     o_seen, o_id, distinct = oracle.stream(stream)
     with lhs.Table(1 << 12, 2) as t:
+        t.set_threads_per_state(tps)
         seen, idx, bounds = _run_stream(lhs, t, stream, 50_000)
         check_stream_batches(o_id, distinct, seen, idx, bounds)
         check_table_invariants(t)
 
 
-def test_one_vector_many_copies(lhs):
-    print("\n[fop] 2^20 copies of one vector", flush=True)
+@pytest.mark.parametrize("tps", TPS)
+def test_one_vector_many_copies(lhs, tps):
+    print(f"\n[fop] 2^20 copies of one vector tps={tps}", flush=True)
     stream = np.tile(np.arange(16, dtype=np.uint32), (1 << 20, 1))
     with lhs.Table(1 << 16, 16) as t:
+        t.set_threads_per_state(tps)
         seen, idx, bounds = _run_stream(lhs, t, stream, 1 << 20)
         assert int((seen == 0).sum()) == 1 and int((seen == 1).sum()) == (1 << 20) - 1
         assert len(np.unique(idx)) == 1
@@ -72,10 +81,12 @@ def test_one_vector_many_copies(lhs):
         print("wait_hits", t.info()["wait_hits"], "cas_failures", t.info()["cas_failures"])
 
 
-def test_full_table_and_clear(lhs):
-    print("\n[fop] capacity-16 table", flush=True)
+@pytest.mark.parametrize("tps", TPS)
+def test_full_table_and_clear(lhs, tps):
+    print(f"\n[fop] capacity-16 table tps={tps}", flush=True)
     rows = gen.words(77, 17 * 4).reshape(17, 4)
     with lhs.Table(16, 4) as t:
+        t.set_threads_per_state(tps)
         seen, idx, _ = _run_stream(lhs, t, rows[:16], 1 << 30)
         assert np.all(seen == 0) and sorted(idx.tolist()) == list(range(16))
         seen, idx, _ = _run_stream(lhs, t, rows[:16], 1 << 30)     # all present now
@@ -93,17 +104,26 @@ def test_full_table_and_clear(lhs):
         assert t.count() == 0
 
 
-def test_high_fill(lhs):
+@pytest.mark.parametrize("tps", TPS)
+def test_high_fill(lhs, tps):
     # 4000 distinct vectors in 4096 slots (97.7 % fill), then every one again
-    print("\n[fop] high fill", flush=True)
+    print(f"\n[fop] high fill tps={tps}", flush=True)
     rows = np.unique(gen.words(9, 4100 * 8).reshape(4100, 8), axis=0)[:4000]
     with lhs.Table(1 << 12, 8) as t:
+        t.set_threads_per_state(tps)
         seen, idx, _ = _run_stream(lhs, t, rows, 1 << 30)
         assert np.all(seen == 0)
         seen2, idx2, _ = _run_stream(lhs, t, rows, 1000)
         assert np.all(seen2 == 1) and np.array_equal(idx, idx2)
         assert t.count() == 4000
         check_table_invariants(t)
+
+
+def test_bad_threads_per_state(lhs):
+    with lhs.Table(1 << 10, 4) as t:
+        for bad in (0, 2, 3, 32):
+            with pytest.raises(lhs.LhsError):
+                t.set_threads_per_state(bad)
 
 
 def test_empty_batch(lhs):

@@ -26,21 +26,22 @@ def _capacity_for(states):
     return 1 << max(10, (2 * states + (1 << 16)).bit_length())
 
 
-def _gpu(lhs, m, cap=None, capacity=None):
+def _gpu(lhs, m, cap=None, capacity=None, tps=8):
     cap = m.cap if cap is None else cap
     if capacity is None:
         capacity = _capacity_for(cap if cap else 1 << 20)
     with lhs.Table(capacity, m.W) as t:
+        t.set_threads_per_state(tps)
         r = lhs.reach_explore(m, cap=cap, table=t)
         rows, _ = check_table_invariants(t)
     return r, rows
 
 
-def _compare(lhs, m, cap=None, capacity=None):
+def _compare(lhs, m, cap=None, capacity=None, tps=8):
     want = oracle.reach(m, cap=cap)
     if capacity is None:
         capacity = _capacity_for(max(want.total, cap or 0))
-    got, rows = _gpu(lhs, m, cap, capacity)
+    got, rows = _gpu(lhs, m, cap, capacity, tps)
     assert result_fields(got) == result_fields(want), m.describe()
     assert oracle.digest(rows) == want.digest
     return got
@@ -77,20 +78,22 @@ def _random_models(n, seed):
 
 def test_random_models(lhs):
     rng = np.random.default_rng(11)
-    for m in _random_models(40, 3):
-        print(f"\n[reach] {m.describe()}", flush=True)
+    for i, m in enumerate(_random_models(40, 3)):
+        tps = (1, 4, 8, 16)[i % 4]
+        print(f"\n[reach] {m.describe()} tps={tps}", flush=True)
         full = oracle.reach(m, cap=200_001)
         cap = 0 if not full.capped else 200_000
-        _compare(lhs, m, cap=cap)
+        _compare(lhs, m, cap=cap, tps=tps)
         if full.total > 10:
-            _compare(lhs, m, cap=int(rng.integers(1, full.total)))
+            _compare(lhs, m, cap=int(rng.integers(1, full.total)), tps=tps)
 
 
+@pytest.mark.parametrize("tps", [1, 4, 8, 16])
 @pytest.mark.parametrize("cap", [1 << 12, 1 << 16, 1 << 19])
-def test_big_model_capped(lhs, cap):
-    print(f"\n[reach] big model cap={cap}", flush=True)
+def test_big_model_capped(lhs, cap, tps):
+    print(f"\n[reach] big model cap={cap} tps={tps}", flush=True)
     m = gen.big_model(cap=cap)
-    got = _compare(lhs, m)
+    got = _compare(lhs, m, tps=tps)
     assert got.capped
 
 
