@@ -184,7 +184,7 @@ def main():
             ms = time_fop(tps)
             sweep[str(tps)] = {"fop_ms": round(ms, 3), "fop_Gops": round(n / ms / 1e6, 3)}
             log(f"tps={tps}: find-or-put {ms:.3f} ms")
-        table.set_threads_per_state(info["threads_per_state"])
+        table.set_threads_per_state(0)
 
     ops_per_s = n / (ms_per_step / 1e3)
     bpo = fop_bytes_per_op(W)
@@ -285,7 +285,7 @@ def main():
                 r = lhs.reach_explore(m, table=table)
                 sweep[str(tps)]["bfs_ms"] = round(r.gpu_ms, 2)
                 log(f"tps={tps}: bfs {r.gpu_ms:.1f} ms")
-            table.set_threads_per_state(info["threads_per_state"])
+            table.set_threads_per_state(0)
         out["bfs"] = bfs
     if sweep:
         out["tps_sweep"] = sweep

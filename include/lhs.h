@@ -90,10 +90,13 @@ lhs_status lhs_clear(lhs_table *t, void *hip_stream);
 lhs_status lhs_find_or_put(lhs_table *t, const uint32_t *d_states, uint64_t n,
                            uint8_t *d_seen, uint32_t *d_index, void *hip_stream);
 
-/* Number of GPU lanes that cooperate on one find-or-put: 1, 4, 8 or 16 (a
- * group of G lanes loads a 128-byte slot line as one coalesced access, 16/G
- * slots per lane).  Affects speed only; results are identical for every
- * value.  Applies to later calls on the table (find-or-put and BFS). */
+/* Number of GPU lanes that cooperate on one find-or-put: 1, 4, 8 or 16, or
+ * 0 for each kernel's default (4 for lhs_find_or_put, 1 for the BFS).  G > 1:
+ * a group of G lanes runs one operation and loads its 128-byte slot line as
+ * one coalesced access (16/G slots per lane).  G = 1: every lane runs its own
+ * operation while the wavefront moves lines and rows cooperatively (eight
+ * lanes per line or row).  Affects speed only; results are identical for
+ * every value.  Applies to later calls on the table (find-or-put and BFS). */
 lhs_status lhs_set_threads_per_state(lhs_table *t, uint32_t tps);
 
 /* Wait for the last stream used with the table, then return its sticky
@@ -127,7 +130,7 @@ typedef struct lhs_info {
                               paper's write-busy "lock" hits)                */
     uint64_t cas_failures; /* lost claims of an empty slot                   */
     uint32_t error;        /* sticky lhs_status of device failures           */
-    uint32_t threads_per_state; /* lanes cooperating on one operation        */
+    uint32_t threads_per_state; /* lhs_set_threads_per_state value (0 = defaults) */
 } lhs_info;
 
 /* Table geometry and device counters (synchronises the last stream). */

@@ -22,7 +22,6 @@ constexpr uint32_t kMaxGrid = 1u << 19;
 // A find-or-put gives up with EFULL after probing this many lines (or every
 // line of a smaller table).
 constexpr uint32_t kMaxRounds = 1u << 16;
-constexpr uint32_t kDefaultTps = 8;
 
 // A vector staged in LDS (row of W words); descriptor x = word offset of
 // the row from the LDS base.
@@ -228,7 +227,7 @@ lhs_status launch_find_or_put(lhs_table *t, const uint32_t *d_states, uint64_t n
     const dim3 grid(grid_for(n, kBlock)), block(kBlock);
     const TableView v = view(t);
     const uint32_t mw = div_magic(t->W);
-    switch (t->tps) {
+    switch (tps_find_or_put(t)) {
     case 1: hipLaunchKernelGGL(k_find_or_put<1>, grid, block, lds, s, v, d_states, n, d_seen, d_index, mw); break;
     case 4: hipLaunchKernelGGL(k_find_or_put<4>, grid, block, lds, s, v, d_states, n, d_seen, d_index, mw); break;
     case 8: hipLaunchKernelGGL(k_find_or_put<8>, grid, block, lds, s, v, d_states, n, d_seen, d_index, mw); break;
@@ -281,7 +280,6 @@ lhs_status lhs_create(uint64_t capacity, uint32_t state_words, lhs_table **out) 
     t->lines = (uint32_t)(capacity / kLineSlots);
     t->max_rounds = std::min<uint32_t>(t->lines, kMaxRounds);
     t->seed = kDefaultSeed;
-    t->tps = kDefaultTps;
     if (hipGetDevice(&t->device) != hipSuccess) {
         delete t;
         return LHS_EDEVICE;
@@ -337,7 +335,7 @@ lhs_status lhs_find_or_put(lhs_table *t, const uint32_t *d_states, uint64_t n, u
 }
 
 lhs_status lhs_set_threads_per_state(lhs_table *t, uint32_t tps) {
-    if (!t || (tps != 1 && tps != 4 && tps != 8 && tps != 16))
+    if (!t || (tps != 0 && tps != 1 && tps != 4 && tps != 8 && tps != 16))
         return LHS_EINVAL;
     t->tps = tps;
     return LHS_OK;
@@ -426,7 +424,7 @@ lhs_status lhs_get_info(lhs_table *t, lhs_info *out) {
     out->capacity = t->capacity;
     out->state_words = t->W;
     out->line_slots = kLineSlots;
-    out->threads_per_state = t->tps;
+    out->threads_per_state = t->tps;   // 0 = per-kernel defaults
     out->hash_seed = t->seed;
     out->wait_hits = st.wait_hits;
     out->cas_failures = st.cas_failures;

@@ -297,7 +297,7 @@ lhs_status launch_expand(lhs_table *t, const TableView &tv, const ModelView &mv,
     const uint32_t blocks = (uint32_t)std::min<uint64_t>((n_front + kBlock - 1) / kBlock, 1u << 16);
     const size_t lds = expand_lds_bytes(mv.W);
     const dim3 grid(std::max(blocks, 1u)), block(kBlock);
-    switch (t->tps) {
+    switch (tps_expand(t)) {
     case 1: hipLaunchKernelGGL(k_expand<1>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit); break;
     case 4: hipLaunchKernelGGL(k_expand<4>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit); break;
     case 8: hipLaunchKernelGGL(k_expand<8>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit); break;

@@ -26,22 +26,38 @@ def _short(name: str) -> str:
 
 
 def kernel_stats(db: str):
+    """Per kernel: calls, total/avg/min/max duration, and the average over the
+    dispatches with the kernel's largest grid (separates e.g. the 2^26-row
+    find-or-put launches from one-row inserts of the same kernel)."""
     con = sqlite3.connect(db)
     rows = con.execute("select name, count(*), sum(duration), avg(duration), min(duration), "
-                       "max(duration) from kernels group by name order by sum(duration) desc").fetchall()
+                       "max(duration), max(grid_x) from kernels group by name "
+                       "order by sum(duration) desc").fetchall()
     total = sum(r[2] for r in rows) or 1
-    return [dict(kernel=_short(r[0]), calls=r[1], total_ms=r[2] / 1e6, avg_ms=r[3] / 1e6,
-                 min_ms=r[4] / 1e6, max_ms=r[5] / 1e6, pct=100.0 * r[2] / total) for r in rows]
+    out = []
+    for r in rows:
+        big = con.execute("select count(*), avg(duration) from kernels where name = ? and grid_x = ?",
+                          (r[0], r[6])).fetchone()
+        out.append(dict(kernel=_short(r[0]), calls=r[1], total_ms=r[2] / 1e6, avg_ms=r[3] / 1e6,
+                        min_ms=r[4] / 1e6, max_ms=r[5] / 1e6, pct=100.0 * r[2] / total,
+                        big_grid=r[6], big_calls=big[0], big_avg_ms=big[1] / 1e6))
+    return out
 
 
 def counter_per_dispatch(db: str, counter: str):
-    """{short kernel name: [value per dispatch, ...]}"""
+    """{short kernel name: [(grid size, value) per dispatch, ...]}"""
     con = sqlite3.connect(db)
     out = {}
-    for name, val in con.execute("select kernel_name, value from counters_collection "
-                                 "where counter_name = ? order by dispatch_id", (counter,)):
-        out.setdefault(_short(name), []).append(val)
+    for name, grid, val in con.execute("select kernel_name, grid_size, value from counters_collection "
+                                       "where counter_name = ? order by dispatch_id", (counter,)):
+        out.setdefault(_short(name), []).append((grid, val))
     return out
+
+
+def largest_dispatch(rows):
+    """Counter value of the dispatch with the largest grid (the last such)."""
+    g = max(r[0] for r in rows)
+    return [r[1] for r in rows if r[0] == g][-1]
 
 
 def sources_sha(paths):
@@ -73,10 +89,12 @@ def main(argv=None):
     if a.mode == "stats":
         if a.cmd:
             print(f"# command: {a.cmd}")
-        print(f"{'kernel':60s} {'calls':>6s} {'total_ms':>10s} {'avg_ms':>9s} {'min_ms':>9s} {'max_ms':>9s} {'%':>6s}")
+        print(f"{'kernel':44s} {'calls':>6s} {'total_ms':>10s} {'avg_ms':>9s} {'min_ms':>9s} "
+              f"{'max_ms':>9s} {'%':>6s}  {'largest-grid calls':>18s} {'avg_ms':>9s}")
         for r in kernel_stats(a.db):
-            print(f"{r['kernel'][:60]:60s} {r['calls']:6d} {r['total_ms']:10.3f} {r['avg_ms']:9.4f} "
-                  f"{r['min_ms']:9.4f} {r['max_ms']:9.4f} {r['pct']:6.2f}")
+            print(f"{r['kernel'][:44]:44s} {r['calls']:6d} {r['total_ms']:10.3f} {r['avg_ms']:9.4f} "
+                  f"{r['min_ms']:9.4f} {r['max_ms']:9.4f} {r['pct']:6.2f}  {r['big_calls']:18d} "
+                  f"{r['big_avg_ms']:9.4f}")
         return
 
     fetch = counter_per_dispatch(a.fetch_db, "FETCH_SIZE")
@@ -85,12 +103,13 @@ def main(argv=None):
     copy_w = write.get("k_probe_copy")
     if not copy_f or not copy_w:
         sys.exit("copy probe missing from the counter runs (run bench.py with --calib-copy)")
-    f_fetch = a.copy_bytes / (copy_f[-1] * 1024.0)
-    f_write = a.copy_bytes / (copy_w[-1] * 1024.0)
-    kf = fetch[a.kernel][-1]
-    kw = write[a.kernel][-1]
+    cf, cw = largest_dispatch(copy_f), largest_dispatch(copy_w)
+    f_fetch = a.copy_bytes / (cf * 1024.0)
+    f_write = a.copy_bytes / (cw * 1024.0)
+    kf = largest_dispatch(fetch[a.kernel])
+    kw = largest_dispatch(write[a.kernel])
     res = dict(kernel=a.kernel, ops_per_launch=a.ops, fetch_kib=kf, write_kib=kw,
-               copy_bytes=a.copy_bytes, copy_fetch_kib=copy_f[-1], copy_write_kib=copy_w[-1],
+               copy_bytes=a.copy_bytes, copy_fetch_kib=cf, copy_write_kib=cw,
                fetch_scale=f_fetch, write_scale=f_write,
                fetch_bytes=kf * 1024.0 * f_fetch, write_bytes=kw * 1024.0 * f_write,
                source_sha=sources_sha(a.sources.split(",")), command=a.cmd, summary=a.summary)

@@ -33,7 +33,7 @@ def _run_stream(lhs, table, stream, batch):
     return seen.cpu().numpy(), idx.cpu().numpy().view(np.uint32), bounds
 
 
-TPS = [1, 4, 8, 16]
+TPS = [0, 1, 4, 8, 16]
 
 
 @pytest.mark.parametrize("tps", TPS)
@@ -121,7 +121,7 @@ def test_high_fill(lhs, tps):
 
 def test_bad_threads_per_state(lhs):
     with lhs.Table(1 << 10, 4) as t:
-        for bad in (0, 2, 3, 32):
+        for bad in (2, 3, 32):
             with pytest.raises(lhs.LhsError):
                 t.set_threads_per_state(bad)
 

@@ -1,0 +1,79 @@
+"""Full-size workloads on the GPU against the CPU oracle.
+
+* the 12-process x 16-local model, BFS capped at 2^27 states, in a 2^28-slot
+  table: per-level counts, edges and deadlocks against the oracle's recorded
+  run (tests/golden/big_model.json, written by tests/golden/make_golden.py
+  with the oracle only), and the stored set against the oracle's set digest;
+  slot invariants on a sample of stored rows.
+* the raw stream: 2^26 rows of 16 words (2^25 distinct, each twice) into a
+  2^28-slot table, as one call and as 2^22-row calls, against the sequential
+  oracle run on the same stream.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+from conftest import GOLDEN
+from gpu_util import check_stream_batches, check_table_invariants, dev_u32
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lhs():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1004_2772_amd
+    return paper_1004_2772_amd
+
+
+@pytest.mark.parametrize("tps", [0, 4])
+def test_big_model_2p27(lhs, tps):
+    print(f"\n[full] big model, cap 2^27, tps={tps}", flush=True)
+    with open(os.path.join(GOLDEN, "big_model.json")) as f:
+        g = json.load(f)
+    m = gen.big_model()
+    assert m.cap == g["cap"] == 1 << 27
+    with lhs.Table(gen.BIG_TABLE_SLOTS, m.W) as t:
+        t.set_threads_per_state(tps)
+        r = lhs.reach_explore(m, table=t)
+        print(f"gpu {r.gpu_ms:.1f} ms, {r.total} states", flush=True)
+        assert (r.total, r.n_levels, r.level_counts, r.edges, r.deadlocks, r.capped) == \
+            (g["total"], g["n_levels"], g["level_counts"], g["edges"], g["deadlocks"], g["capped"])
+        rows, _ = check_table_invariants(t, sample=200_000)
+    d = oracle.digest(rows)
+    assert [d[0], hex(d[1]), hex(d[2])] == g["digest"]
+
+
+@pytest.fixture(scope="module")
+def full_stream():
+    rows, order = gen.stream_workload()
+    stream = gen.gather(rows, order)
+    del rows
+    seen, ids, distinct = oracle.stream(stream)
+    return stream, ids, distinct
+
+
+@pytest.mark.parametrize("batch", [1 << 26, 1 << 22])
+def test_stream_2p26(lhs, full_stream, batch):
+    import torch
+    stream, o_id, distinct = full_stream
+    print(f"\n[full] stream 2^26, batch {batch}", flush=True)
+    n = len(stream)
+    dev = dev_u32(stream)
+    seen = torch.empty(n, dtype=torch.uint8, device="cuda")
+    idx = torch.empty(n, dtype=torch.int32, device="cuda")
+    bounds = []
+    with lhs.Table(gen.STREAM_TABLE_SLOTS, gen.STREAM_W) as t:
+        for lo in range(0, n, batch):
+            hi = min(n, lo + batch)
+            t.find_or_put(dev[lo:hi], seen[lo:hi], idx[lo:hi])
+            bounds.append((lo, hi))
+        t.check()
+        assert t.count() == distinct
+    check_stream_batches(o_id, distinct, seen.cpu().numpy(), idx.cpu().numpy().view(np.uint32), bounds)

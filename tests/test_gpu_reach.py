@@ -26,7 +26,7 @@ def _capacity_for(states):
     return 1 << max(10, (2 * states + (1 << 16)).bit_length())
 
 
-def _gpu(lhs, m, cap=None, capacity=None, tps=8):
+def _gpu(lhs, m, cap=None, capacity=None, tps=0):
     cap = m.cap if cap is None else cap
     if capacity is None:
         capacity = _capacity_for(cap if cap else 1 << 20)
@@ -37,7 +37,7 @@ def _gpu(lhs, m, cap=None, capacity=None, tps=8):
     return r, rows
 
 
-def _compare(lhs, m, cap=None, capacity=None, tps=8):
+def _compare(lhs, m, cap=None, capacity=None, tps=0):
     want = oracle.reach(m, cap=cap)
     if capacity is None:
         capacity = _capacity_for(max(want.total, cap or 0))
@@ -79,7 +79,7 @@ def _random_models(n, seed):
 def test_random_models(lhs):
     rng = np.random.default_rng(11)
     for i, m in enumerate(_random_models(40, 3)):
-        tps = (1, 4, 8, 16)[i % 4]
+        tps = (0, 1, 4, 8, 16)[i % 5]
         print(f"\n[reach] {m.describe()} tps={tps}", flush=True)
         full = oracle.reach(m, cap=200_001)
         cap = 0 if not full.capped else 200_000
@@ -88,7 +88,7 @@ def test_random_models(lhs):
             _compare(lhs, m, cap=int(rng.integers(1, full.total)), tps=tps)
 
 
-@pytest.mark.parametrize("tps", [1, 4, 8, 16])
+@pytest.mark.parametrize("tps", [0, 1, 4, 8, 16])
 @pytest.mark.parametrize("cap", [1 << 12, 1 << 16, 1 << 19])
 def test_big_model_capped(lhs, cap, tps):
     print(f"\n[reach] big model cap={cap} tps={tps}", flush=True)
