@@ -17,6 +17,9 @@ Extra legs in the same JSON line:
                  8-lane cooperative) and random 64-bit CAS throughput.
   bfs          : level-synchronous BFS of the 12-process x 16-local synthetic
                  model capped at 2^27 states (states/s, edges/s).
+  batch        : the 64-model mix (2-16 processes, widths 4-32, 10^3-10^6
+                 states each) explored in one persistent launch, in one launch
+                 per step, and one model at a time, on the same tables.
   cpu_baseline : the CPU oracle (sequential find-or-put) timed on a bounded
                  prefix of the same stream, one host thread.
 
@@ -80,6 +83,7 @@ def main():
     ap.add_argument("--no-bfs", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-probes", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="also run the copy probe (counter calibration)")
     ap.add_argument("--bfs-cap", type=int, default=1 << 27)
     ap.add_argument("--cpu-sample", type=int, default=1 << 25)
@@ -292,6 +296,43 @@ def main():
 
     table.close()
     del states_d, seen_d, idx_d
+
+    if not args.no_batch:
+        models = gen.batch_models()
+        tables = [lhs.Table(1 << 21, m.W) for m in models]
+        n_states = None
+
+        def run_batch(flags):
+            w0 = time.time()
+            rs = lhs.reach_explore_batch(models, tables=tables, flags=flags)
+            return rs, (time.time() - w0) * 1e3
+
+        def run_alone():
+            w0 = time.time()
+            rs = [lhs.reach_explore(m, table=t) for m, t in zip(models, tables)]
+            return rs, (time.time() - w0) * 1e3
+
+        batch = {}
+        for name, fn in (("persistent", lambda: run_batch(0)), ("host_loop", lambda: run_batch(1)),
+                         ("one_at_a_time", run_alone)):
+            fn()
+            times = []
+            for _ in range(3):
+                rs, wall = fn()
+                times.append(wall)
+            n_states = sum(r.total for r in rs)
+            ms = sorted(times)[1]
+            batch[name] = {"wall_ms": round(ms, 2), "states_per_s": round(n_states / (ms / 1e3), 1)}
+            if name != "one_at_a_time":
+                batch[name]["gpu_ms"] = round(rs[0].gpu_ms, 2)
+            log(f"batch {name}: {ms:.1f} ms")
+        for t in tables:
+            t.close()
+        batch["workload"] = "64-model mix (gen/manifests/batch_models.json), tables of 2^21 slots"
+        batch["states"] = n_states
+        batch["speedup_persistent_vs_one_at_a_time"] = round(
+            batch["one_at_a_time"]["wall_ms"] / batch["persistent"]["wall_ms"], 2)
+        out["batch"] = batch
 
     if not args.no_cpu:
         import oracle

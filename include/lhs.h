@@ -189,7 +189,9 @@ typedef struct reach_opts {
 } reach_opts;
 
 #define REACH_F_NONE 0u
-#define REACH_F_HOST_LOOP 1u   /* one launch per level, host reads counters    */
+#define REACH_F_HOST_LOOP 1u   /* batch: one launch per level step, the host
+                                  reads the counters after each (default: one
+                                  persistent launch for all levels)           */
 
 typedef struct reach_result {
     uint64_t total_states;  /* |kept levels|                                   */
@@ -208,6 +210,27 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
 
 /* Free what reach_explore / reach_explore_batch allocated in r. */
 void reach_result_free(reach_result *r);
+
+/* Explore n models (1..1024) together: every model has its own table region
+ * (slots, rows, frontiers) and results identical to reach_explore on it
+ * alone; all models advance one BFS level per step and the expansion of a
+ * step covers every unfinished model, so models of different sizes and
+ * widths share the GPU.  By default the whole exploration is one
+ * cooperative (persistent) launch whose workgroups meet at grid barriers
+ * between expansion and per-model level finalisation; REACH_F_HOST_LOOP
+ * uses one launch per step instead.
+ *   models  : n host pointers to models (same rules as reach_explore).
+ *   o       : capacity = slots per model table (0: pow2 >= 2*state_cap +
+ *             2^16 for capped models, 2^21 otherwise); max_levels (0 =
+ *             65536); flags; hip_stream.  o->table is ignored.
+ *   tables  : optional, n caller tables (NULL entries = internal); a given
+ *             table must match the model's width, is cleared first and keeps
+ *             the model's reachable set.
+ *   results : n results, filled on LHS_OK (free each with reach_result_free);
+ *             gpu_ms is the time of the whole batch.
+ * Synchronous. */
+lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, const reach_opts *o,
+                               lhs_table *const *tables, reach_result *results);
 
 /* ------------------------------------------------------------------------
  * Measurement probes (ceilings for the roofline of find-or-put).

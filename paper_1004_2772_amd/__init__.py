@@ -28,7 +28,7 @@ REACH_F_HOST_LOOP = 1
 EXPORTS = ["lhs_strerror", "lhs_create", "lhs_destroy", "lhs_clear", "lhs_find_or_put",
            "lhs_set_threads_per_state",
            "lhs_check", "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info",
-           "reach_explore", "reach_result_free",
+           "reach_explore", "reach_result_free", "reach_explore_batch",
            "lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_copy"]
 
 
@@ -92,6 +92,9 @@ def lib() -> ctypes.CDLL:
         L.reach_explore.argtypes = [ctypes.POINTER(ReachModel), ctypes.POINTER(ReachOpts),
                                     ctypes.POINTER(ReachResultC)]
         L.reach_result_free.argtypes = [ctypes.POINTER(ReachResultC)]
+        L.reach_explore_batch.argtypes = [ctypes.POINTER(ctypes.POINTER(ReachModel)), u32,
+                                          ctypes.POINTER(ReachOpts), ctypes.POINTER(p),
+                                          ctypes.POINTER(ReachResultC)]
         L.reach_result_free.restype = None
         L.lhs_probe_random_lines.argtypes = [p, u64, u32, u64, u64, p, p]
         L.lhs_probe_random_cas.argtypes = [p, u64, u64, u64, p, p]
@@ -99,7 +102,8 @@ def lib() -> ctypes.CDLL:
         for name in ("lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_copy",
                      "lhs_create", "lhs_destroy", "lhs_clear", "lhs_find_or_put", "lhs_check",
                      "lhs_set_threads_per_state",
-                     "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info", "reach_explore"):
+                     "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info", "reach_explore",
+                     "reach_explore_batch"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -227,6 +231,41 @@ def _model_struct(model, cap):
     m = ReachModel(model.P, model.L, model.S, model.K, trans.ctypes.data, init.ctypes.data,
                    model.cap if cap is None else cap)
     return m, (trans, init)
+
+
+def _result(r: ReachResultC) -> ReachResult:
+    levels = [int(r.level_counts[i]) for i in range(r.n_levels)]
+    return ReachResult(total=r.total_states, n_levels=r.n_levels, level_counts=levels,
+                       edges=r.edges, deadlocks=r.deadlocks, capped=bool(r.capped),
+                       wait_hits=r.wait_hits, gpu_ms=r.gpu_ms)
+
+
+def reach_explore_batch(models, capacity: int = 0, tables=None, stream=None, max_levels: int = 0,
+                        flags: int = 0, caps=None) -> list:
+    """Explore several models together on the GPU (synchronous).  ``tables``:
+    optional list of Table (or None) per model; ``caps``: optional per-model
+    state caps overriding model.cap."""
+    n = len(models)
+    structs, keep = [], []
+    for i, m in enumerate(models):
+        st, k = _model_struct(m, None if caps is None else caps[i])
+        structs.append(st)
+        keep.append(k)
+    arr = (ctypes.POINTER(ReachModel) * n)(*[ctypes.pointer(x) for x in structs])
+    tabs = None
+    if tables is not None:
+        tabs = (ctypes.c_void_p * n)(*[(t.handle.value if t is not None else None) for t in tables])
+    o = ReachOpts(capacity, max_levels, flags, None, _stream_handle(stream))
+    res = (ReachResultC * n)()
+    _check(lib().reach_explore_batch(arr, n, ctypes.byref(o),
+                                     ctypes.cast(tabs, ctypes.POINTER(ctypes.c_void_p)) if tabs else None,
+                                     res), "reach_explore_batch")
+    try:
+        return [_result(res[i]) for i in range(n)]
+    finally:
+        for i in range(n):
+            lib().reach_result_free(ctypes.byref(res[i]))
+        del keep, structs
 
 
 def reach_explore(model, cap: int | None = None, capacity: int = 0, table: Table | None = None,

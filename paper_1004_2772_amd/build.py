@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblhs.so")
-SOURCES = ["lhs_table.hip", "reach.hip", "probes.hip"]
+SOURCES = ["lhs_table.hip", "reach.hip", "batch.hip", "probes.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
