@@ -5,11 +5,12 @@
 // step expands the tiles of every unfinished model in the same launch, so
 // small and large models, and models of different state widths, share the
 // GPU.  Two drivers:
-//   * persistent (default): one cooperative launch runs every step of every
-//     model; workgroups meet at grid barriers between the expansion and the
-//     per-model finalisation of a level;
-//   * host loop (REACH_F_HOST_LOOP): one launch per step, the host reading
-//     the per-model counters after each.
+//   * persistent (default): one cooperative launch runs every level of every
+//     model from a device work queue of (model, tile) items; each model
+//     advances at its own pace, with no grid-wide barrier;
+//   * host loop (REACH_F_HOST_LOOP): all models advance together, one launch
+//     per level step covering the tiles of every unfinished model, the host
+//     reading the per-model counters after each.
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
@@ -25,7 +26,7 @@ using namespace lhs;
 namespace {
 
 constexpr uint32_t kMaxBatch = 1024;   // models per call (tile prefix lives in LDS)
-constexpr uint32_t kBarrierSpinLimit = 1u << 24;
+constexpr uint32_t kBarrierSpinLimit = 1u << 24;   // bound on every queue wait
 
 // One model's expansion work of the current step.
 struct BatchSlot {
@@ -38,23 +39,6 @@ struct BatchSlot {
     uint32_t limit;
     uint32_t tile_begin;   // first global tile of this model in the step
     uint32_t pad;
-};
-
-// Full per-model state of the persistent driver (device memory).
-struct ModelState {
-    BatchSlot s;
-    uint32_t *fr[2];
-    uint64_t *levels;      // [max_levels]
-    uint64_t total, edges, deadlocks, cap;
-    uint32_t cur, n_levels, max_levels, done;
-    uint32_t capped, overflow, pad0, pad1;
-};
-
-struct PersistState {
-    uint32_t bar_count;
-    uint32_t bar_gen;
-    uint32_t error;
-    uint32_t steps;
 };
 
 __device__ __forceinline__ uint32_t find_slot_by_tile(const uint32_t *begin, uint32_t n, uint32_t g) {
@@ -122,144 +106,221 @@ __global__ void k_rollback_one(uint64_t *bucket, const uint32_t *next, uint32_t 
         bucket[next[i]] = 0;
 }
 
-// ---- persistent driver ----------------------------------------------------
+// ---- persistent driver: a device work queue, no grid-wide barriers ---------
+//
+// Items are (model, tile of the model's current level).  Workgroups take
+// items from a bounded multi-producer multi-consumer ring (cells carry a
+// sequence number: cell of position p is ready when seq == p + 1, free for
+// the producer of position p + R when seq == p + R).  The workgroup that
+// finishes the last tile of a model's level finalises that level (cap
+// rollback, level count, frontier swap, counter reset) and enqueues the
+// tiles of the model's next level, so every model advances at its own pace.
+// Everything one workgroup hands to another goes through agent-scope
+// (coherent) accesses, completed (vmcnt(0)) before the item or counter that
+// announces it.  Every wait is bounded; on timeout the error flag is set and
+// all workgroups leave.
 
-// Grid-wide barrier (all workgroups are co-resident: cooperative launch).
-// Agent-scope fences make every workgroup's writes of the phase visible to
-// the others.  The wait is bounded: on timeout the error flag is set and
-// every workgroup leaves at its next barrier.  Returns false on error.
-__device__ bool grid_barrier(PersistState *ps, uint32_t nblocks) {
-    __shared__ uint32_t s_ok;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t gen = __hip_atomic_load(&ps->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t arrived = atomicAdd(&ps->bar_count, 1u) + 1u;
-        if (arrived == nblocks) {
-            __hip_atomic_store(&ps->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ps->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            uint32_t spins = 0;
-            while (__hip_atomic_load(&ps->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if (++spins > kBarrierSpinLimit) {
-                    atomicCAS(&ps->error, 0u, (uint32_t)LHS_ESTALL);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(8);
-            }
-        }
-        __threadfence();
-        s_ok = __hip_atomic_load(&ps->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
-    }
-    __syncthreads();
-    return s_ok != 0;
+struct QCell {
+    unsigned long long seq;
+    uint32_t model;
+    uint32_t tile;
+};
+
+struct QueueState {
+    unsigned long long head;    // next position to take
+    unsigned long long tail;    // next position to fill
+    uint32_t remaining;         // unfinished models
+    uint32_t error;
+    unsigned long long mask;    // ring size - 1
+};
+
+// Per-model level state (changes every level; coherent accesses only).
+struct LevelState {
+    unsigned long long front;   // uint32_t* of the current frontier
+    unsigned long long next;    // uint32_t* of the next frontier
+    uint32_t n_front;
+    uint32_t limit;
+    uint32_t tiles_total;
+    uint32_t tiles_done;
+};
+
+// Per-model constants (written by the host before the launch, read-only in
+// the kernel, so plain loads are fine).
+struct ModelState {
+    TableView t;
+    ModelView m;
+    LevelCounters *lc;
+    uint32_t *fr[2];
+    unsigned long long *levels;   // [max_levels] level counts (coherent stores)
+    unsigned long long cap;
+    uint32_t max_levels, pad;
+};
+
+// Per-model progress: updated by whichever workgroup finalises a level, so
+// only ever accessed with coherent loads and stores.
+struct ModelProgress {
+    unsigned long long total, edges, deadlocks;
+    uint32_t cur, n_levels, done, capped, overflow, pad;
+};
+
+__device__ __forceinline__ bool queue_failed(QueueState *qs) {
+    return ld_coherent(&qs->error) != 0u;
 }
 
-// All levels of all models in one launch.  Per step:
-//   (1) every workgroup computes the tile prefix over unfinished models
-//       (in LDS); no tiles left -> done;
-//   (2) workgroups take global tiles g = blockIdx.x, + gridDim.x, ...;
-//   (3) barrier; model i is finalised by workgroup i mod gridDim.x (cap
-//       rollback, level count, frontier swap, counter reset); barrier.
-template <int G>
-__global__ __launch_bounds__(kExpandBlock) void k_batch_persistent(ModelState *__restrict__ ms, uint32_t n,
-                                                                   PersistState *ps, uint32_t max_steps) {
-    extern __shared__ uint32_t smem[];
-    __shared__ uint32_t s_begin[kMaxBatch + 1];
-    __shared__ uint32_t s_part[kExpandBlock];
+// Finalise model i's level; block-wide.  Called by the workgroup that
+// completed its last tile.
+__device__ void finalize_level(const ModelState *ms, ModelProgress *mp, LevelState *lv, uint32_t i,
+                               QueueState *qs, QCell *ring) {
+    __shared__ uint32_t s_nt;
+    __shared__ unsigned long long s_pos0;
     const uint32_t tid = threadIdx.x;
-    for (uint32_t step = 0; step < max_steps; ++step) {
-        // (1) tile prefix: thread t sums the tiles of models t, t+256, ...
-        //     (contiguous chunks so the scan gives model order)
-        const uint32_t per = (n + kExpandBlock - 1) / kExpandBlock;
-        uint32_t local = 0;
-        for (uint32_t i = tid * per; i < min(n, (tid + 1) * per); ++i) {
-            const uint32_t nf = ms[i].done ? 0u : ms[i].s.n_front;
-            s_begin[i] = (nf + kExpandBlock - 1) / kExpandBlock;   // tiles, prefix below
-            local += s_begin[i];
+    const ModelState &M = ms[i];
+    ModelProgress &P = mp[i];
+    LevelState &L = lv[i];
+    LevelCounters *lc = M.lc;
+    const uint32_t n_next = ld_coherent(&lc->n_next);
+    const uint32_t limit = ld_coherent(&L.limit);
+    uint32_t *next = reinterpret_cast<uint32_t *>(ld_coherent(&L.next));
+    const bool over = M.cap && n_next > limit;
+    if (over) {
+        // discard the partial level: zero every slot it claimed
+        for (uint32_t j = tid; j < n_next; j += kExpandBlock)
+            st_coherent(M.t.bucket + ld_coherent(next + j), 0ull);
+    }
+    wait_vm_complete();
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t nt = 0, done = 0;
+        if (over) {
+            st_coherent(&P.capped, 1u);
+            done = 1;
+        } else {
+            st_coherent(&P.edges, ld_coherent(&P.edges) + ld_coherent(&lc->edges));
+            st_coherent(&P.deadlocks, ld_coherent(&P.deadlocks) + ld_coherent(&lc->deadlocks));
+            const uint32_t nl = ld_coherent(&P.n_levels);
+            if (n_next == 0) {
+                done = 1;
+            } else if (nl == M.max_levels) {
+                st_coherent(&P.overflow, 1u);
+                done = 1;
+            } else {
+                st_coherent(M.levels + nl, (unsigned long long)n_next);
+                st_coherent(&P.n_levels, nl + 1u);
+                const unsigned long long total = ld_coherent(&P.total) + n_next;
+                st_coherent(&P.total, total);
+                const uint32_t cur = ld_coherent(&P.cur) ^ 1u;
+                st_coherent(&P.cur, cur);
+                nt = (n_next + kExpandBlock - 1) / kExpandBlock;
+                const uint64_t room = M.cap ? M.cap - total : 0xFFFFFFFFull;
+                st_coherent(&L.front, (unsigned long long)M.fr[cur]);
+                st_coherent(&L.next, (unsigned long long)M.fr[cur ^ 1u]);
+                st_coherent(&L.n_front, n_next);
+                st_coherent(&L.limit, (uint32_t)min<uint64_t>(room, 0xFFFFFFFFull));
+                st_coherent(&L.tiles_total, nt);
+                st_coherent(&L.tiles_done, 0u);
+            }
         }
-        s_part[tid] = local;
+        if (done)
+            st_coherent(&P.done, 1u);
+        st_coherent(&lc->n_next, 0u);
+        st_coherent(&lc->abort, 0u);
+        st_coherent(&lc->edges, 0ull);
+        st_coherent(&lc->deadlocks, 0ull);
+        wait_vm_complete();
+        if (done)
+            atomicSub(&qs->remaining, 1u);
+        else
+            s_pos0 = atomicAdd(&qs->tail, (unsigned long long)nt);
+        s_nt = nt;
+    }
+    __syncthreads();
+    const uint32_t nt = s_nt;
+    // enqueue the next level's tiles: wait for each cell to be free, fill it,
+    // then publish it
+    for (uint32_t k = tid; k < nt; k += kExpandBlock) {
+        const unsigned long long pos = s_pos0 + k;
+        QCell *c = ring + (pos & qs->mask);
+        uint32_t spins = 0;
+        while (ld_coherent(&c->seq) != pos) {
+            if (++spins > kBarrierSpinLimit || queue_failed(qs)) {
+                atomicCAS(&qs->error, 0u, (uint32_t)LHS_ESTALL);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        st_coherent(&c->model, i);
+        st_coherent(&c->tile, k);
+        wait_vm_complete();
+        st_coherent(&c->seq, pos + 1ull);
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(kExpandBlock) void k_batch_persistent(const ModelState *__restrict__ ms,
+                                                                   ModelProgress *mp, LevelState *lv,
+                                                                   QueueState *qs, QCell *ring) {
+    extern __shared__ uint32_t smem[];
+    __shared__ uint32_t s_model, s_tile, s_exit, s_fin;
+    const uint32_t tid = threadIdx.x;
+    while (true) {
+        if (tid == 0) {
+            uint32_t ex = 0;
+            const unsigned long long pos = atomicAdd(&qs->head, 1ull);
+            QCell *c = ring + (pos & qs->mask);
+            uint32_t spins = 0;
+            while (ld_coherent(&c->seq) != pos + 1ull) {
+                if (ld_coherent(&qs->remaining) == 0u || queue_failed(qs)) {
+                    ex = 1;
+                    break;
+                }
+                if (++spins > kBarrierSpinLimit) {
+                    atomicCAS(&qs->error, 0u, (uint32_t)LHS_ESTALL);
+                    ex = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(4);
+            }
+            if (!ex) {
+                s_model = ld_coherent(&c->model);
+                s_tile = ld_coherent(&c->tile);
+                st_coherent(&c->seq, pos + qs->mask + 1ull);   // free for position pos + R
+            }
+            s_exit = ex;
+        }
+        __syncthreads();
+        if (s_exit)
+            break;
+        const uint32_t i = s_model, j = s_tile;
+        const ModelState &M = ms[i];
+        LevelState &L = lv[i];
+        const uint32_t *front = reinterpret_cast<const uint32_t *>(ld_coherent(&L.front));
+        uint32_t *next = reinterpret_cast<uint32_t *>(ld_coherent(&L.next));
+        const uint32_t n_front = ld_coherent(&L.n_front);
+        const uint32_t limit = ld_coherent(&L.limit);
+        const uint64_t base = (uint64_t)j * kExpandBlock;
+        const uint32_t rows = (uint32_t)min<uint64_t>(kExpandBlock, n_front - base);
+        expand_tile<G, true>(smem, M.t, M.m, front, base, rows, next, M.lc, limit);
+        // this workgroup's stores of the tile are complete before it counts
+        // the tile as done
+        wait_vm_complete();
         __syncthreads();
         if (tid == 0) {
-            uint32_t acc = 0;
-            for (uint32_t w = 0; w < kExpandBlock; ++w) {
-                const uint32_t v = s_part[w];
-                s_part[w] = acc;
-                acc += v;
-            }
-            s_begin[n] = acc;
+            const uint32_t done = atomicAdd(&L.tiles_done, 1u) + 1u;
+            s_fin = done == ld_coherent(&L.tiles_total);
         }
         __syncthreads();
-        {
-            uint32_t acc = s_part[tid];
-            for (uint32_t i = tid * per; i < min(n, (tid + 1) * per); ++i) {
-                const uint32_t v = s_begin[i];
-                s_begin[i] = acc;
-                acc += v;
-            }
-        }
-        __syncthreads();
-        const uint32_t total = s_begin[n];
-        if (total == 0)
-            break;
-        // (2) expansion
-        for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
-            const uint32_t i = find_slot_by_tile(s_begin, n, g);
-            const BatchSlot s = ms[i].s;
-            const uint64_t base = (uint64_t)(g - s_begin[i]) * kExpandBlock;
-            const uint32_t rows = (uint32_t)min<uint64_t>(kExpandBlock, s.n_front - base);
-            expand_tile<G>(smem, s.t, s.m, s.front, base, rows, s.next, s.lc, s.limit);
-        }
-        if (!grid_barrier(ps, gridDim.x))
-            return;
-        // (3) per-model finalisation of the level
-        for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-            ModelState &M = ms[i];
-            if (M.done)
-                continue;
-            LevelCounters *lc = M.s.lc;
-            const uint32_t n_next = lc->n_next;
-            const bool over = M.cap && n_next > M.s.limit;
-            if (over) {
-                // discard the partial level: zero every slot it claimed
-                for (uint32_t j = tid; j < n_next; j += kExpandBlock)
-                    M.s.t.bucket[M.s.next[j]] = 0;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                if (over) {
-                    M.capped = 1;
-                    M.done = 1;
-                } else {
-                    M.edges += lc->edges;
-                    M.deadlocks += lc->deadlocks;
-                    if (n_next == 0) {
-                        M.done = 1;
-                    } else if (M.n_levels == M.max_levels) {
-                        M.overflow = 1;
-                        M.done = 1;
-                    } else {
-                        M.levels[M.n_levels++] = n_next;
-                        M.total += n_next;
-                        M.cur ^= 1u;
-                        M.s.front = M.fr[M.cur];
-                        M.s.next = M.fr[M.cur ^ 1u];
-                        M.s.n_front = n_next;
-                        const uint64_t room = M.cap ? M.cap - M.total : 0xFFFFFFFFull;
-                        M.s.limit = (uint32_t)min<uint64_t>(room, 0xFFFFFFFFull);
-                    }
-                }
-                lc->n_next = 0;
-                lc->abort = 0;
-                lc->edges = 0;
-                lc->deadlocks = 0;
-            }
-            __syncthreads();
-        }
-        if (tid == 0 && blockIdx.x == 0)
-            ps->steps = step + 1;
-        if (!grid_barrier(ps, gridDim.x))
-            return;
+        if (s_fin)
+            finalize_level(ms, mp, lv, i, qs, ring);
+    }
+}
+
+__global__ void k_init_ring(QCell *ring, unsigned long long cells, uint32_t n_models) {
+    for (unsigned long long p = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; p < cells;
+         p += (unsigned long long)gridDim.x * blockDim.x) {
+        // positions 0..n_models-1 hold level 0 (tile 0) of every model
+        ring[p].seq = p < n_models ? p + 1 : p;
+        ring[p].model = p < n_models ? (uint32_t)p : 0u;
+        ring[p].tile = 0;
     }
 }
 
@@ -311,7 +372,10 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
     BatchSlot *d_slots = nullptr, *h_slots = nullptr;
     uint32_t *d_begin = nullptr, *h_begin = nullptr, *d_roots = nullptr, *d_root_off = nullptr;
     ModelState *d_ms = nullptr;
-    PersistState *d_ps = nullptr;
+    ModelProgress *d_mp = nullptr;
+    LevelState *d_lv = nullptr;
+    QueueState *d_qs = nullptr;
+    QCell *d_ring = nullptr;
     uint64_t *d_levels = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     uint32_t max_W = 1;
@@ -404,27 +468,54 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
     // ---- exploration -------------------------------------------------------
     if (rc == LHS_OK && !host_loop) {
         std::vector<ModelState> hms(n);
+        std::vector<ModelProgress> hmp(n);
+        std::vector<LevelState> hlv(n);
+        // ring: at most one level's tiles per model are pending at a time
+        uint64_t pending = n;
+        for (uint32_t i = 0; i < n; ++i)
+            pending += bm[i].t->capacity / kExpandBlock + 1;
+        uint64_t cells = 1024;
+        while (cells < 2 * pending)
+            cells <<= 1;
+        QueueState hq{};
+        hq.head = 0;
+        hq.tail = n;
+        hq.remaining = n;
+        hq.error = 0;
+        hq.mask = cells - 1;
         if (hipMalloc(&d_ms, n * sizeof(ModelState)) != hipSuccess ||
-            hipMalloc(&d_ps, sizeof(PersistState)) != hipSuccess ||
-            hipMalloc(&d_levels, (uint64_t)n * max_levels * sizeof(uint64_t)) != hipSuccess ||
-            hipMemset(d_ps, 0, sizeof(PersistState)) != hipSuccess)
+            hipMalloc(&d_mp, n * sizeof(ModelProgress)) != hipSuccess ||
+            hipMalloc(&d_lv, n * sizeof(LevelState)) != hipSuccess ||
+            hipMalloc(&d_qs, sizeof(QueueState)) != hipSuccess ||
+            hipMalloc(&d_ring, cells * sizeof(QCell)) != hipSuccess ||
+            hipMalloc(&d_levels, (uint64_t)n * max_levels * sizeof(uint64_t)) != hipSuccess)
             rc = LHS_ENOMEM;
         for (uint32_t i = 0; i < n && rc == LHS_OK; ++i) {
             ModelState &M = hms[i];
             std::memset(&M, 0, sizeof(M));
-            M.s = h_slots[i];
+            M.t = h_slots[i].t;
+            M.m = h_slots[i].m;
+            M.lc = h_slots[i].lc;
             M.fr[0] = bm[i].t->frontier[0];
             M.fr[1] = bm[i].t->frontier[1];
-            M.levels = d_levels + (uint64_t)i * max_levels;
-            M.total = 1;
+            M.levels = reinterpret_cast<unsigned long long *>(d_levels + (uint64_t)i * max_levels);
             M.cap = bm[i].m->state_cap;
             M.max_levels = max_levels;
-            M.n_levels = 1;
+            ModelProgress &P = hmp[i];
+            std::memset(&P, 0, sizeof(P));
+            P.total = 1;
+            P.n_levels = 1;
+            LevelState &L = hlv[i];
+            L.front = (unsigned long long)M.fr[0];
+            L.next = (unsigned long long)M.fr[1];
+            L.n_front = 1;
+            L.limit = bm[i].limit;
+            L.tiles_total = 1;
+            L.tiles_done = 0;
         }
-        // level 0 count = 1 for every model
-        std::vector<uint64_t> ones((uint64_t)n * max_levels, 0);
+        std::vector<uint64_t> lvl_host((uint64_t)n * max_levels, 0);
         for (uint32_t i = 0; i < n; ++i)
-            ones[(uint64_t)i * max_levels] = 1;
+            lvl_host[(uint64_t)i * max_levels] = 1;
         int dev = 0, ncu = 0, per_cu = 0;
         const void *fn = nullptr;
         switch (tps) {
@@ -435,42 +526,46 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
         }
         if (rc == LHS_OK &&
             (hipMemcpy(d_ms, hms.data(), n * sizeof(ModelState), hipMemcpyHostToDevice) != hipSuccess ||
-             hipMemcpy(d_levels, ones.data(), ones.size() * sizeof(uint64_t), hipMemcpyHostToDevice) !=
-                 hipSuccess ||
+             hipMemcpy(d_mp, hmp.data(), n * sizeof(ModelProgress), hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(d_lv, hlv.data(), n * sizeof(LevelState), hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(d_qs, &hq, sizeof(hq), hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(d_levels, lvl_host.data(), lvl_host.size() * sizeof(uint64_t),
+                       hipMemcpyHostToDevice) != hipSuccess ||
              hipGetDevice(&dev) != hipSuccess ||
              hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
              hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kExpandBlock, lds) != hipSuccess ||
              per_cu < 1))
             rc = LHS_EDEVICE;
         if (rc == LHS_OK) {
+            hipLaunchKernelGGL(k_init_ring, dim3((uint32_t)std::min<uint64_t>((cells + 255) / 256, 4096)),
+                               dim3(256), 0, s, d_ring, (unsigned long long)cells, n);
             const uint32_t grid = (uint32_t)(ncu * per_cu);
-            uint32_t max_steps = max_levels + 1;
-            void *args[] = {&d_ms, &n, &d_ps, &max_steps};
+            void *args[] = {&d_ms, &d_mp, &d_lv, &d_qs, &d_ring};
             (void)hipEventRecord(e0, s);
-            if (hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kExpandBlock), args, lds, s) != hipSuccess)
+            if (hipGetLastError() != hipSuccess ||
+                hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kExpandBlock), args, lds, s) != hipSuccess)
                 rc = LHS_EDEVICE;
             (void)hipEventRecord(e1, s);
             if (rc == LHS_OK && hipStreamSynchronize(s) != hipSuccess)
                 rc = LHS_EDEVICE;
         }
-        PersistState ps{};
         DevStatus st{};
         if (rc == LHS_OK &&
-            (hipMemcpy(&ps, d_ps, sizeof(ps), hipMemcpyDeviceToHost) != hipSuccess ||
+            (hipMemcpy(&hq, d_qs, sizeof(hq), hipMemcpyDeviceToHost) != hipSuccess ||
              hipMemcpy(&st, d_status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess ||
-             hipMemcpy(hms.data(), d_ms, n * sizeof(ModelState), hipMemcpyDeviceToHost) != hipSuccess ||
-             hipMemcpy(ones.data(), d_levels, ones.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) !=
-                 hipSuccess))
+             hipMemcpy(hmp.data(), d_mp, n * sizeof(ModelProgress), hipMemcpyDeviceToHost) != hipSuccess ||
+             hipMemcpy(lvl_host.data(), d_levels, lvl_host.size() * sizeof(uint64_t),
+                       hipMemcpyDeviceToHost) != hipSuccess))
             rc = LHS_EDEVICE;
-        if (rc == LHS_OK && (ps.error || st.error))
-            rc = (lhs_status)(ps.error ? ps.error : st.error);
+        if (rc == LHS_OK && (hq.error || st.error))
+            rc = (lhs_status)(hq.error ? hq.error : st.error);
         float ms = 0;
         if (rc == LHS_OK)
             (void)hipEventElapsedTime(&ms, e0, e1);
         for (uint32_t i = 0; i < n && rc == LHS_OK; ++i) {
-            const ModelState &M = hms[i];
+            const ModelProgress &M = hmp[i];
             if (M.overflow || !M.done) {
-                rc = LHS_EINVAL;
+                rc = M.overflow ? LHS_EINVAL : LHS_EDEVICE;
                 break;
             }
             reach_result &r = results[i];
@@ -486,7 +581,8 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
                 rc = LHS_ENOMEM;
                 break;
             }
-            std::memcpy(r.level_counts, ones.data() + (uint64_t)i * max_levels, M.n_levels * sizeof(uint64_t));
+            std::memcpy(r.level_counts, lvl_host.data() + (uint64_t)i * max_levels,
+                        M.n_levels * sizeof(uint64_t));
         }
     } else if (rc == LHS_OK) {
         (void)hipEventRecord(e0, s);
@@ -608,7 +704,10 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
     (void)hipFree(d_roots);
     (void)hipFree(d_root_off);
     (void)hipFree(d_ms);
-    (void)hipFree(d_ps);
+    (void)hipFree(d_mp);
+    (void)hipFree(d_lv);
+    (void)hipFree(d_qs);
+    (void)hipFree(d_ring);
     (void)hipFree(d_levels);
     if (h_lc)
         (void)hipHostFree(h_lc);

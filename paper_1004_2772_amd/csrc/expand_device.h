@@ -53,7 +53,12 @@ __host__ __device__ constexpr uint32_t expand_lds_words(uint32_t W) {
 // appended to next[] (the cap); the tile then stops early.  Edges and
 // deadlocks of a completed tile are added to lc (one atomic per wavefront),
 // event counts to t.status.
-template <int G>
+//
+// COHERENT: frontier indices and rows are read, and next[] is written, with
+// agent-scope (cross-XCD coherent) accesses.  Needed when the previous level
+// was produced inside the same launch by other workgroups (the persistent
+// driver); across launches the kernel boundary already makes them visible.
+template <int G, bool COHERENT = false>
 __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, const ModelView &m,
                                             const uint32_t *__restrict__ front, uint64_t base,
                                             uint32_t rows, uint32_t *__restrict__ next,
@@ -82,10 +87,20 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
     succ_cnt[tid] = 0;
     if (tid < rows) {
         // rows of earlier levels were published before this level started
-        const uint64_t slot = front[base + tid];
+        const uint64_t slot = COHERENT ? ld_coherent(front + base + tid) : front[base + tid];
         const uint32_t *src = t.data + slot * W;
         uint32_t *dst = tile + tid * stride;
-        if ((W & 3u) == 0) {
+        if (COHERENT && (W & 1u) == 0) {
+            const uint64_t *s2 = reinterpret_cast<const uint64_t *>(src);
+            for (uint32_t i = 0; i < W; i += 2) {
+                const uint64_t x = ld_coherent(s2 + (i >> 1));
+                dst[i] = (uint32_t)x;
+                dst[i + 1] = (uint32_t)(x >> 32);
+            }
+        } else if (COHERENT) {
+            for (uint32_t i = 0; i < W; ++i)
+                dst[i] = ld_coherent(src + i);
+        } else if ((W & 3u) == 0) {
             const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
             for (uint32_t i = 0; i < W; i += 4) {
                 const uint4 x = s4[i >> 2];
@@ -186,8 +201,12 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
                         __hip_atomic_store(&lc->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
                 wbase = __shfl(wbase, 0, 64);
-                if (is_new)
-                    next[wbase + mbcnt(nm)] = slot;
+                if (is_new) {
+                    if (COHERENT)
+                        st_coherent(next + wbase + mbcnt(nm), slot);
+                    else
+                        next[wbase + mbcnt(nm)] = slot;
+                }
             }
         }
         head += take;
