@@ -20,6 +20,9 @@ Extra legs in the same JSON line:
   batch        : the 64-model mix (2-16 processes, widths 4-32, 10^3-10^6
                  states each) explored in one persistent launch, in one launch
                  per step, and one model at a time, on the same tables.
+  serve        : Poisson arrivals (200/s) of queries drawn uniformly from the
+                 mix, served with continuous batching and, for comparison, one
+                 query at a time; p50/p99 latency from scheduled arrival.
   cpu_baseline : the CPU oracle (sequential find-or-put) timed on a bounded
                  prefix of the same stream, one host thread.
 
@@ -84,6 +87,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-probes", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="query arrivals per second")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-warmup", type=float, default=1.0, help="seconds excluded from latency stats")
     ap.add_argument("--calib-copy", action="store_true", help="also run the copy probe (counter calibration)")
     ap.add_argument("--bfs-cap", type=int, default=1 << 27)
     ap.add_argument("--cpu-sample", type=int, default=1 << 25)
@@ -333,6 +340,48 @@ def main():
         batch["speedup_persistent_vs_one_at_a_time"] = round(
             batch["one_at_a_time"]["wall_ms"] / batch["persistent"]["wall_ms"], 2)
         out["batch"] = batch
+
+    if not args.no_serve:
+        models = gen.batch_models()
+        n_q = int(args.serve_rate * args.serve_seconds)
+        arrivals = gen.poisson_arrivals(0x5E4E, args.serve_rate, n_q)
+        picks = (gen.xs64(0x5E4F, n_q) % np.uint64(len(models))).astype(np.int64)
+        serve = {"workload": f"Poisson arrivals {args.serve_rate:g}/s for {args.serve_seconds:g} s "
+                             f"({n_q} queries) drawn uniformly from the 64-model mix; tables of "
+                             f"2^21 slots; latency = result time - scheduled arrival; first "
+                             f"{args.serve_warmup:g} s excluded"}
+        for label, max_active in (("continuous", 0), ("one_at_a_time", 1)):
+            with lhs.Server(capacity=1 << 21, max_active=max_active) as srv:
+                # resident tables: one warm-up query per shape before the clock starts
+                for t in [srv.submit(m) for m in models]:
+                    srv.wait(t)
+                t0 = srv.clock() + 0.05
+                tickets = []
+                for i in range(n_q):
+                    delay = t0 + arrivals[i] - srv.clock()
+                    if delay > 0:
+                        time.sleep(delay)
+                    tickets.append((i, srv.submit(models[picks[i]])))
+                lat, svc, states, done_last = [], [], 0, t0
+                for i, t in tickets:
+                    r, (sub, adm, done) = srv.wait(t)
+                    states += r.total
+                    done_last = max(done_last, done)
+                    if arrivals[i] >= args.serve_warmup:
+                        lat.append((done - (t0 + arrivals[i])) * 1e3)
+                        svc.append((done - adm) * 1e3)
+                st = srv.stats()
+            lat, svc = np.array(lat), np.array(svc)
+            serve[label] = {"queries": n_q, "states": int(states),
+                            "states_per_s": round(states / (done_last - t0), 1),
+                            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                            "service_p50_ms": round(float(np.percentile(svc, 50)), 3),
+                            "steps": st["steps"], "peak_table_bytes": st["peak_bytes"]}
+            log(f"serve {label}: p50 {serve[label]['p50_ms']} ms, p99 {serve[label]['p99_ms']} ms")
+        serve["p99_speedup_vs_one_at_a_time"] = round(
+            serve["one_at_a_time"]["p99_ms"] / serve["continuous"]["p99_ms"], 2)
+        out["serve"] = serve
 
     if not args.no_cpu:
         import oracle

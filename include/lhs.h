@@ -233,6 +233,71 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
                                lhs_table *const *tables, reach_result *results);
 
 /* ------------------------------------------------------------------------
+ * Serving: reachability queries with continuous batching.
+ *
+ * A server owns a worker thread and a HIP stream on the device that was
+ * current at reach_server_create.  Between every BFS level step it admits
+ * queued queries (first come, first served) while their tables fit the
+ * device-memory budget, expands the current level of every admitted query
+ * in one launch, and retires finished ones.  Tables stay resident in a pool
+ * and are reused by later queries of the same capacity and width.  A query's
+ * result equals reach_explore on it alone.
+ * ---------------------------------------------------------------------- */
+typedef struct reach_server reach_server;
+
+typedef struct reach_server_opts {
+    uint64_t budget_bytes; /* device memory for query tables (0 = 200 GiB)      */
+    uint64_t capacity;     /* slots per query table (power of two); 0 = pow2 >=
+                              2*state_cap + 2^16 if the model is capped, else
+                              2^21                                               */
+    uint32_t max_active;   /* queries on the GPU at once (0 = 1024)             */
+    uint32_t flags;        /* reserved, 0                                       */
+} reach_server_opts;
+
+typedef struct reach_query_times {
+    double submit_s;       /* reach_server_clock() at submission                */
+    double admit_s;        /* ... when its table was granted                    */
+    double done_s;         /* ... when its result was complete                  */
+} reach_query_times;
+
+typedef struct reach_server_stats {
+    uint64_t submitted, completed, steps;
+    uint64_t states;        /* states found by successfully completed queries   */
+    uint64_t bytes_in_use;  /* table memory allocated (in use and pooled)       */
+    uint64_t bytes_pooled;  /* of which idle in the pool                        */
+    uint64_t peak_bytes;
+    uint32_t active, queued;
+    double busy_s;          /* worker time spent admitting and stepping         */
+} reach_server_stats;
+
+/* Monotonic clock (seconds) used for reach_query_times. */
+double reach_server_clock(void);
+
+/* Start a server.  o may be NULL (defaults).  Errors: LHS_EINVAL (bad
+ * capacity), LHS_EDEVICE. */
+lhs_status reach_server_create(const reach_server_opts *o, reach_server **out);
+
+/* Queue a query; the model (host memory) is copied, the caller may free it
+ * on return.  *ticket identifies the query.  LHS_EBUDGET if its table can
+ * never fit the budget, LHS_EINVAL for an invalid model. */
+lhs_status reach_server_submit(reach_server *s, const reach_model *m, uint64_t *ticket);
+
+/* Non-blocking: LHS_EAGAIN while the query runs; otherwise fills r (free with
+ * reach_result_free) and t (either may be NULL), forgets the ticket and
+ * returns the query's status (LHS_OK or its device error).  LHS_ENOTFOUND for
+ * an unknown or already collected ticket. */
+lhs_status reach_server_poll(reach_server *s, uint64_t ticket, reach_result *r, reach_query_times *t);
+
+/* Blocking version of reach_server_poll. */
+lhs_status reach_server_wait(reach_server *s, uint64_t ticket, reach_result *r, reach_query_times *t);
+
+lhs_status reach_server_get_stats(reach_server *s, reach_server_stats *out);
+
+/* Finish every queued and running query, stop the worker and free all device
+ * memory; uncollected results are dropped.  NULL is accepted. */
+lhs_status reach_server_destroy(reach_server *s);
+
+/* ------------------------------------------------------------------------
  * Measurement probes (ceilings for the roofline of find-or-put).
  * All asynchronous on hip_stream; d_sink is a device uint64 the kernels may
  * write to keep their loads alive.

@@ -29,6 +29,8 @@ EXPORTS = ["lhs_strerror", "lhs_create", "lhs_destroy", "lhs_clear", "lhs_find_o
            "lhs_set_threads_per_state",
            "lhs_check", "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info",
            "reach_explore", "reach_result_free", "reach_explore_batch",
+           "reach_server_clock", "reach_server_create", "reach_server_submit", "reach_server_poll",
+           "reach_server_wait", "reach_server_get_stats", "reach_server_destroy",
            "lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_copy"]
 
 
@@ -57,6 +59,24 @@ class ReachOpts(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_uint64), ("max_levels", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("table", ctypes.c_void_p),
                 ("hip_stream", ctypes.c_void_p)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("capacity", ctypes.c_uint64),
+                ("max_active", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class QueryTimes(ctypes.Structure):
+    _fields_ = [("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double),
+                ("done_s", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("steps", ctypes.c_uint64), ("states", ctypes.c_uint64),
+                ("bytes_in_use", ctypes.c_uint64), ("bytes_pooled", ctypes.c_uint64),
+                ("peak_bytes", ctypes.c_uint64), ("active", ctypes.c_uint32),
+                ("queued", ctypes.c_uint32), ("busy_s", ctypes.c_double)]
 
 
 class ReachResultC(ctypes.Structure):
@@ -96,6 +116,14 @@ def lib() -> ctypes.CDLL:
                                           ctypes.POINTER(ReachOpts), ctypes.POINTER(p),
                                           ctypes.POINTER(ReachResultC)]
         L.reach_result_free.restype = None
+        L.reach_server_clock.argtypes = []
+        L.reach_server_clock.restype = ctypes.c_double
+        L.reach_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(p)]
+        L.reach_server_submit.argtypes = [p, ctypes.POINTER(ReachModel), ctypes.POINTER(u64)]
+        L.reach_server_poll.argtypes = [p, u64, ctypes.POINTER(ReachResultC), ctypes.POINTER(QueryTimes)]
+        L.reach_server_wait.argtypes = [p, u64, ctypes.POINTER(ReachResultC), ctypes.POINTER(QueryTimes)]
+        L.reach_server_get_stats.argtypes = [p, ctypes.POINTER(ServerStats)]
+        L.reach_server_destroy.argtypes = [p]
         L.lhs_probe_random_lines.argtypes = [p, u64, u32, u64, u64, p, p]
         L.lhs_probe_random_cas.argtypes = [p, u64, u64, u64, p, p]
         L.lhs_probe_copy.argtypes = [p, p, u64, p]
@@ -103,7 +131,9 @@ def lib() -> ctypes.CDLL:
                      "lhs_create", "lhs_destroy", "lhs_clear", "lhs_find_or_put", "lhs_check",
                      "lhs_set_threads_per_state",
                      "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info", "reach_explore",
-                     "reach_explore_batch"):
+                     "reach_explore_batch", "reach_server_create", "reach_server_submit",
+                     "reach_server_poll", "reach_server_wait", "reach_server_get_stats",
+                     "reach_server_destroy"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -287,6 +317,63 @@ def reach_explore(model, cap: int | None = None, capacity: int = 0, table: Table
     finally:
         lib().reach_result_free(ctypes.byref(r))
         del keep
+
+
+class Server:
+    """Continuous-batching reachability server (one worker thread on the GPU)."""
+
+    def __init__(self, budget_bytes: int = 0, capacity: int = 0, max_active: int = 0):
+        h = ctypes.c_void_p()
+        o = ServerOpts(budget_bytes, capacity, max_active, 0)
+        _check(lib().reach_server_create(ctypes.byref(o), ctypes.byref(h)), "reach_server_create")
+        self.handle = h
+
+    @staticmethod
+    def clock() -> float:
+        return lib().reach_server_clock()
+
+    def submit(self, model, cap: int | None = None) -> int:
+        m, keep = _model_struct(model, cap)
+        t = ctypes.c_uint64()
+        _check(lib().reach_server_submit(self.handle, ctypes.byref(m), ctypes.byref(t)),
+               "reach_server_submit")
+        del keep
+        return t.value
+
+    def _collect(self, fn, ticket):
+        r, tm = ReachResultC(), QueryTimes()
+        rc = fn(self.handle, ticket, ctypes.byref(r), ctypes.byref(tm))
+        if rc == 8:          # LHS_EAGAIN
+            return None
+        try:
+            _check(rc, "reach_server_poll")
+            return _result(r), (tm.submit_s, tm.admit_s, tm.done_s)
+        finally:
+            lib().reach_result_free(ctypes.byref(r))
+
+    def poll(self, ticket: int):
+        """(ReachResult, (submit_s, admit_s, done_s)) or None while running."""
+        return self._collect(lib().reach_server_poll, ticket)
+
+    def wait(self, ticket: int):
+        return self._collect(lib().reach_server_wait, ticket)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().reach_server_get_stats(self.handle, ctypes.byref(st)), "reach_server_get_stats")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            rc = lib().reach_server_destroy(self.handle)
+            self.handle = None
+            _check(rc, "reach_server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def probe_random_lines(buf, lanes_per_line: int, n_reads: int, seed: int, sink, stream=None):

@@ -17,6 +17,7 @@
 #include <new>
 #include <vector>
 
+#include "batch_kernels.h"
 #include "expand_device.h"
 #include "internal.h"
 #include "reach_internal.h"
@@ -27,84 +28,6 @@ namespace {
 
 constexpr uint32_t kMaxBatch = 1024;   // models per call (tile prefix lives in LDS)
 constexpr uint32_t kBarrierSpinLimit = 1u << 24;   // bound on every queue wait
-
-// One model's expansion work of the current step.
-struct BatchSlot {
-    TableView t;
-    ModelView m;
-    const uint32_t *front;
-    uint32_t *next;
-    LevelCounters *lc;
-    uint32_t n_front;
-    uint32_t limit;
-    uint32_t tile_begin;   // first global tile of this model in the step
-    uint32_t pad;
-};
-
-__device__ __forceinline__ uint32_t find_slot_by_tile(const uint32_t *begin, uint32_t n, uint32_t g) {
-    uint32_t lo = 0, hi = n;   // begin[lo] <= g < begin[hi]
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (begin[mid] <= g)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-// ---- host-driven step ---------------------------------------------------
-template <int G>
-__global__ __launch_bounds__(kExpandBlock) void k_expand_multi(const BatchSlot *__restrict__ slots,
-                                                               const uint32_t *__restrict__ begin,
-                                                               uint32_t n_slots, uint32_t total_tiles) {
-    extern __shared__ uint32_t smem[];
-    for (uint32_t g = blockIdx.x; g < total_tiles; g += gridDim.x) {
-        const BatchSlot &s = slots[find_slot_by_tile(begin, n_slots, g)];
-        const uint64_t base = (uint64_t)(g - s.tile_begin) * kExpandBlock;
-        const uint32_t rows = (uint32_t)min<uint64_t>(kExpandBlock, s.n_front - base);
-        expand_tile<G>(smem, s.t, s.m, s.front, base, rows, s.next, s.lc, s.limit);
-    }
-}
-
-__global__ void k_zero_levels(LevelCounters *lc, uint32_t n) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        lc[i] = LevelCounters{0, 0, 0, 0};
-}
-
-// Insert each model's initial state (level 0): block b handles model b.
-struct LdsRowB {
-    const uint32_t *r;
-    __device__ __forceinline__ uint32_t get(uint32_t i) const { return r[i]; }
-};
-
-__global__ void k_insert_roots(const BatchSlot *slots, const uint32_t *roots, const uint32_t *root_off,
-                               uint32_t n) {
-    __shared__ uint32_t row[32];
-    const uint32_t b = blockIdx.x;
-    if (b >= n)
-        return;
-    const BatchSlot &s = slots[b];
-    if (threadIdx.x < s.m.W)
-        row[threadIdx.x] = roots[root_off[b] + threadIdx.x];
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        LaneCounters cnt;
-        const LdsRowB v{row};
-        const bool active = threadIdx.x == 0;
-        uint32_t slot = kNoSlot, code = kFull;
-        const uint64_t h = hash_vec(v, s.m.W, s.t.seed);
-        find_or_put<1>(s.t, v, h, active, slot, code, cnt);
-        if (active)
-            const_cast<uint32_t *>(s.front)[0] = slot;
-    }
-}
-
-// Undo a discarded level of one model (see reach.hip).
-__global__ void k_rollback_one(uint64_t *bucket, const uint32_t *next, uint32_t n) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        bucket[next[i]] = 0;
-}
 
 // ---- persistent driver: a device work queue, no grid-wide barriers ---------
 //
@@ -612,7 +535,6 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
                 break;
             const uint32_t na = (uint32_t)act.size();
             h_begin[na] = tiles;
-            const uint32_t grid = std::min<uint32_t>(tiles, 1u << 16);
             if (hipMemcpyAsync(d_slots, h_slots, na * sizeof(BatchSlot), hipMemcpyHostToDevice, s) != hipSuccess ||
                 hipMemcpyAsync(d_begin, h_begin, (na + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s) !=
                     hipSuccess) {
@@ -620,12 +542,7 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
                 break;
             }
             hipLaunchKernelGGL(k_zero_levels, dim3((na + 255) / 256), dim3(256), 0, s, d_lc, na);
-            switch (tps) {
-            case 1: hipLaunchKernelGGL(k_expand_multi<1>, dim3(grid), dim3(kExpandBlock), lds, s, d_slots, d_begin, na, tiles); break;
-            case 4: hipLaunchKernelGGL(k_expand_multi<4>, dim3(grid), dim3(kExpandBlock), lds, s, d_slots, d_begin, na, tiles); break;
-            case 8: hipLaunchKernelGGL(k_expand_multi<8>, dim3(grid), dim3(kExpandBlock), lds, s, d_slots, d_begin, na, tiles); break;
-            default: hipLaunchKernelGGL(k_expand_multi<16>, dim3(grid), dim3(kExpandBlock), lds, s, d_slots, d_begin, na, tiles); break;
-            }
+            launch_expand_multi(tps, tiles, lds, s, d_slots, d_begin, na);
             DevStatus st{};
             if (hipGetLastError() != hipSuccess ||
                 hipMemcpyAsync(h_lc, d_lc, na * sizeof(LevelCounters), hipMemcpyDeviceToHost, s) != hipSuccess ||

@@ -15,7 +15,7 @@ import paper_1004_2772_amd as lhs
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "lhs.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:lhs_status|void|const char \*)\s*\**(\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:lhs_status|void|double|const char \*)\s*\**(\w+)\s*\(", src, re.M)))
 
 
 def test_header_and_binding_agree():
@@ -87,3 +87,15 @@ def test_reach_rejects_bad_models(name, patch):
     m = lhs.ReachModel(P, L, S, K, trans.ctypes.data, init.ctypes.data, 0)
     r = lhs.ReachResultC()
     assert lhs.lib().reach_explore(ctypes.byref(m), None, ctypes.byref(r)) == 1
+
+
+def test_server_rejects_bad_arguments():
+    L = lhs.lib()
+    h = ctypes.c_void_p()
+    o = lhs.ServerOpts(0, 24, 0, 0)           # capacity not a power of two
+    assert L.reach_server_create(ctypes.byref(o), ctypes.byref(h)) == 1
+    assert L.reach_server_create(ctypes.byref(o), None) == 1
+    t = ctypes.c_uint64()
+    assert L.reach_server_submit(None, None, ctypes.byref(t)) == 1
+    assert L.reach_server_poll(None, 1, None, None) == 1
+    assert L.reach_server_destroy(None) == 0
