@@ -369,6 +369,12 @@ class Server:
             self.handle = None
             _check(rc, "reach_server_destroy")
 
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
     def __enter__(self):
         return self
 
