@@ -181,8 +181,10 @@ __device__ void finalize_level(const ModelState *ms, ModelProgress *mp, LevelSta
 template <int G>
 __global__ __launch_bounds__(kExpandBlock) void k_batch_persistent(const ModelState *__restrict__ ms,
                                                                    ModelProgress *mp, LevelState *lv,
-                                                                   QueueState *qs, QCell *ring) {
+                                                                   QueueState *qs, QCell *ring,
+                                                                   uint32_t tcap) {
     extern __shared__ uint32_t smem[];
+    expand_begin();
     __shared__ uint32_t s_model, s_tile, s_exit, s_fin;
     const uint32_t tid = threadIdx.x;
     while (true) {
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(kExpandBlock) void k_batch_persistent(const ModelSt
         const uint32_t limit = ld_coherent(&L.limit);
         const uint64_t base = (uint64_t)j * kExpandBlock;
         const uint32_t rows = (uint32_t)min<uint64_t>(kExpandBlock, n_front - base);
-        expand_tile<G, true>(smem, M.t, M.m, front, base, rows, next, M.lc, limit);
+        expand_tile<G, true>(smem, M.t, M.m, front, base, rows, next, M.lc, limit, tcap);
         // this workgroup's stores of the tile are complete before it counts
         // the tile as done
         wait_vm_complete();
@@ -301,7 +303,7 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
     QCell *d_ring = nullptr;
     uint64_t *d_levels = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    uint32_t max_W = 1;
+    uint32_t max_W = 1, tcap = 0;
     uint32_t tps = 0;
 
     // ---- set-up: tables, models, roots (outside the timed exploration) --
@@ -310,6 +312,7 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
         b.m = models[i];
         b.W = b.m->n_procs + b.m->n_shared;
         max_W = std::max(max_W, b.W);
+        tcap = std::max(tcap, trans_lds_entries(b.m->n_procs, b.m->n_locals, b.m->trans_per_local));
         if (tables && tables[i]) {
             b.t = tables[i];
         } else {
@@ -386,7 +389,7 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
             rc = LHS_EDEVICE;
     }
-    const size_t lds = (size_t)expand_lds_words(max_W) * sizeof(uint32_t);
+    const size_t lds = (size_t)expand_lds_words(max_W, tcap) * sizeof(uint32_t);
 
     // ---- exploration -------------------------------------------------------
     if (rc == LHS_OK && !host_loop) {
@@ -463,7 +466,7 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
             hipLaunchKernelGGL(k_init_ring, dim3((uint32_t)std::min<uint64_t>((cells + 255) / 256, 4096)),
                                dim3(256), 0, s, d_ring, (unsigned long long)cells, n);
             const uint32_t grid = (uint32_t)(ncu * per_cu);
-            void *args[] = {&d_ms, &d_mp, &d_lv, &d_qs, &d_ring};
+            void *args[] = {&d_ms, &d_mp, &d_lv, &d_qs, &d_ring, &tcap};
             (void)hipEventRecord(e0, s);
             if (hipGetLastError() != hipSuccess ||
                 hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kExpandBlock), args, lds, s) != hipSuccess)
@@ -542,7 +545,7 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
                 break;
             }
             hipLaunchKernelGGL(k_zero_levels, dim3((na + 255) / 256), dim3(256), 0, s, d_lc, na);
-            launch_expand_multi(tps, tiles, lds, s, d_slots, d_begin, na);
+            launch_expand_multi(tps, tiles, max_W, tcap, s, d_slots, d_begin, na);
             DevStatus st{};
             if (hipGetLastError() != hipSuccess ||
                 hipMemcpyAsync(h_lc, d_lc, na * sizeof(LevelCounters), hipMemcpyDeviceToHost, s) != hipSuccess ||

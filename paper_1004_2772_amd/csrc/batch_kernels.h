@@ -43,13 +43,15 @@ __device__ __forceinline__ uint32_t find_slot_by_tile(const uint32_t *begin, uin
 template <int G>
 __global__ __launch_bounds__(kExpandBlock) void k_expand_multi(const BatchSlot *__restrict__ slots,
                                                                const uint32_t *__restrict__ begin,
-                                                               uint32_t n_slots, uint32_t total_tiles) {
+                                                               uint32_t n_slots, uint32_t total_tiles,
+                                                               uint32_t tcap) {
     extern __shared__ uint32_t smem[];
+    expand_begin();
     for (uint32_t g = blockIdx.x; g < total_tiles; g += gridDim.x) {
         const BatchSlot &s = slots[find_slot_by_tile(begin, n_slots, g)];
         const uint64_t base = (uint64_t)(g - s.tile_begin) * kExpandBlock;
         const uint32_t rows = (uint32_t)min<uint64_t>(kExpandBlock, s.n_front - base);
-        expand_tile<G>(smem, s.t, s.m, s.front, base, rows, s.next, s.lc, s.limit);
+        expand_tile<G>(smem, s.t, s.m, s.front, base, rows, s.next, s.lc, s.limit, tcap);
     }
 }
 
@@ -95,18 +97,20 @@ __global__ void k_rollback_one(uint64_t *bucket, const uint32_t *next, uint32_t 
 
 template <int G>
 inline void launch_expand_multi_t(dim3 grid, size_t lds, hipStream_t s, const BatchSlot *slots,
-                                  const uint32_t *begin, uint32_t n, uint32_t tiles) {
-    hipLaunchKernelGGL(k_expand_multi<G>, grid, dim3(kExpandBlock), lds, s, slots, begin, n, tiles);
+                                  const uint32_t *begin, uint32_t n, uint32_t tiles, uint32_t tcap) {
+    hipLaunchKernelGGL(k_expand_multi<G>, grid, dim3(kExpandBlock), lds, s, slots, begin, n, tiles, tcap);
 }
 
-inline void launch_expand_multi(uint32_t tps, uint32_t tiles, size_t lds, hipStream_t s,
+// tcap: LDS entries for transitions (max over the step's models that fit).
+inline void launch_expand_multi(uint32_t tps, uint32_t tiles, uint32_t max_W, uint32_t tcap, hipStream_t s,
                                 const BatchSlot *slots, const uint32_t *begin, uint32_t n) {
     const dim3 grid(std::min<uint32_t>(std::max(tiles, 1u), 1u << 16));
+    const size_t lds = (size_t)expand_lds_words(max_W, tcap) * sizeof(uint32_t);
     switch (tps) {
-    case 1: launch_expand_multi_t<1>(grid, lds, s, slots, begin, n, tiles); break;
-    case 4: launch_expand_multi_t<4>(grid, lds, s, slots, begin, n, tiles); break;
-    case 8: launch_expand_multi_t<8>(grid, lds, s, slots, begin, n, tiles); break;
-    default: launch_expand_multi_t<16>(grid, lds, s, slots, begin, n, tiles); break;
+    case 1: launch_expand_multi_t<1>(grid, lds, s, slots, begin, n, tiles, tcap); break;
+    case 4: launch_expand_multi_t<4>(grid, lds, s, slots, begin, n, tiles, tcap); break;
+    case 8: launch_expand_multi_t<8>(grid, lds, s, slots, begin, n, tiles, tcap); break;
+    default: launch_expand_multi_t<16>(grid, lds, s, slots, begin, n, tiles, tcap); break;
     }
 }
 

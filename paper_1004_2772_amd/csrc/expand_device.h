@@ -37,53 +37,141 @@ struct SuccVec {
     }
 };
 
-// Dynamic LDS of the expansion (32-bit words):
+// Dynamic LDS of the expansion (32-bit words), for state width W and a
+// transition-table area of `tcap` entries:
 //   tile     [256][W|1]  frontier states of the current tile
-//   queue    [kQueue]    enabled (state, process, transition) triples
+//   tr       [tcap] u64  the model's packed transitions (when they fit)
+//   masks    [256] u64   enabled transitions of each tile state (P*K <= 64)
+//   offs     [258]       exclusive prefix of successor counts (+ total)
+//   queue    [kQueue]    (P*K > 64) enabled (state, process, transition)
 //   succ_cnt [256]       successors per tile state (edges, deadlocks)
 //   hq       [256] u64   hash of each successor of the current pass
 //   d0, d1   [256]       successor descriptors of the pass
-__host__ __device__ constexpr uint32_t expand_lds_words(uint32_t W) {
-    return kExpandBlock * (W | 1u) + kQueue + kExpandBlock + 2 * kExpandBlock + 2 * kExpandBlock;
+//   nbuf     [kNewBuf]   slots of new states, flushed to next[] in bulk
+constexpr uint32_t kNewBuf = 1024;
+constexpr uint32_t kEagerRoom = 1u << 22;
+__host__ __device__ constexpr uint32_t expand_lds_words(uint32_t W, uint32_t tcap = 0) {
+    return kExpandBlock * (W | 1u) + 2 * tcap + 2 * kExpandBlock + 258 + kQueue + kExpandBlock +
+           2 * kExpandBlock + 2 * kExpandBlock + kNewBuf;
+}
+
+// Transitions that fit this many LDS entries are staged in LDS.
+constexpr uint32_t kTransLdsMax = 2048;
+
+// LDS entries to reserve for a model's transitions (0 = read from HBM).
+__host__ __device__ inline uint32_t trans_lds_entries(uint32_t P, uint32_t L, uint32_t K) {
+    const uint64_t n = (uint64_t)P * L * K;
+    return n <= kTransLdsMax ? (uint32_t)n : 0u;
+}
+
+// Which model's transitions are currently staged in this workgroup's LDS.
+static __shared__ const uint2 *s_trans_staged;
+// Edge / deadlock counts accumulated over tiles (deferred mode).
+static __shared__ unsigned long long s_acc_edges, s_acc_dead;
+
+// Call once at kernel start, before the first expand_tile.
+__device__ __forceinline__ void expand_begin() {
+    if (threadIdx.x == 0) {
+        s_trans_staged = nullptr;
+        s_acc_edges = 0;
+        s_acc_dead = 0;
+    }
+}
+
+// Deferred mode: add the workgroup's accumulated counts to lc (one atomic
+// each).  Call by all threads after the last expand_tile of the launch.
+__device__ __forceinline__ void expand_end(LevelCounters *lc) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_acc_edges)
+            atomicAdd(&lc->edges, s_acc_edges);
+        if (s_acc_dead)
+            atomicAdd(&lc->deadlocks, s_acc_dead);
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
+    const uint32_t lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= (uint32_t)d)
+            x += y;
+    }
+    return x;
 }
 
 // Expand states front[base, base + rows) of one model (rows <= 256).  All
 // 256 threads of the workgroup call it together.  Returns true (uniformly)
 // if the level has been aborted, i.e. more than `limit` new states were
-// appended to next[] (the cap); the tile then stops early.  Edges and
-// deadlocks of a completed tile are added to lc (one atomic per wavefront),
-// event counts to t.status.
+// appended to next[] (the cap); the tile then stops early.  Edge and
+// deadlock counts go to lc (see DEFER), event counts to t.status.  tcap = LDS entries reserved for transitions.
+//
+// Successor enumeration (P*K <= 64): every lane evaluates all guards of its
+// own state into a 64-bit mask of enabled (process, transition) pairs, read
+// from the LDS copy of the transition table; a block prefix sum over the mask
+// popcounts numbers the tile's successors, and lane q of a pass decodes
+// successor number q by binary search over the prefix and the rank of its
+// bit.  Wider models (P*K > 64) enumerate candidates 256 at a time into an
+// LDS ring.
+//
+// New states are compacted into LDS and appended to next[] with one atomic
+// per workgroup and flush: the level's append cursor is a single address that
+// every workgroup of the GPU shares, and atomics on it serialise.  Far from
+// the cap a workgroup flushes once per tile (or when its buffer of kNewBuf
+// slots is nearly full).  Within kEagerRoom of the cap it flushes after every
+// pass of 256 successors and rereads the abort flag, so a discarded level
+// overshoots the cap by at most one pass per resident workgroup, as with
+// per-pass appends.  kEagerRoom exceeds resident workgroups x kNewBuf, so the
+// lazily buffered states cannot cross the cap unseen.
 //
 // COHERENT: frontier indices and rows are read, and next[] is written, with
 // agent-scope (cross-XCD coherent) accesses.  Needed when the previous level
 // was produced inside the same launch by other workgroups (the persistent
 // driver); across launches the kernel boundary already makes them visible.
-template <int G, bool COHERENT = false>
+// DEFER: edge/deadlock counts stay in LDS until expand_end (single-model
+// launches, whose counters are read only after the launch); otherwise they
+// are added to lc at the end of every tile.
+template <int G, bool COHERENT = false, bool DEFER = false>
 __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, const ModelView &m,
                                             const uint32_t *__restrict__ front, uint64_t base,
                                             uint32_t rows, uint32_t *__restrict__ next,
-                                            LevelCounters *lc, uint32_t limit) {
+                                            LevelCounters *lc, uint32_t limit, uint32_t tcap) {
     constexpr uint32_t kBlock = kExpandBlock;
     const uint32_t W = m.W, stride = W | 1u;
     uint32_t *tile = smem;
-    uint32_t *queue = tile + kBlock * stride;
+    uint2 *tr_lds = reinterpret_cast<uint2 *>(tile + kBlock * stride);
+    uint64_t *masks = reinterpret_cast<uint64_t *>(tr_lds + tcap);
+    uint32_t *offs = reinterpret_cast<uint32_t *>(masks + kBlock);
+    uint32_t *queue = offs + 258;
     uint32_t *succ_cnt = queue + kQueue;
     uint64_t *hq = reinterpret_cast<uint64_t *>(succ_cnt + kBlock);   // 8-byte aligned
     uint32_t *d0 = reinterpret_cast<uint32_t *>(hq + kBlock);
     uint32_t *d1 = d0 + kBlock;
-    __shared__ uint32_t s_tail, s_abort;
+    uint32_t *nbuf = d1 + kBlock;
+    __shared__ uint32_t s_tail, s_abort, s_eager, s_wtot[kBlock / 64], s_nnew, s_nbase;
+    __shared__ WaveScratch ws[kBlock / 64];
 
     constexpr uint32_t NG = kBlock / G;
     LaneCounters cnt;
     const uint32_t tid = threadIdx.x, gi = tid / G;
     const bool leader = (tid & (G - 1)) == 0;
     const uint32_t PK = m.P * m.K;
+    const uint32_t PLK = m.P * m.L * m.K;
+    const bool tr_in_lds = PLK <= tcap;
 
     __syncthreads();   // the previous tile is fully consumed
+    const bool restage = tr_in_lds && s_trans_staged != m.trans;
     if (tid == 0) {
         s_tail = 0;
+        s_nnew = 0;
         s_abort = __hip_atomic_load(&lc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t nn = __hip_atomic_load(&lc->n_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_eager = limit != 0xFFFFFFFFu && (uint64_t)nn + kEagerRoom > limit;
     }
+    if (restage)
+        for (uint32_t i = tid; i < PLK; i += kBlock)
+            tr_lds[i] = m.trans[i];
     succ_cnt[tid] = 0;
     if (tid < rows) {
         // rows of earlier levels were published before this level started
@@ -115,69 +203,47 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
         }
     }
     __syncthreads();
+    if (restage && tid == 0)
+        s_trans_staged = m.trans;
     if (s_abort)
         return true;
+    const uint2 *tr = tr_in_lds ? tr_lds : m.trans;
 
-    const uint32_t total_c = rows * PK;
-    uint32_t c_pos = 0, head = 0, tail = 0;
-    bool aborted = false;
-    while (true) {
-        // ---- enumerate guarded candidates into the LDS ring --------------
-        while (c_pos < total_c && tail - head < kBlock) {
-            const uint32_t c = c_pos + tid;
-            bool en = false;
-            uint32_t entry = 0;
-            if (c < total_c) {
-                const uint32_t st = __umulhi(c, m.magic_PK);
-                const uint32_t j = c - st * PK;
-                const uint32_t p = m.K == 1 ? j : __umulhi(j, m.magic_K);
-                const uint32_t k = j - p * m.K;
-                const uint32_t *row = tile + st * stride;
-                const uint32_t local = row[p];
-                if (local < m.L) {
-                    const uint2 tr = m.trans[((uint64_t)p * m.L + local) * m.K + k];
-                    const uint32_t gvar = (tr.x >> 16) & 0xFFu;
-                    en = gvar == 0xFFu || row[m.P + gvar] == (tr.y & 0xFFFFu);
-                }
-                if (en) {
-                    atomicAdd(&succ_cnt[st], 1u);
-                    entry = st | (p << 8) | (k << 16);
+    // ---- append the buffered new slots to next[] (block-wide) --------------
+    auto flush_new = [&]() {
+        __syncthreads();
+        const uint32_t nn = s_nnew;
+        if (tid == 0) {
+            if (nn) {
+                const uint32_t b = atomicAdd(&lc->n_next, nn);
+                s_nbase = b;
+                if ((uint64_t)b + nn > limit) {
+                    __hip_atomic_store(&lc->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s_abort = 1;
+                } else if (limit != 0xFFFFFFFFu && (uint64_t)b + nn + kEagerRoom > limit) {
+                    s_eager = 1;
                 }
             }
-            const uint64_t mask = __ballot(en);
-            uint32_t wbase = 0;
-            if (__lane_id() == 0 && mask)
-                wbase = atomicAdd(&s_tail, (uint32_t)__popcll(mask));
-            wbase = __shfl(wbase, 0, 64);
-            if (en)
-                queue[(wbase + mbcnt(mask)) & (kQueue - 1)] = entry;
-            c_pos += kBlock;
-            __syncthreads();
-            tail = s_tail;
-            __syncthreads();
-        }
-        if (tail == head)
-            break;
-        // ---- one pass over up to 256 successors ---------------------------
-        // (a) one lane per successor: decode and hash
-        const uint32_t take = min(tail - head, kBlock);
-        if (tid < take) {
-            const uint32_t e = queue[(head + tid) & (kQueue - 1)];
-            const uint32_t st = e & 0xFFu, p = (e >> 8) & 0xFFu, k = e >> 16;
-            const uint32_t *row = tile + st * stride;
-            const uint2 tr = m.trans[((uint64_t)p * m.L + row[p]) * m.K + k];
-            const uint32_t evar = tr.x >> 24;
-            const uint32_t ew = evar == 0xFFu ? 0xFFu : m.P + evar;
-            const SuccVec v{row, p, tr.x & 0xFFFFu, ew == 0xFFu ? 0xFFFFFFFFu : ew, tr.y >> 16};
-            hq[tid] = hash_vec(v, W, t.seed);
-            d0[tid] = (st * stride) | (p << 16) | (ew << 24);
-            d1[tid] = (tr.x & 0xFFFFu) | ((tr.y >> 16) << 16);
+            if (s_eager && !s_abort)
+                s_abort = __hip_atomic_load(&lc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
-        // (b) find-or-put of every successor (G == 1: one lane each with
-        //     wavefront-cooperative memory accesses; G > 1: one group of G
-        //     lanes each), then ballot/prefix compaction of the new ones into
-        //     next[] with one atomic per wavefront
+        if (nn) {
+            const uint32_t b = s_nbase;
+            for (uint32_t i = tid; i < nn; i += kBlock) {
+                if (COHERENT)
+                    st_coherent(next + b + i, nbuf[i]);
+                else
+                    next[b + i] = nbuf[i];
+            }
+            __syncthreads();
+            if (tid == 0)
+                s_nnew = 0;
+            __syncthreads();
+        }
+    };
+    // ---- find-or-put of successors d0/d1/hq[0, take); new slots to nbuf ----
+    auto fop_pass = [&](uint32_t take) {
         for (uint32_t r = 0; r < G; ++r) {
             const uint32_t q = r * NG + gi;
             const bool active = q < take;
@@ -185,7 +251,6 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
             const uint2 dsc = make_uint2(d0[o], d1[o]);
             uint32_t slot, code;
             if constexpr (G == 1) {
-                __shared__ WaveScratch ws[kBlock / 64];
                 find_or_put_wave<SuccVec>(t, &ws[tid / 64], smem, dsc, hq[o], active, slot, code, cnt);
             } else {
                 find_or_put<G>(t, SuccVec::decode(smem, dsc), hq[o], active, slot, code, cnt);
@@ -194,43 +259,162 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
             const uint64_t nm = __ballot(is_new);
             if (nm) {
                 uint32_t wbase = 0;
-                const uint32_t wn = (uint32_t)__popcll(nm);
-                if (__lane_id() == 0) {
-                    wbase = atomicAdd(&lc->n_next, wn);
-                    if ((uint64_t)wbase + wn > limit)
-                        __hip_atomic_store(&lc->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
+                if (__lane_id() == 0)
+                    wbase = atomicAdd(&s_nnew, (uint32_t)__popcll(nm));
                 wbase = __shfl(wbase, 0, 64);
-                if (is_new) {
-                    if (COHERENT)
-                        st_coherent(next + wbase + mbcnt(nm), slot);
-                    else
-                        next[wbase + mbcnt(nm)] = slot;
+                if (is_new)
+                    nbuf[wbase + mbcnt(nm)] = slot;
+            }
+        }
+        __syncthreads();
+        if (s_eager || s_nnew > kNewBuf - kBlock)
+            flush_new();
+        return s_abort != 0;
+    };
+    // decode successor (st, p, k) into hq/d0/d1[slot_i]
+    auto stage_successor = [&](uint32_t i, uint32_t st, uint32_t p, uint32_t k) {
+        const uint32_t *row = tile + st * stride;
+        const uint2 x = tr[((uint64_t)p * m.L + row[p]) * m.K + k];
+        const uint32_t evar = x.x >> 24;
+        const uint32_t ew = evar == 0xFFu ? 0xFFu : m.P + evar;
+        const SuccVec v{row, p, x.x & 0xFFFFu, ew == 0xFFu ? 0xFFFFFFFFu : ew, x.y >> 16};
+        hq[i] = hash_vec(v, W, t.seed);
+        d0[i] = (st * stride) | (p << 16) | (ew << 24);
+        d1[i] = (x.x & 0xFFFFu) | ((x.y >> 16) << 16);
+    };
+
+    bool aborted = false;
+    if (PK <= 64) {
+        // ---- enabled-transition masks, one lane per state ------------------
+        uint64_t mask = 0;
+        if (tid < rows) {
+            const uint32_t *row = tile + tid * stride;
+            for (uint32_t p = 0; p < m.P; ++p) {
+                const uint32_t local = row[p];
+                if (local >= m.L)
+                    continue;
+                const uint2 *tp = tr + ((uint64_t)p * m.L + local) * m.K;
+                for (uint32_t k = 0; k < m.K; ++k) {
+                    const uint2 x = tp[k];
+                    const uint32_t gvar = (x.x >> 16) & 0xFFu;
+                    const bool en = gvar == 0xFFu || row[m.P + gvar] == (x.y & 0xFFFFu);
+                    mask |= (uint64_t)en << (p * m.K + k);
                 }
             }
         }
-        head += take;
+        masks[tid] = mask;
+        const uint32_t c = (uint32_t)__popcll(mask);
+        succ_cnt[tid] = c;
+        const uint32_t incl = wave_scan_incl(c);
+        if (__lane_id() == 63)
+            s_wtot[tid / 64] = incl;
         __syncthreads();
+        uint32_t woff = 0, total = 0;
+        for (uint32_t w = 0; w < kBlock / 64; ++w) {
+            woff += w < tid / 64 ? s_wtot[w] : 0u;
+            total += s_wtot[w];
+        }
+        offs[tid] = woff + incl - c;
         if (tid == 0)
-            s_abort = __hip_atomic_load(&lc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            offs[kBlock] = total;
         __syncthreads();
-        if (s_abort) {
-            aborted = true;
-            break;
+        // ---- passes of 256 successors -------------------------------------
+        for (uint32_t s0 = 0; s0 < total && !aborted; s0 += kBlock) {
+            const uint32_t take = min(total - s0, kBlock);
+            if (tid < take) {
+                const uint32_t q = s0 + tid;
+                uint32_t lo = 0, hi = kBlock;    // offs[lo] <= q < offs[hi]
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (offs[mid] <= q)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                uint64_t mk = masks[lo];
+                for (uint32_t r = q - offs[lo]; r; --r)
+                    mk &= mk - 1;
+                const uint32_t j = (uint32_t)__builtin_ctzll(mk);
+                const uint32_t p = m.K == 1 ? j : __umulhi(j, m.magic_K);
+                stage_successor(tid, lo, p, j - p * m.K);
+            }
+            __syncthreads();
+            aborted = fop_pass(take);
+        }
+    } else {
+        // ---- wide models: candidates 256 at a time into the LDS ring ------
+        const uint32_t total_c = rows * PK;
+        uint32_t c_pos = 0, head = 0, tail = 0;
+        while (true) {
+            while (c_pos < total_c && tail - head < kBlock) {
+                const uint32_t c = c_pos + tid;
+                bool en = false;
+                uint32_t entry = 0;
+                if (c < total_c) {
+                    const uint32_t st = __umulhi(c, m.magic_PK);
+                    const uint32_t j = c - st * PK;
+                    const uint32_t p = m.K == 1 ? j : __umulhi(j, m.magic_K);
+                    const uint32_t k = j - p * m.K;
+                    const uint32_t *row = tile + st * stride;
+                    const uint32_t local = row[p];
+                    if (local < m.L) {
+                        const uint2 x = tr[((uint64_t)p * m.L + local) * m.K + k];
+                        const uint32_t gvar = (x.x >> 16) & 0xFFu;
+                        en = gvar == 0xFFu || row[m.P + gvar] == (x.y & 0xFFFFu);
+                    }
+                    if (en) {
+                        atomicAdd(&succ_cnt[st], 1u);
+                        entry = st | (p << 8) | (k << 16);
+                    }
+                }
+                const uint64_t msk = __ballot(en);
+                uint32_t wbase = 0;
+                if (__lane_id() == 0 && msk)
+                    wbase = atomicAdd(&s_tail, (uint32_t)__popcll(msk));
+                wbase = __shfl(wbase, 0, 64);
+                if (en)
+                    queue[(wbase + mbcnt(msk)) & (kQueue - 1)] = entry;
+                c_pos += kBlock;
+                __syncthreads();
+                tail = s_tail;
+                __syncthreads();
+            }
+            if (tail == head)
+                break;
+            const uint32_t take = min(tail - head, kBlock);
+            if (tid < take) {
+                const uint32_t e = queue[(head + tid) & (kQueue - 1)];
+                stage_successor(tid, e & 0xFFu, (e >> 8) & 0xFFu, e >> 16);
+            }
+            __syncthreads();
+            head += take;
+            if (fop_pass(take)) {
+                aborted = true;
+                break;
+            }
         }
     }
-    if (!aborted) {
-        const uint32_t mine = tid < rows ? succ_cnt[tid] : 0u;
-        const uint32_t e32 = wave_sum(mine), d32 = wave_sum(tid < rows && mine == 0);
-        if (__lane_id() == 0) {
-            if (e32)
-                atomicAdd(&lc->edges, (unsigned long long)e32);
-            if (d32)
-                atomicAdd(&lc->deadlocks, (unsigned long long)d32);
+    flush_new();
+    // ---- edge and deadlock counts of the tile -------------------------------
+    const uint32_t mine = tid < rows ? succ_cnt[tid] : 0u;
+    const uint32_t e32 = wave_sum(mine), d32 = wave_sum(tid < rows && mine == 0);
+    if (__lane_id() == 0) {
+        atomicAdd(&s_acc_edges, (unsigned long long)e32);
+        atomicAdd(&s_acc_dead, (unsigned long long)d32);
+    }
+    if constexpr (!DEFER) {
+        __syncthreads();
+        if (tid == 0) {
+            if (s_acc_edges)
+                atomicAdd(&lc->edges, s_acc_edges);
+            if (s_acc_dead)
+                atomicAdd(&lc->deadlocks, s_acc_dead);
+            s_acc_edges = 0;
+            s_acc_dead = 0;
         }
     }
     flush_counters(t.status, cnt);
-    return aborted;
+    return s_abort != 0;
 }
 
 }  // namespace lhs

@@ -189,37 +189,41 @@ struct Group {
 };
 
 // Snapshot of one 128-byte line: masks of empty slots and of slots whose
-// memo equals `memo` (any status), bit i = slot i of the line.  The G lanes of
-// a group load 16/G contiguous slots each (one coalesced 128-byte access per
-// group).
+// memo equals `memo` (any status), bit i = slot i of the line.  The line is
+// eight 16-byte chunks (two slots each); lane `sub` of a group of G loads
+// chunks sub, sub + G, ..., so every load instruction of the group covers one
+// contiguous 16*G-byte segment of the line.
 template <int G>
 __device__ __forceinline__ void line_masks(const Group<G> &g, const uint64_t *line_ptr, uint64_t memo,
                                            uint32_t &empty, uint32_t &match) {
     constexpr uint32_t SPL = kLineSlots / G;
-    uint64_t s[SPL];
-    if constexpr (SPL == 1) {
-        s[0] = line_ptr[g.sub];
-    } else {
-        const uint4 *p = reinterpret_cast<const uint4 *>(line_ptr + g.sub * SPL);
-#pragma unroll
-        for (uint32_t q = 0; q < SPL / 2; ++q) {
-            const uint4 x = p[q];
-            s[2 * q] = ((uint64_t)x.y << 32) | x.x;
-            s[2 * q + 1] = ((uint64_t)x.w << 32) | x.z;
-        }
-    }
     uint32_t e = 0, m = 0;
-    if constexpr (G == 1) {
-#pragma unroll
-        for (uint32_t i = 0; i < SPL; ++i) {
-            e |= (uint32_t)(s[i] == 0) << i;
-            m |= (uint32_t)((s[i] & ~kDone) == memo) << i;
-        }
+    if constexpr (SPL == 1) {
+        const uint64_t s0 = line_ptr[g.sub];
+        e = g.bits(__ballot(s0 == 0));
+        m = g.bits(__ballot((s0 & ~kDone) == memo));
     } else {
+        constexpr uint32_t Q = SPL / 2;          // chunks per lane
+        const uint4 *p = reinterpret_cast<const uint4 *>(line_ptr);
+        uint4 x[Q];
 #pragma unroll
-        for (uint32_t i = 0; i < SPL; ++i) {
-            e |= spread<SPL>(g.bits(__ballot(s[i] == 0))) << i;
-            m |= spread<SPL>(g.bits(__ballot((s[i] & ~kDone) == memo))) << i;
+        for (uint32_t q = 0; q < Q; ++q)
+            x[q] = p[q * G + g.sub];
+#pragma unroll
+        for (uint32_t q = 0; q < Q; ++q) {
+            const uint64_t s0 = ((uint64_t)x[q].y << 32) | x[q].x;
+            const uint64_t s1 = ((uint64_t)x[q].w << 32) | x[q].z;
+            if constexpr (G == 1) {
+                e |= ((uint32_t)(s0 == 0) | ((uint32_t)(s1 == 0) << 1)) << (2 * q);
+                m |= ((uint32_t)((s0 & ~kDone) == memo) | ((uint32_t)((s1 & ~kDone) == memo) << 1))
+                     << (2 * q);
+            } else {
+                // chunk q*G + sub holds slots 2(q*G + sub) and 2(q*G + sub) + 1
+                e |= spread<2>(g.bits(__ballot(s0 == 0))) << (2 * q * G);
+                e |= spread<2>(g.bits(__ballot(s1 == 0))) << (2 * q * G + 1);
+                m |= spread<2>(g.bits(__ballot((s0 & ~kDone) == memo))) << (2 * q * G);
+                m |= spread<2>(g.bits(__ballot((s1 & ~kDone) == memo))) << (2 * q * G + 1);
+            }
         }
     }
     empty = e;

@@ -20,14 +20,16 @@ template <int G>
 __global__ __launch_bounds__(kExpandBlock) void k_expand(TableView t, ModelView m,
                                                          const uint32_t *__restrict__ front,
                                                          uint32_t n_front, uint32_t *__restrict__ next,
-                                                         LevelCounters *lc, uint32_t limit) {
+                                                         LevelCounters *lc, uint32_t limit, uint32_t tcap) {
     extern __shared__ uint32_t smem[];
+    expand_begin();
     for (uint64_t base = (uint64_t)blockIdx.x * kExpandBlock; base < n_front;
          base += (uint64_t)gridDim.x * kExpandBlock) {
         const uint32_t rows = (uint32_t)min<uint64_t>(kExpandBlock, n_front - base);
-        if (expand_tile<G>(smem, t, m, front, base, rows, next, lc, limit))
+        if (expand_tile<G, false, true>(smem, t, m, front, base, rows, next, lc, limit, tcap))
             break;
     }
+    expand_end(lc);
 }
 
 // Undo the inserts of a discarded level: zero the slots listed in next[].
@@ -97,21 +99,22 @@ ModelView model_view(const reach_model *m, const uint2 *d_trans) {
     return v;
 }
 
-size_t expand_lds_bytes(uint32_t W) {
-    return (size_t)expand_lds_words(W) * sizeof(uint32_t);
+size_t expand_lds_bytes(uint32_t W, uint32_t tcap) {
+    return (size_t)expand_lds_words(W, tcap) * sizeof(uint32_t);
 }
 
 lhs_status launch_expand(lhs_table *t, const TableView &tv, const ModelView &mv, const uint32_t *front,
                          uint32_t n_front, uint32_t *next, LevelCounters *lc, uint32_t limit,
                          hipStream_t s) {
     const uint32_t blocks = (uint32_t)std::min<uint64_t>((n_front + kExpandBlock - 1) / kExpandBlock, 1u << 16);
-    const size_t lds = expand_lds_bytes(mv.W);
+    const uint32_t tc = trans_lds_entries(mv.P, mv.L, mv.K);
+    const size_t lds = expand_lds_bytes(mv.W, tc);
     const dim3 grid(std::max(blocks, 1u)), block(kExpandBlock);
     switch (tps_expand(t)) {
-    case 1: hipLaunchKernelGGL(k_expand<1>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit); break;
-    case 4: hipLaunchKernelGGL(k_expand<4>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit); break;
-    case 8: hipLaunchKernelGGL(k_expand<8>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit); break;
-    case 16: hipLaunchKernelGGL(k_expand<16>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit); break;
+    case 1: hipLaunchKernelGGL(k_expand<1>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit, tc); break;
+    case 4: hipLaunchKernelGGL(k_expand<4>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit, tc); break;
+    case 8: hipLaunchKernelGGL(k_expand<8>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit, tc); break;
+    case 16: hipLaunchKernelGGL(k_expand<16>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit, tc); break;
     default: return LHS_EINVAL;
     }
     return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;

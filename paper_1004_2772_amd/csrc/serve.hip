@@ -249,7 +249,7 @@ lhs_status step_queries(reach_server *s, std::vector<Query *> &finished) {
     lhs_status rc = ensure_step_buffers(s, na);
     if (rc != LHS_OK)
         return rc;
-    uint32_t tiles = 0, maxW = 1, tps = 1;
+    uint32_t tiles = 0, maxW = 1, tps = 1, tcap = 0;
     for (uint32_t a = 0; a < na; ++a) {
         Query *q = s->active[a];
         BatchSlot &sl = s->h_slots[a];
@@ -265,17 +265,17 @@ lhs_status step_queries(reach_server *s, std::vector<Query *> &finished) {
         s->h_begin[a] = tiles;
         tiles += (q->n_cur + kExpandBlock - 1) / kExpandBlock;
         maxW = std::max(maxW, q->W);
+        tcap = std::max(tcap, trans_lds_entries(q->m.n_procs, q->m.n_locals, q->m.trans_per_local));
         tps = tps_expand(q->t);
     }
     s->h_begin[na] = tiles;
-    const size_t lds = (size_t)expand_lds_words(maxW) * sizeof(uint32_t);
     if (hipMemcpyAsync(s->d_slots, s->h_slots, na * sizeof(BatchSlot), hipMemcpyHostToDevice, s->stream) !=
             hipSuccess ||
         hipMemcpyAsync(s->d_begin, s->h_begin, (na + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s->stream) !=
             hipSuccess)
         return LHS_EDEVICE;
     hipLaunchKernelGGL(k_zero_step, dim3((na + 255) / 256), dim3(256), 0, s->stream, s->d_lc, s->d_st, na);
-    launch_expand_multi(tps, tiles, lds, s->stream, s->d_slots, s->d_begin, na);
+    launch_expand_multi(tps, tiles, maxW, tcap, s->stream, s->d_slots, s->d_begin, na);
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(s->h_lc, s->d_lc, na * sizeof(LevelCounters), hipMemcpyDeviceToHost, s->stream) !=
             hipSuccess ||
