@@ -56,10 +56,11 @@ def source_sha(paths):
     return h.hexdigest()[:16]
 
 
-def fop_bytes_per_op(W):
-    """Algorithmic bytes of one find-or-put: input row, one 128-B slot line,
-    one row of data (written if new, compared if seen), seen byte + index."""
-    return 4 * W + 128 + 4 * W + 1 + 4
+def fop_bytes_per_op(W, line_slots=16):
+    """Algorithmic bytes of one find-or-put: input row, one line of 8-byte
+    slots, one row of data (written if new, compared if seen), seen byte +
+    index."""
+    return 4 * W + 8 * line_slots + 4 * W + 1 + 4
 
 
 def load_traffic(kernel, workload, n_launch_ops):
@@ -96,6 +97,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 25)
     ap.add_argument("--tps", type=int, default=0, help="lanes per operation (0 = library default)")
     ap.add_argument("--sweep-tps", action="store_true", help="also time every threads-per-state value")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="ignore the package's tuning table (default table shapes)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -114,6 +117,8 @@ def main():
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream()
     lhs.lib()   # fails loudly if the HIP library is missing
+    n_tuned = 0 if args.no_tune else lhs.tune_load_default()
+    log(f"tuning table: {n_tuned} entries loaded")
 
     W = gen.STREAM_W
     n_distinct = args.distinct
@@ -198,7 +203,7 @@ def main():
         table.set_threads_per_state(0)
 
     ops_per_s = n / (ms_per_step / 1e3)
-    bpo = fop_bytes_per_op(W)
+    bpo = fop_bytes_per_op(W, info["line_slots"])
     launch_ops = min(batch, n)
     achieved = bpo * launch_ops / (launch_ms / 1e3) / 1e9
     traffic, tinfo = load_traffic("k_find_or_put", "stream2p26", launch_ops)
@@ -225,7 +230,8 @@ def main():
         "roofline": roofline,
         "checks": {"new_equals_distinct": ok, "wait_hits": info["wait_hits"],
                    "cas_failures": info["cas_failures"]},
-        "threads_per_state": info["threads_per_state"],
+        "table_shape": {"tuning_entries": n_tuned, "stream_table": table.config(),
+                        "tps_in_effect": [info["tps_find_or_put"], info["tps_expand"]]},
         "wall_s_timed": round(wall, 3),
     }
 
@@ -306,7 +312,9 @@ def main():
 
     if not args.no_batch:
         models = gen.batch_models()
-        tables = [lhs.Table(1 << 21, m.W) for m in models]
+        batch_cfg, _ = lhs.tune_lookup(lhs.TUNE_BATCH, 32, 1 << 21)
+        out["table_shape"]["batch_tables"] = batch_cfg
+        tables = [lhs.Table(1 << 21, m.W, lhs.config(**batch_cfg)) for m in models]
         n_states = None
 
         def run_batch(flags):

@@ -47,24 +47,57 @@ const char *lhs_strerror(lhs_status s);
  * Table: one shared, lockless, open-addressing set of fixed-width vectors.
  *
  * Design (section "Hash Table Design"): open addressing; probing walks the
- * 128-byte line (16 eight-byte slots) that holds the home slot, starting at
- * the home slot and wrapping inside the line ("walking the line",
- * Algorithm 4), then moves to another line by double hashing; vectors live in
- * a separate data array indexed by slot; each slot memoises the vector's hash
- * and carries write/done status; 2^n slots so the index is the low hash
- * bits; empty = 0; slots are claimed with a 64-bit compare-and-swap
- * (Algorithm 2).  The table never resizes and allocates nothing after
- * lhs_create (requirements listed in "Requirements on the State Storage").
+ * line of slots that holds the home slot (by default 128 bytes = 16
+ * eight-byte slots), starting at the home slot and wrapping inside the line
+ * ("walking the line", Algorithm 4), then moves to another line (by default
+ * double hashing); vectors live in a separate data array indexed by slot;
+ * each slot memoises the vector's hash and carries write/done status; 2^n
+ * slots so the index is the low hash bits; empty = 0; slots are claimed with
+ * a 64-bit compare-and-swap (Algorithm 2).  The table never resizes and
+ * allocates nothing after creation (requirements listed in "Requirements on
+ * the State Storage").
  * ---------------------------------------------------------------------- */
 typedef struct lhs_table lhs_table;
+
+/* Line-to-line probe sequence after the home line ("Hash Table Design": the
+ * paper rehashes with further hash functions).  On 2^n lines each visits
+ * every line once in its first 2^n rounds. */
+typedef enum lhs_probe {
+    LHS_PROBE_DOUBLE = 0,    /* line_k = line_0 + k*step, step odd, from the hash */
+    LHS_PROBE_LINEAR = 1,    /* line_k = line_0 + k                               */
+    LHS_PROBE_QUADRATIC = 2  /* line_k = line_0 + k(k+1)/2                        */
+} lhs_probe;
+
+/* Tunable shape of a table.  Every choice gives the same results (the same
+ * stored set, seen flags and per-level counts); only speed and the slot
+ * numbers differ. */
+typedef struct lhs_config {
+    uint32_t line_slots;      /* slots per line walked before the next probe:
+                                 8, 16 or 32 (64, 128, 256 bytes); 0 = 16     */
+    uint32_t probe;           /* lhs_probe                                     */
+    uint32_t tps_find_or_put; /* GPU lanes per operation in lhs_find_or_put:
+                                 1, 4, 8, 16, or 0 = 4 (see
+                                 lhs_set_threads_per_state)                    */
+    uint32_t tps_expand;      /* the same for BFS expansion; 0 = 1             */
+} lhs_config;
 
 /* Create a table on the current HIP device.
  *   capacity    : number of slots, a power of two in [16, 2^32].
  *   state_words : vector width W in 32-bit words, in [1, 32].
  * Allocates capacity*8 bytes of slots (zeroed) plus capacity*W*4 bytes of
  * vector data, once.  *out receives the handle (owned by the caller, freed by
- * lhs_destroy).  Errors: LHS_EINVAL, LHS_ENOMEM, LHS_EDEVICE. */
+ * lhs_destroy).  The table's shape is the loaded tuning table's choice for
+ * (state_words, capacity) (lhs_tune_load), or the defaults of lhs_config.
+ * Errors: LHS_EINVAL, LHS_ENOMEM, LHS_EDEVICE. */
 lhs_status lhs_create(uint64_t capacity, uint32_t state_words, lhs_table **out);
+
+/* lhs_create with an explicit shape (cfg NULL = defaults, no tuning table).
+ * LHS_EINVAL for a value outside the ranges of lhs_config. */
+lhs_status lhs_create_ex(uint64_t capacity, uint32_t state_words, const lhs_config *cfg,
+                         lhs_table **out);
+
+/* The table's shape as configured (0 = default for the tps fields). */
+lhs_status lhs_get_config(lhs_table *t, lhs_config *out);
 
 /* Free the table and everything it allocated.  NULL is accepted. The caller
  * must not have work on the table in flight. */
@@ -92,11 +125,12 @@ lhs_status lhs_find_or_put(lhs_table *t, const uint32_t *d_states, uint64_t n,
 
 /* Number of GPU lanes that cooperate on one find-or-put: 1, 4, 8 or 16, or
  * 0 for each kernel's default (4 for lhs_find_or_put, 1 for the BFS).  G > 1:
- * a group of G lanes runs one operation and loads its 128-byte slot line as
- * one coalesced access (16/G slots per lane).  G = 1: every lane runs its own
- * operation while the wavefront moves lines and rows cooperatively (eight
- * lanes per line or row).  Affects speed only; results are identical for
- * every value.  Applies to later calls on the table (find-or-put and BFS). */
+ * a group of G lanes runs one operation and loads its slot line as one
+ * coalesced access (line_slots/G slots per lane).  G = 1: every lane runs its
+ * own operation while the wavefront moves lines and rows cooperatively
+ * (line_slots/2 lanes per line, eight per row).  Affects speed only; results
+ * are identical for every value.  Sets both tps fields of the table's
+ * lhs_config; applies to later calls (find-or-put and BFS). */
 lhs_status lhs_set_threads_per_state(lhs_table *t, uint32_t tps);
 
 /* Wait for the last stream used with the table, then return its sticky
@@ -124,17 +158,53 @@ lhs_status lhs_dump_slots(lhs_table *t, uint64_t *h_slots);
 typedef struct lhs_info {
     uint64_t capacity;     /* slots                                          */
     uint32_t state_words;  /* W                                              */
-    uint32_t line_slots;   /* slots per probed line (16)                     */
+    uint32_t line_slots;   /* slots per probed line (8, 16, 32)              */
     uint64_t hash_seed;    /* seed of the 64-bit vector hash                 */
     uint64_t wait_hits;    /* waits on a slot still being written (the
                               paper's write-busy "lock" hits)                */
     uint64_t cas_failures; /* lost claims of an empty slot                   */
     uint32_t error;        /* sticky lhs_status of device failures           */
-    uint32_t threads_per_state; /* lhs_set_threads_per_state value (0 = defaults) */
+    uint32_t probe;        /* lhs_probe                                      */
+    uint32_t tps_find_or_put; /* lanes per operation in effect (defaults
+                                 resolved)                                   */
+    uint32_t tps_expand;
 } lhs_info;
 
 /* Table geometry and device counters (synchronises the last stream). */
 lhs_status lhs_get_info(lhs_table *t, lhs_info *out);
+
+/* ------------------------------------------------------------------------
+ * Tuning table: table shapes chosen by the autotuner
+ * (paper_1004_2772_amd/autotune.py), which times every lhs_config on
+ * synthetic workloads of a set of widths and sizes and writes them as JSON:
+ *   {"format": "lhs-tune-1", "device": "<gcn arch>", "entries": [
+ *     {"kind": "table"|"batch", "W": w, "log2_capacity": c,
+ *      "line_slots": 8|16|32, "probe": "double"|"linear"|"quadratic",
+ *      "tps_find_or_put": g, "tps_expand": g, ...}, ...]}
+ * (other keys are ignored).  A loaded table is process-wide; lhs_create,
+ * reach_explore (kind "table"), reach_explore_batch and the server (kind
+ * "batch") take their tables' shapes from it.
+ * ---------------------------------------------------------------------- */
+#define LHS_TUNE_TABLE 0u
+#define LHS_TUNE_BATCH 1u
+
+/* Load a tuning file, replacing the loaded table.  Entries of another device
+ * are skipped: device = the arch name to match ("gfx950"), NULL = the
+ * current HIP device's.  *n_loaded (may be NULL) = entries kept.  Errors:
+ * LHS_EINVAL (unreadable file, malformed JSON or a value out of range; the
+ * loaded table is then unchanged), LHS_EDEVICE (device NULL and no device). */
+lhs_status lhs_tune_load(const char *path, const char *device, uint32_t *n_loaded);
+
+/* Forget the loaded tuning table (back to the defaults). */
+lhs_status lhs_tune_clear(void);
+
+/* The shape used for a table of `kind` with W = state_words and `capacity`
+ * slots: among the loaded entries of that kind, those of the smallest tuned
+ * W >= state_words (else the largest W), and of these the one whose
+ * log2_capacity is nearest (ties: the larger).  *found = 1 if it came from
+ * the tuning table, 0 for the defaults (found may be NULL). */
+lhs_status lhs_tune_lookup(uint32_t kind, uint32_t state_words, uint64_t capacity, lhs_config *out,
+                           int32_t *found);
 
 /* ------------------------------------------------------------------------
  * Reachability (Algorithm 1, "Reachability analysis") as level-synchronous
@@ -213,12 +283,15 @@ void reach_result_free(reach_result *r);
 
 /* Explore n models (1..1024) together: every model has its own table region
  * (slots, rows, frontiers) and results identical to reach_explore on it
- * alone; all models advance one BFS level per step and the expansion of a
- * step covers every unfinished model, so models of different sizes and
- * widths share the GPU.  By default the whole exploration is one
- * cooperative (persistent) launch whose workgroups meet at grid barriers
- * between expansion and per-model level finalisation; REACH_F_HOST_LOOP
- * uses one launch per step instead.
+ * alone, so models of different sizes and widths share the GPU.  By default
+ * the whole exploration is one persistent launch: its workgroups take
+ * (model, tile) items from a device work queue, and the workgroup that
+ * finishes a model's last tile of a level finalises that level and queues
+ * the next one, so models advance independently.  REACH_F_HOST_LOOP instead
+ * runs one launch per step in which every unfinished model advances one
+ * level.  All tables of a batch share one line width and lanes per state
+ * (internal tables: the tuning table's "batch" choice; given tables must
+ * agree on line_slots, and the first one's tps_expand is used).
  *   models  : n host pointers to models (same rules as reach_explore).
  *   o       : capacity = slots per model table (0: pow2 >= 2*state_cap +
  *             2^16 for capped models, 2^21 otherwise); max_levels (0 =
@@ -252,6 +325,8 @@ typedef struct reach_server_opts {
                               2^21                                               */
     uint32_t max_active;   /* queries on the GPU at once (0 = 1024)             */
     uint32_t flags;        /* reserved, 0                                       */
+    lhs_config table;      /* shape of every query table; all zero = the
+                              tuning table's "batch" choice                   */
 } reach_server_opts;
 
 typedef struct reach_query_times {

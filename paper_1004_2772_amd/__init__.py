@@ -18,15 +18,20 @@ import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "liblhs.so")
+#: tuning table written by ``python -m paper_1004_2772_amd.autotune`` on the target GPU
+TUNE_PATH_DEFAULT = os.path.join(PKG, "tune.json")
 
 STATUS = {0: "LHS_OK", 1: "LHS_EINVAL", 2: "LHS_ENOMEM", 3: "LHS_EFULL", 4: "LHS_ESTALL",
           5: "LHS_EDEVICE", 6: "LHS_EBUDGET", 7: "LHS_ENOTFOUND", 8: "LHS_EAGAIN"}
 REACH_NONE = 0xFFFFFFFF
 REACH_F_HOST_LOOP = 1
+PROBES = {"double": 0, "linear": 1, "quadratic": 2}
+TUNE_TABLE, TUNE_BATCH = 0, 1
 
 #: every symbol include/lhs.h declares
-EXPORTS = ["lhs_strerror", "lhs_create", "lhs_destroy", "lhs_clear", "lhs_find_or_put",
-           "lhs_set_threads_per_state",
+EXPORTS = ["lhs_strerror", "lhs_create", "lhs_create_ex", "lhs_get_config", "lhs_destroy",
+           "lhs_clear", "lhs_find_or_put", "lhs_set_threads_per_state",
+           "lhs_tune_load", "lhs_tune_clear", "lhs_tune_lookup",
            "lhs_check", "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info",
            "reach_explore", "reach_result_free", "reach_explore_batch",
            "reach_server_clock", "reach_server_create", "reach_server_submit", "reach_server_poll",
@@ -45,7 +50,26 @@ class LhsInfo(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_uint64), ("state_words", ctypes.c_uint32),
                 ("line_slots", ctypes.c_uint32), ("hash_seed", ctypes.c_uint64),
                 ("wait_hits", ctypes.c_uint64), ("cas_failures", ctypes.c_uint64),
-                ("error", ctypes.c_uint32), ("threads_per_state", ctypes.c_uint32)]
+                ("error", ctypes.c_uint32), ("probe", ctypes.c_uint32),
+                ("tps_find_or_put", ctypes.c_uint32), ("tps_expand", ctypes.c_uint32)]
+
+
+class LhsConfig(ctypes.Structure):
+    _fields_ = [("line_slots", ctypes.c_uint32), ("probe", ctypes.c_uint32),
+                ("tps_find_or_put", ctypes.c_uint32), ("tps_expand", ctypes.c_uint32)]
+
+
+def config(line_slots: int = 16, probe="double", tps_find_or_put: int = 0,
+           tps_expand: int = 0) -> LhsConfig:
+    """An lhs_config; probe by name ("double", "linear", "quadratic") or number."""
+    return LhsConfig(line_slots, PROBES[probe] if isinstance(probe, str) else probe,
+                     tps_find_or_put, tps_expand)
+
+
+def config_dict(c: LhsConfig) -> dict:
+    names = {v: k for k, v in PROBES.items()}
+    return {"line_slots": c.line_slots, "probe": names.get(c.probe, c.probe),
+            "tps_find_or_put": c.tps_find_or_put, "tps_expand": c.tps_expand}
 
 
 class ReachModel(ctypes.Structure):
@@ -63,7 +87,8 @@ class ReachOpts(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("capacity", ctypes.c_uint64),
-                ("max_active", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+                ("max_active", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("table", LhsConfig)]
 
 
 class QueryTimes(ctypes.Structure):
@@ -100,6 +125,12 @@ def lib() -> ctypes.CDLL:
         L.lhs_strerror.argtypes = [st]
         L.lhs_strerror.restype = ctypes.c_char_p
         L.lhs_create.argtypes = [u64, u32, ctypes.POINTER(p)]
+        L.lhs_create_ex.argtypes = [u64, u32, ctypes.POINTER(LhsConfig), ctypes.POINTER(p)]
+        L.lhs_get_config.argtypes = [p, ctypes.POINTER(LhsConfig)]
+        L.lhs_tune_load.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(u32)]
+        L.lhs_tune_clear.argtypes = []
+        L.lhs_tune_lookup.argtypes = [u32, u32, u64, ctypes.POINTER(LhsConfig),
+                                      ctypes.POINTER(ctypes.c_int32)]
         L.lhs_destroy.argtypes = [p]
         L.lhs_clear.argtypes = [p, p]
         L.lhs_find_or_put.argtypes = [p, p, u64, p, p, p]
@@ -129,7 +160,8 @@ def lib() -> ctypes.CDLL:
         L.lhs_probe_copy.argtypes = [p, p, u64, p]
         for name in ("lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_copy",
                      "lhs_create", "lhs_destroy", "lhs_clear", "lhs_find_or_put", "lhs_check",
-                     "lhs_set_threads_per_state",
+                     "lhs_set_threads_per_state", "lhs_create_ex", "lhs_get_config",
+                     "lhs_tune_load", "lhs_tune_clear", "lhs_tune_lookup",
                      "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info", "reach_explore",
                      "reach_explore_batch", "reach_server_create", "reach_server_submit",
                      "reach_server_poll", "reach_server_wait", "reach_server_get_stats",
@@ -162,12 +194,45 @@ def _ptr(x) -> int | None:
     return x.data_ptr()
 
 
-class Table:
-    """A lockless find-or-put table on the current HIP device."""
+def tune_load(path: str, device: str | None = None) -> int:
+    """Load a tuning file (lhs_tune_load); returns the entries kept."""
+    n = ctypes.c_uint32()
+    _check(lib().lhs_tune_load(os.fsencode(path), device.encode() if device else None,
+                               ctypes.byref(n)), "lhs_tune_load")
+    return n.value
 
-    def __init__(self, capacity: int, state_words: int):
+
+def tune_load_default() -> int:
+    """Load the package's tuning table if it exists; returns the entries kept
+    (0 if there is none or it was measured on another device)."""
+    if not os.path.exists(TUNE_PATH_DEFAULT):
+        return 0
+    return tune_load(TUNE_PATH_DEFAULT)
+
+
+def tune_clear():
+    _check(lib().lhs_tune_clear(), "lhs_tune_clear")
+
+
+def tune_lookup(kind: int, state_words: int, capacity: int):
+    """(config dict, found) the tuning table gives for a table (lhs_tune_lookup)."""
+    c, f = LhsConfig(), ctypes.c_int32()
+    _check(lib().lhs_tune_lookup(kind, state_words, capacity, ctypes.byref(c), ctypes.byref(f)),
+           "lhs_tune_lookup")
+    return config_dict(c), bool(f.value)
+
+
+class Table:
+    """A lockless find-or-put table on the current HIP device.  ``cfg``: an
+    LhsConfig (lhs_create_ex) or None for lhs_create (tuned or default)."""
+
+    def __init__(self, capacity: int, state_words: int, cfg: LhsConfig | None = None):
         h = ctypes.c_void_p()
-        _check(lib().lhs_create(capacity, state_words, ctypes.byref(h)), "lhs_create")
+        if cfg is None:
+            _check(lib().lhs_create(capacity, state_words, ctypes.byref(h)), "lhs_create")
+        else:
+            _check(lib().lhs_create_ex(capacity, state_words, ctypes.byref(cfg), ctypes.byref(h)),
+                   "lhs_create_ex")
         self.handle = h
         self.capacity = capacity
         self.W = state_words
@@ -236,6 +301,11 @@ class Table:
         i = LhsInfo()
         _check(lib().lhs_get_info(self.handle, ctypes.byref(i)), "lhs_get_info")
         return {f: getattr(i, f) for f, _ in LhsInfo._fields_}
+
+    def config(self) -> dict:
+        c = LhsConfig()
+        _check(lib().lhs_get_config(self.handle, ctypes.byref(c)), "lhs_get_config")
+        return config_dict(c)
 
 
 @dataclasses.dataclass
@@ -322,9 +392,10 @@ def reach_explore(model, cap: int | None = None, capacity: int = 0, table: Table
 class Server:
     """Continuous-batching reachability server (one worker thread on the GPU)."""
 
-    def __init__(self, budget_bytes: int = 0, capacity: int = 0, max_active: int = 0):
+    def __init__(self, budget_bytes: int = 0, capacity: int = 0, max_active: int = 0,
+                 cfg: LhsConfig | None = None):
         h = ctypes.c_void_p()
-        o = ServerOpts(budget_bytes, capacity, max_active, 0)
+        o = ServerOpts(budget_bytes, capacity, max_active, 0, cfg if cfg is not None else LhsConfig())
         _check(lib().reach_server_create(ctypes.byref(o), ctypes.byref(h)), "reach_server_create")
         self.handle = h
 

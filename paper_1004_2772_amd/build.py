@@ -4,19 +4,21 @@
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
+import tempfile
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblhs.so")
-SOURCES = ["lhs_table.hip", "reach.hip", "batch.hip", "serve.hip", "probes.hip"]
+SOURCES = ["lhs_table.hip", "reach.hip", "batch.hip", "serve.hip", "probes.hip", "tune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Wall", "-Wno-unused-result", "-pthread",
     # packed fp32 instructions are kept out of every HIP object
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -24,19 +26,34 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + srcs + ["-o", tmp]
+NOISE = "is not a recognized feature for this target"
+
+
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
-    noise = "is not a recognized feature for this target"
-    err = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if noise not in l)
+    err = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if NOISE not in l)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed ({r.returncode}):\n{err}")
     if err.strip() and verbose:
         print(err, file=sys.stderr)
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source to an object in parallel (each holds its own
+    device code), then link liblhs.so."""
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1, 16)
+    with tempfile.TemporaryDirectory(prefix="lhs_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        cmds = [[HIPCC] + FLAGS + ["-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
+        with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+            for f in [ex.submit(_run, c, verbose) for c in cmds]:
+                f.result()
+        tmp = LIB + ".tmp"
+        # only the C-ABI (lhs_*, reach_*) is exported
+        _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread",
+              "-Wl,--version-script=" + os.path.join(CSRC, "exports.map")] + objs + ["-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -178,7 +178,7 @@ __device__ void finalize_level(const ModelState *ms, ModelProgress *mp, LevelSta
     }
 }
 
-template <int G>
+template <int G, uint32_t LS>
 __global__ __launch_bounds__(kExpandBlock) void k_batch_persistent(const ModelState *__restrict__ ms,
                                                                    ModelProgress *mp, LevelState *lv,
                                                                    QueueState *qs, QCell *ring,
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(kExpandBlock) void k_batch_persistent(const ModelSt
         const uint32_t limit = ld_coherent(&L.limit);
         const uint64_t base = (uint64_t)j * kExpandBlock;
         const uint32_t rows = (uint32_t)min<uint64_t>(kExpandBlock, n_front - base);
-        expand_tile<G, true>(smem, M.t, M.m, front, base, rows, next, M.lc, limit, tcap);
+        expand_tile<G, LS, true>(smem, M.t, M.m, front, base, rows, next, M.lc, limit, tcap);
         // this workgroup's stores of the tile are complete before it counts
         // the tile as done
         wait_vm_complete();
@@ -304,7 +304,12 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
     uint64_t *d_levels = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     uint32_t max_W = 1, tcap = 0;
-    uint32_t tps = 0;
+    uint32_t tps = 0, ls = 0;
+    // shape of the internal tables: the tuned batch choice for the widest model
+    uint32_t widest = 1;
+    for (uint32_t i = 0; i < n; ++i)
+        widest = std::max(widest, models[i]->n_procs + models[i]->n_shared);
+    const lhs_config batch_cfg = tuned_config(LHS_TUNE_BATCH, widest, opts.capacity ? opts.capacity : (1ull << 21));
 
     // ---- set-up: tables, models, roots (outside the timed exploration) --
     for (uint32_t i = 0; i < n && rc == LHS_OK; ++i) {
@@ -317,7 +322,7 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
             b.t = tables[i];
         } else {
             const uint64_t cap = opts.capacity ? opts.capacity : batch_auto_capacity(b.m);
-            rc = lhs_create(cap, b.W, &b.t);
+            rc = lhs_create_ex(cap, b.W, &batch_cfg, &b.t);
             b.own = rc == LHS_OK;
         }
         if (rc != LHS_OK)
@@ -326,8 +331,13 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
             rc = LHS_EINVAL;
             break;
         }
-        if (i == 0)
+        if (i == 0) {
             tps = tps_expand(b.t);
+            ls = b.t->line_slots;
+        } else if (b.t->line_slots != ls) {
+            rc = LHS_EINVAL;   // one launch serves every table: one line width
+            break;
+        }
         rc = ensure_bfs_buffers(b.t);
         if (rc != LHS_OK)
             break;
@@ -385,8 +395,8 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
         if (hipMemcpyAsync(d_slots, h_slots, n * sizeof(BatchSlot), hipMemcpyHostToDevice, s) != hipSuccess)
             rc = LHS_EDEVICE;
         hipLaunchKernelGGL(k_zero_levels, dim3((n + 255) / 256), dim3(256), 0, s, d_lc, n);
-        hipLaunchKernelGGL(k_insert_roots, dim3(n), dim3(64), 0, s, d_slots, d_roots, d_root_off, n);
-        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        if (launch_insert_roots(ls, s, d_slots, d_roots, d_root_off, n) != LHS_OK ||
+            hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
             rc = LHS_EDEVICE;
     }
     const size_t lds = (size_t)expand_lds_words(max_W, tcap) * sizeof(uint32_t);
@@ -444,12 +454,10 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
             lvl_host[(uint64_t)i * max_levels] = 1;
         int dev = 0, ncu = 0, per_cu = 0;
         const void *fn = nullptr;
-        switch (tps) {
-        case 1: fn = (const void *)k_batch_persistent<1>; break;
-        case 4: fn = (const void *)k_batch_persistent<4>; break;
-        case 8: fn = (const void *)k_batch_persistent<8>; break;
-        default: fn = (const void *)k_batch_persistent<16>; break;
-        }
+        (void)with_shape(tps, ls, [&](auto G, auto L) {
+            fn = (const void *)k_batch_persistent<decltype(G)::value, decltype(L)::value>;
+            return LHS_OK;
+        });
         if (rc == LHS_OK &&
             (hipMemcpy(d_ms, hms.data(), n * sizeof(ModelState), hipMemcpyHostToDevice) != hipSuccess ||
              hipMemcpy(d_mp, hmp.data(), n * sizeof(ModelProgress), hipMemcpyHostToDevice) != hipSuccess ||
@@ -545,7 +553,10 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
                 break;
             }
             hipLaunchKernelGGL(k_zero_levels, dim3((na + 255) / 256), dim3(256), 0, s, d_lc, na);
-            launch_expand_multi(tps, tiles, max_W, tcap, s, d_slots, d_begin, na);
+            if (launch_expand_multi(tps, ls, tiles, max_W, tcap, s, d_slots, d_begin, na) != LHS_OK) {
+                rc = LHS_EDEVICE;
+                break;
+            }
             DevStatus st{};
             if (hipGetLastError() != hipSuccess ||
                 hipMemcpyAsync(h_lc, d_lc, na * sizeof(LevelCounters), hipMemcpyDeviceToHost, s) != hipSuccess ||

@@ -40,7 +40,7 @@ __device__ __forceinline__ uint32_t find_slot_by_tile(const uint32_t *begin, uin
 }
 
 // ---- host-driven step ---------------------------------------------------
-template <int G>
+template <int G, uint32_t LS>
 __global__ __launch_bounds__(kExpandBlock) void k_expand_multi(const BatchSlot *__restrict__ slots,
                                                                const uint32_t *__restrict__ begin,
                                                                uint32_t n_slots, uint32_t total_tiles,
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kExpandBlock) void k_expand_multi(const BatchSlot *
         const BatchSlot &s = slots[find_slot_by_tile(begin, n_slots, g)];
         const uint64_t base = (uint64_t)(g - s.tile_begin) * kExpandBlock;
         const uint32_t rows = (uint32_t)min<uint64_t>(kExpandBlock, s.n_front - base);
-        expand_tile<G>(smem, s.t, s.m, s.front, base, rows, s.next, s.lc, s.limit, tcap);
+        expand_tile<G, LS>(smem, s.t, s.m, s.front, base, rows, s.next, s.lc, s.limit, tcap);
     }
 }
 
@@ -66,6 +66,7 @@ struct LdsRowB {
     __device__ __forceinline__ uint32_t get(uint32_t i) const { return r[i]; }
 };
 
+template <uint32_t LS>
 __global__ void k_insert_roots(const BatchSlot *slots, const uint32_t *roots, const uint32_t *root_off,
                                uint32_t n) {
     __shared__ uint32_t row[32];
@@ -82,7 +83,7 @@ __global__ void k_insert_roots(const BatchSlot *slots, const uint32_t *roots, co
         const bool active = threadIdx.x == 0;
         uint32_t slot = kNoSlot, code = kFull;
         const uint64_t h = hash_vec(v, s.m.W, s.t.seed);
-        find_or_put<1>(s.t, v, h, active, slot, code, cnt);
+        find_or_put<1, LS>(s.t, v, h, active, slot, code, cnt);
         if (active)
             const_cast<uint32_t *>(s.front)[0] = slot;
     }
@@ -95,23 +96,26 @@ __global__ void k_rollback_one(uint64_t *bucket, const uint32_t *next, uint32_t 
 }
 
 
-template <int G>
-inline void launch_expand_multi_t(dim3 grid, size_t lds, hipStream_t s, const BatchSlot *slots,
-                                  const uint32_t *begin, uint32_t n, uint32_t tiles, uint32_t tcap) {
-    hipLaunchKernelGGL(k_expand_multi<G>, grid, dim3(kExpandBlock), lds, s, slots, begin, n, tiles, tcap);
+// Insert the roots of slots[0, n) (every table has line width ls).
+inline lhs_status launch_insert_roots(uint32_t ls, hipStream_t s, const BatchSlot *slots, const uint32_t *roots,
+                                      const uint32_t *root_off, uint32_t n) {
+    return with_line_slots(ls, [&](auto L) {
+        hipLaunchKernelGGL((k_insert_roots<decltype(L)::value>), dim3(n), dim3(64), 0, s, slots, roots,
+                           root_off, n);
+        return LHS_OK;
+    });
 }
 
 // tcap: LDS entries for transitions (max over the step's models that fit).
-inline void launch_expand_multi(uint32_t tps, uint32_t tiles, uint32_t max_W, uint32_t tcap, hipStream_t s,
-                                const BatchSlot *slots, const uint32_t *begin, uint32_t n) {
+inline lhs_status launch_expand_multi(uint32_t tps, uint32_t ls, uint32_t tiles, uint32_t max_W, uint32_t tcap,
+                                      hipStream_t s, const BatchSlot *slots, const uint32_t *begin, uint32_t n) {
     const dim3 grid(std::min<uint32_t>(std::max(tiles, 1u), 1u << 16));
     const size_t lds = (size_t)expand_lds_words(max_W, tcap) * sizeof(uint32_t);
-    switch (tps) {
-    case 1: launch_expand_multi_t<1>(grid, lds, s, slots, begin, n, tiles, tcap); break;
-    case 4: launch_expand_multi_t<4>(grid, lds, s, slots, begin, n, tiles, tcap); break;
-    case 8: launch_expand_multi_t<8>(grid, lds, s, slots, begin, n, tiles, tcap); break;
-    default: launch_expand_multi_t<16>(grid, lds, s, slots, begin, n, tiles, tcap); break;
-    }
+    return with_shape(tps, ls, [&](auto G, auto L) {
+        hipLaunchKernelGGL((k_expand_multi<decltype(G)::value, decltype(L)::value>), grid, dim3(kExpandBlock),
+                           lds, s, slots, begin, n, tiles, tcap);
+        return LHS_OK;
+    });
 }
 
 }  // namespace

@@ -132,7 +132,7 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
 // DEFER: edge/deadlock counts stay in LDS until expand_end (single-model
 // launches, whose counters are read only after the launch); otherwise they
 // are added to lc at the end of every tile.
-template <int G, bool COHERENT = false, bool DEFER = false>
+template <int G, uint32_t LS, bool COHERENT = false, bool DEFER = false>
 __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, const ModelView &m,
                                             const uint32_t *__restrict__ front, uint64_t base,
                                             uint32_t rows, uint32_t *__restrict__ next,
@@ -251,9 +251,9 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
             const uint2 dsc = make_uint2(d0[o], d1[o]);
             uint32_t slot, code;
             if constexpr (G == 1) {
-                find_or_put_wave<SuccVec>(t, &ws[tid / 64], smem, dsc, hq[o], active, slot, code, cnt);
+                find_or_put_wave<LS, SuccVec>(t, &ws[tid / 64], smem, dsc, hq[o], active, slot, code, cnt);
             } else {
-                find_or_put<G>(t, SuccVec::decode(smem, dsc), hq[o], active, slot, code, cnt);
+                find_or_put<G, LS>(t, SuccVec::decode(smem, dsc), hq[o], active, slot, code, cnt);
             }
             const bool is_new = active && leader && code == kNew;
             const uint64_t nm = __ballot(is_new);

@@ -30,7 +30,7 @@ namespace lhs {
 constexpr uint64_t kOcc = 1ull << 63;
 constexpr uint64_t kDone = 1ull << 62;
 constexpr uint64_t kMemoMask = kDone - 1;
-constexpr uint32_t kLineSlots = 16;          // 128-byte line of 8-byte slots
+constexpr uint32_t kLineSlots = 16;          // default line: 128 bytes of 8-byte slots
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 constexpr uint32_t kSpinLimit = 1u << 22;    // bound on one wait (ESTALL)
 
@@ -50,6 +50,9 @@ struct LaneCounters {
     uint32_t cas_failures = 0;
 };
 
+// Probe sequence across lines (after the home line's walk).
+enum : uint32_t { kProbeDouble = 0, kProbeLinear = 1, kProbeQuadratic = 2 };
+
 struct TableView {
     uint64_t *bucket;
     uint32_t *data;
@@ -57,8 +60,29 @@ struct TableView {
     uint32_t W;
     uint32_t line_mask;      // lines - 1
     uint32_t max_rounds;     // lines probed before EFULL
+    uint32_t probe;          // kProbe*
     DevStatus *status;
 };
+
+// log2 of the line width in slots (8, 16 or 32).
+template <uint32_t LS>
+__host__ __device__ constexpr uint32_t line_shift() {
+    static_assert(LS == 8 || LS == 16 || LS == 32, "line slots");
+    return LS == 8 ? 3u : (LS == 16 ? 4u : 5u);
+}
+
+// Line-to-line step of a vector's probe sequence.  Double hashing: a
+// constant odd step from the hash's high half; linear: the next line;
+// quadratic: the k-th move goes k lines on (the lines visited are line0 +
+// k(k+1)/2).  On 2^n lines each sequence visits every line once in its first
+// 2^n rounds.
+__device__ __forceinline__ uint32_t probe_step(uint64_t h, uint32_t probe) {
+    return probe == kProbeLinear ? 1u : ((uint32_t)(h >> 32) | 1u);
+}
+__device__ __forceinline__ uint32_t next_line(uint32_t line, uint32_t rounds_done, uint32_t step,
+                                              uint32_t probe, uint32_t line_mask) {
+    return (line + (probe == kProbeQuadratic ? rounds_done : step)) & line_mask;
+}
 
 __device__ __forceinline__ uint32_t mbcnt(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -139,25 +163,21 @@ __device__ __forceinline__ void set_error(DevStatus *st, uint32_t code) {
     atomicCAS(&st->error, 0u, code);
 }
 
-// rotate a 16-bit mask right by r (bit k of the result = bit (k + r) mod 16)
-__device__ __forceinline__ uint32_t rotr16(uint32_t m, uint32_t r) {
-    return ((m >> r) | (m << (16 - r))) & 0xFFFFu;
+// rotate an LS-bit mask right by r (bit k of the result = bit (k + r) mod LS)
+template <uint32_t LS>
+__device__ __forceinline__ uint32_t rotr_line(uint32_t m, uint32_t r) {
+    if constexpr (LS == 32)
+        return __builtin_rotateright32(m, r);
+    else
+        return ((m >> r) | (m << (LS - r))) & ((1u << LS) - 1u);
 }
 
-// Spread the low 16/S bits of x so that bit i lands on bit i*S (S = 1, 2, 4).
-template <uint32_t S>
-__device__ __forceinline__ uint32_t spread(uint32_t x) {
-    if constexpr (S == 1) {
-        return x;
-    } else if constexpr (S == 2) {
-        x = (x | (x << 4)) & 0x0F0Fu;
-        x = (x | (x << 2)) & 0x3333u;
-        return (x | (x << 1)) & 0x5555u;
-    } else {
-        static_assert(S == 4, "slots per lane");
-        x = (x | (x << 6)) & 0x0303u;
-        return (x | (x << 3)) & 0x1111u;
-    }
+// Spread the low 16 bits of x so that bit i lands on bit 2i.
+__device__ __forceinline__ uint32_t spread2(uint32_t x) {
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    return (x | (x << 1)) & 0x55555555u;
 }
 
 // Lane geometry of a group of G consecutive lanes of a wavefront.
@@ -188,20 +208,23 @@ struct Group {
     }
 };
 
-// Snapshot of one 128-byte line: masks of empty slots and of slots whose
+// Snapshot of one line of LS slots: masks of empty slots and of slots whose
 // memo equals `memo` (any status), bit i = slot i of the line.  The line is
-// eight 16-byte chunks (two slots each); lane `sub` of a group of G loads
+// LS/2 16-byte chunks (two slots each); lane `sub` of a group of G loads
 // chunks sub, sub + G, ..., so every load instruction of the group covers one
-// contiguous 16*G-byte segment of the line.
-template <int G>
+// contiguous 16*G-byte segment of the line.  With G >= LS every lane below
+// LS loads one slot and the others only take part in the ballots.
+template <int G, uint32_t LS>
 __device__ __forceinline__ void line_masks(const Group<G> &g, const uint64_t *line_ptr, uint64_t memo,
                                            uint32_t &empty, uint32_t &match) {
-    constexpr uint32_t SPL = kLineSlots / G;
+    constexpr uint32_t SPL = LS / G;
     uint32_t e = 0, m = 0;
-    if constexpr (SPL == 1) {
-        const uint64_t s0 = line_ptr[g.sub];
-        e = g.bits(__ballot(s0 == 0));
-        m = g.bits(__ballot((s0 & ~kDone) == memo));
+    if constexpr (SPL <= 1) {
+        const bool own = (uint32_t)G == LS || g.sub < LS;
+        const uint64_t s0 = own ? line_ptr[g.sub] : ~0ull;
+        constexpr uint32_t lm = LS == 32 ? 0xFFFFFFFFu : (1u << LS) - 1u;
+        e = g.bits(__ballot(own && s0 == 0)) & lm;
+        m = g.bits(__ballot(own && (s0 & ~kDone) == memo)) & lm;
     } else {
         constexpr uint32_t Q = SPL / 2;          // chunks per lane
         const uint4 *p = reinterpret_cast<const uint4 *>(line_ptr);
@@ -219,10 +242,10 @@ __device__ __forceinline__ void line_masks(const Group<G> &g, const uint64_t *li
                      << (2 * q);
             } else {
                 // chunk q*G + sub holds slots 2(q*G + sub) and 2(q*G + sub) + 1
-                e |= spread<2>(g.bits(__ballot(s0 == 0))) << (2 * q * G);
-                e |= spread<2>(g.bits(__ballot(s1 == 0))) << (2 * q * G + 1);
-                m |= spread<2>(g.bits(__ballot((s0 & ~kDone) == memo))) << (2 * q * G);
-                m |= spread<2>(g.bits(__ballot((s1 & ~kDone) == memo))) << (2 * q * G + 1);
+                e |= spread2(g.bits(__ballot(s0 == 0))) << (2 * q * G);
+                e |= spread2(g.bits(__ballot(s1 == 0))) << (2 * q * G + 1);
+                m |= spread2(g.bits(__ballot((s0 & ~kDone) == memo))) << (2 * q * G);
+                m |= spread2(g.bits(__ballot((s1 & ~kDone) == memo))) << (2 * q * G + 1);
             }
         }
     }
@@ -261,21 +284,22 @@ __device__ __forceinline__ bool row_equals(const Group<G> &g, const uint32_t *ro
     return g.all(diff == 0);
 }
 
-// One find-or-put per group of G lanes (G = 1, 4, 8 or 16).
+// One find-or-put per group of G lanes (G = 1, 4, 8 or 16) on a table of
+// LS-slot lines (LS = 8, 16 or 32: 64, 128 or 256 bytes).
 //
 // All lanes of the wavefront call this together; `active`, `v` and `h` are
 // uniform within a group, and every decision below is taken from
 // group-uniform values, so the G lanes of a group always run the same path.
 //
-// The probe sequence of a vector with hash h: home line (h >> 4) & line_mask,
-// start slot h & 15 inside it; the line is examined in walk order
-// start, start+1, ..., wrapping inside the line (Algorithm 4 with the start
-// offset read as the line base); after a line, the next line is
-// line + step (mod lines) with step = (h >> 32) | 1, odd, so successive
-// rounds visit distinct lines until every line was seen (double hashing
-// across lines).  After max_rounds lines the operation reports EFULL.
+// The probe sequence of a vector with hash h: home line
+// (h >> log2 LS) & line_mask, start slot h & (LS-1) inside it; the line is
+// examined in walk order start, start+1, ..., wrapping inside the line
+// (Algorithm 4 with the start offset read as the line base); after a line,
+// the next line follows the table's probe sequence (probe_step/next_line:
+// double hashing by default), which visits distinct lines until every line
+// was seen.  After max_rounds lines the operation reports EFULL.
 //
-// Per line one 128-byte snapshot is taken.  Candidates are, in walk order, the
+// Per line one snapshot is taken.  Candidates are, in walk order, the
 // snapshot's empty slots and the slots whose memo equals ours.  Slots that
 // are claimed with another memo are skipped: they are immutable.
 //  - empty candidate: the group leader CASes 0 -> OCC|memo.  Won: the group
@@ -292,17 +316,17 @@ __device__ __forceinline__ bool row_equals(const Group<G> &g, const uint32_t *ro
 // slot claimed by a group of its own wavefront therefore finds it already
 // published; a claim made by another wavefront is published without that
 // wavefront waiting on anything first.
-template <int G, class Vec>
+template <int G, uint32_t LS, class Vec>
 __device__ __forceinline__ void find_or_put(const TableView &t, const Vec &v, uint64_t h, bool active,
                                             uint32_t &out_slot, uint32_t &out_code,
                                             LaneCounters &cnt) {
     const Group<G> g;
     const uint64_t memo = kOcc | (h & kMemoMask);
-    const uint32_t start = (uint32_t)h & (kLineSlots - 1);
-    const uint32_t step = (uint32_t)(h >> 32) | 1u;
-    uint32_t line = (uint32_t)(h >> 4) & t.line_mask;
+    const uint32_t start = (uint32_t)h & (LS - 1);
+    const uint32_t step = probe_step(h, t.probe);
+    uint32_t line = (uint32_t)(h >> line_shift<LS>()) & t.line_mask;
     uint32_t rounds = 0;
-    uint32_t cand = 0, empty = 0;  // walk-ordered: bit k <-> slot start+k (mod 16)
+    uint32_t cand = 0, empty = 0;  // walk-ordered: bit k <-> slot start+k (mod LS)
     bool have_line = false;
     out_slot = kNoSlot;
     out_code = kFull;
@@ -318,20 +342,20 @@ __device__ __forceinline__ void find_or_put(const TableView &t, const Vec &v, ui
                 break;
             }
             uint32_t e, m;
-            line_masks<G>(g, t.bucket + (uint64_t)line * kLineSlots, memo, e, m);
-            empty = rotr16(e, start);
-            cand = rotr16(e | m, start);
+            line_masks<G, LS>(g, t.bucket + (uint64_t)line * LS, memo, e, m);
+            empty = rotr_line<LS>(e, start);
+            cand = rotr_line<LS>(e | m, start);
             have_line = true;
         }
         if (cand == 0) {
             have_line = false;
             ++rounds;
-            line = (line + step) & t.line_mask;
+            line = next_line(line, rounds, step, t.probe, t.line_mask);
             continue;
         }
         const uint32_t k = __builtin_ctz(cand);
         cand &= cand - 1;
-        const uint32_t slot = line * kLineSlots + ((start + k) & (kLineSlots - 1));
+        const uint32_t slot = line * LS + ((start + k) & (LS - 1));
         uint64_t *bp = t.bucket + slot;
         uint32_t *row = t.data + (uint64_t)slot * t.W;
         bool match = ((empty >> k) & 1u) == 0;
@@ -393,8 +417,9 @@ __device__ __forceinline__ void find_or_put(const TableView &t, const Vec &v, ui
 // Every lane owns one find-or-put (64 operations in flight per wavefront),
 // but the random 128-byte slot lines and the vector rows are moved by the
 // whole wavefront: the lanes that need a line (or a row) this iteration are
-// compacted into a list in LDS, and eight lanes serve each listed line (16
-// bytes each, one coalesced access per line) or row (8 bytes each).  Results
+// compacted into a list in LDS, and LS/2 lanes serve each listed line (16
+// bytes each, one coalesced access per line), eight lanes each row (8 bytes
+// each).  Results
 // come back through the same per-wavefront LDS area.  The helpers need the
 // owner's vector: `Vec` has a two-word descriptor any lane can decode.
 
@@ -403,7 +428,7 @@ struct WaveScratch {         // one per wavefront, in LDS
     uint32_t aux[64];        // second word (row descriptor y)
     uint64_t key[64];        // memo per rank (line snapshots)
     uint32_t desc[64];       // row descriptor x per rank
-    uint8_t res[64 * 8];     // per (rank, helper lane) result bits
+    uint8_t res[64 * 16];    // per (rank, helper lane) result bits
 };
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -413,9 +438,12 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Masks (bit i = slot i of the line) of empty, memo-matching and done slots
 // for every lane with `need`; other lanes only help.  Wavefront-uniform call.
+// C = LS/2 helper lanes per line, 64/C lines per load instruction, C rounds.
+template <uint32_t LS>
 __device__ __forceinline__ void coop_line_masks(WaveScratch *ws, const uint64_t *bucket, bool need,
                                                 uint32_t line, uint64_t memo, uint32_t &empty,
                                                 uint32_t &match, uint32_t &done) {
+    constexpr uint32_t C = LS / 2, CS = line_shift<LS>() - 1, LPQ = 64 / C;
     const uint32_t lane = __lane_id();
     const uint64_t nmask = __ballot(need);
     const uint32_t nn = (uint32_t)__popcll(nmask);
@@ -425,17 +453,17 @@ __device__ __forceinline__ void coop_line_masks(WaveScratch *ws, const uint64_t 
         ws->key[rank] = memo;
     }
     wave_lds_sync();
-    const uint32_t c = lane & 7u;
-    uint4 x[8];
+    const uint32_t c = lane & (C - 1);
+    uint4 x[C];
 #pragma unroll
-    for (uint32_t q = 0; q < 8; ++q) {
-        const uint32_t i = q * 8 + (lane >> 3);
+    for (uint32_t q = 0; q < C; ++q) {
+        const uint32_t i = q * LPQ + (lane >> CS);
         if (i < nn)
-            x[q] = reinterpret_cast<const uint4 *>(bucket + (uint64_t)ws->idx[i] * kLineSlots)[c];
+            x[q] = reinterpret_cast<const uint4 *>(bucket + (uint64_t)ws->idx[i] * LS)[c];
     }
 #pragma unroll
-    for (uint32_t q = 0; q < 8; ++q) {
-        const uint32_t i = q * 8 + (lane >> 3);
+    for (uint32_t q = 0; q < C; ++q) {
+        const uint32_t i = q * LPQ + (lane >> CS);
         if (i < nn) {
             const uint64_t s0 = ((uint64_t)x[q].y << 32) | x[q].x;
             const uint64_t s1 = ((uint64_t)x[q].w << 32) | x[q].z;
@@ -444,16 +472,16 @@ __device__ __forceinline__ void coop_line_masks(WaveScratch *ws, const uint64_t 
                                ((uint32_t)((s0 & ~kDone) == mk) << 2) |
                                ((uint32_t)((s1 & ~kDone) == mk) << 3) |
                                ((uint32_t)(s0 >> 62) & 1u) << 4 | (((uint32_t)(s1 >> 62) & 1u) << 5);
-            ws->res[i * 8 + c] = (uint8_t)b;
+            ws->res[i * C + c] = (uint8_t)b;
         }
     }
     wave_lds_sync();
     if (need) {
-        const uint2 r = reinterpret_cast<const uint2 *>(ws->res)[rank];
+        const uint32_t *r = reinterpret_cast<const uint32_t *>(ws->res) + rank * (C / 4);
         uint32_t e = 0, m = 0, d = 0;
 #pragma unroll
-        for (uint32_t k = 0; k < 8; ++k) {
-            const uint32_t b = ((k < 4 ? r.x : r.y) >> (8 * (k & 3))) & 0xFFu;
+        for (uint32_t k = 0; k < C; ++k) {
+            const uint32_t b = (r[k >> 2] >> (8 * (k & 3))) & 0xFFu;
             e |= (b & 3u) << (2 * k);
             m |= ((b >> 2) & 3u) << (2 * k);
             d |= ((b >> 4) & 3u) << (2 * k);
@@ -555,15 +583,15 @@ __device__ __forceinline__ bool coop_rows_equal(WaveScratch *ws, const uint32_t 
 //
 // All 64 lanes must call this together (inactive lanes only help).  `d` is
 // the lane's vector descriptor (Vec::decode(smem, d) rebuilds it in any lane).
-template <class Vec>
+template <uint32_t LS, class Vec>
 __device__ __forceinline__ void find_or_put_wave(const TableView &t, WaveScratch *ws,
                                                  const uint32_t *smem, uint2 d, uint64_t h,
                                                  bool active, uint32_t &out_slot,
                                                  uint32_t &out_code, LaneCounters &cnt) {
     const uint64_t memo = kOcc | (h & kMemoMask);
-    const uint32_t start = (uint32_t)h & (kLineSlots - 1);
-    const uint32_t step = (uint32_t)(h >> 32) | 1u;
-    uint32_t line = (uint32_t)(h >> 4) & t.line_mask;
+    const uint32_t start = (uint32_t)h & (LS - 1);
+    const uint32_t step = probe_step(h, t.probe);
+    uint32_t line = (uint32_t)(h >> line_shift<LS>()) & t.line_mask;
     uint32_t rounds = 0, cand = 0, empty = 0, donem = 0;
     bool have_line = false, finished = !active;
     out_slot = kNoSlot;
@@ -579,11 +607,11 @@ __device__ __forceinline__ void find_or_put_wave(const TableView &t, WaveScratch
         const bool need = !finished && !have_line;
         if (__ballot(need)) {
             uint32_t e = 0, m = 0, dn = 0;
-            coop_line_masks(ws, t.bucket, need, line, memo, e, m, dn);
+            coop_line_masks<LS>(ws, t.bucket, need, line, memo, e, m, dn);
             if (need) {
-                empty = rotr16(e, start);
-                cand = rotr16(e | m, start);
-                donem = rotr16(dn, start);
+                empty = rotr_line<LS>(e, start);
+                cand = rotr_line<LS>(e | m, start);
+                donem = rotr_line<LS>(dn, start);
                 have_line = true;
             }
         }
@@ -594,11 +622,11 @@ __device__ __forceinline__ void find_or_put_wave(const TableView &t, WaveScratch
             if (cand == 0) {
                 have_line = false;
                 ++rounds;
-                line = (line + step) & t.line_mask;
+                line = next_line(line, rounds, step, t.probe, t.line_mask);
             } else {
                 const uint32_t k = __builtin_ctz(cand);
                 cand &= cand - 1;
-                slot = line * kLineSlots + ((start + k) & (kLineSlots - 1));
+                slot = line * LS + ((start + k) & (LS - 1));
                 kind = ((empty >> k) & 1u) ? 1u : 2u;
                 known_done = (donem >> k) & 1u;
             }

@@ -2,7 +2,7 @@
 //
 // Memory layout in HBM (section "Hash Table Design": separated data, 2^n
 // table, memoised hash, empty = 0):
-//   bucket : uint64[capacity]            8 B/slot, 16 slots per 128-B line
+//   bucket : uint64[capacity]            8 B/slot, 8/16/32 slots per line
 //   data   : uint32[capacity][W]         row of slot i at data + i*W
 //   status : DevStatus                   sticky error + counters
 #include <algorithm>
@@ -41,7 +41,7 @@ struct LdsRow {
 // flight per workgroup).  G > 1: one group of G lanes per operation (256/G in
 // flight, G rounds per tile).  Results go through LDS so that seen/index are
 // written coalesced.
-template <int G>
+template <int G, uint32_t LS>
 __global__ __launch_bounds__(kBlock) void k_find_or_put(TableView t, const uint32_t *__restrict__ in,
                                                         uint64_t n, uint8_t *__restrict__ seen,
                                                         uint32_t *__restrict__ index,
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_find_or_put(TableView t, const uint3
             __shared__ WaveScratch ws[kBlock / 64];
             const bool active = tid < rows;
             uint32_t slot, code;
-            find_or_put_wave<LdsRow>(t, &ws[tid / 64], smem, make_uint2(tid * stride, 0u),
+            find_or_put_wave<LS, LdsRow>(t, &ws[tid / 64], smem, make_uint2(tid * stride, 0u),
                                      hs[active ? tid : 0], active, slot, code, cnt);
             res_slot[tid] = slot;
             res_code[tid] = code;
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_find_or_put(TableView t, const uint3
                 const bool active = op < rows;
                 const uint32_t o = active ? op : 0;
                 uint32_t slot, code;
-                find_or_put<G>(t, LdsRow{tile + o * stride}, hs[o], active, slot, code, cnt);
+                find_or_put<G, LS>(t, LdsRow{tile + o * stride}, hs[o], active, slot, code, cnt);
                 if (active && (tid & (G - 1)) == 0) {
                     res_slot[op] = slot;
                     res_code[op] = code;
@@ -113,8 +113,9 @@ __global__ void k_zero_status(DevStatus *st) {
     st->cas_failures = 0;
 }
 
-// Per-block count of done slots.  Block b covers lines [b*256, b*256+256),
-// thread i one line.
+// Done slots are scanned in chunks of kLineSlots slots (any line width).
+// Per-block count of done slots.  Block b covers chunks [b*256, b*256+256),
+// thread i one chunk.
 __global__ __launch_bounds__(kBlock) void k_count_done(const uint64_t *bucket, uint64_t lines,
                                                        uint32_t *block_counts) {
     __shared__ uint32_t part[kBlock / 64];
@@ -227,13 +228,13 @@ lhs_status launch_find_or_put(lhs_table *t, const uint32_t *d_states, uint64_t n
     const dim3 grid(grid_for(n, kBlock)), block(kBlock);
     const TableView v = view(t);
     const uint32_t mw = div_magic(t->W);
-    switch (tps_find_or_put(t)) {
-    case 1: hipLaunchKernelGGL(k_find_or_put<1>, grid, block, lds, s, v, d_states, n, d_seen, d_index, mw); break;
-    case 4: hipLaunchKernelGGL(k_find_or_put<4>, grid, block, lds, s, v, d_states, n, d_seen, d_index, mw); break;
-    case 8: hipLaunchKernelGGL(k_find_or_put<8>, grid, block, lds, s, v, d_states, n, d_seen, d_index, mw); break;
-    case 16: hipLaunchKernelGGL(k_find_or_put<16>, grid, block, lds, s, v, d_states, n, d_seen, d_index, mw); break;
-    default: return LHS_EINVAL;
-    }
+    const lhs_status rc = with_shape(tps_find_or_put(t), t->line_slots, [&](auto G, auto L) {
+        hipLaunchKernelGGL((k_find_or_put<decltype(G)::value, decltype(L)::value>), grid, block, lds, s,
+                           v, d_states, n, d_seen, d_index, mw);
+        return LHS_OK;
+    });
+    if (rc != LHS_OK)
+        return rc;
     return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
 }
 
@@ -268,8 +269,24 @@ const char *lhs_strerror(lhs_status s) {
 }
 
 lhs_status lhs_create(uint64_t capacity, uint32_t state_words, lhs_table **out) {
+    if (!out || state_words < 1 || state_words > 32)
+        return LHS_EINVAL;
+    const lhs_config cfg = tuned_config(LHS_TUNE_TABLE, state_words, capacity);
+    return lhs_create_ex(capacity, state_words, &cfg, out);
+}
+
+lhs_status lhs_create_ex(uint64_t capacity, uint32_t state_words, const lhs_config *cfg,
+                         lhs_table **out) {
+    lhs_config c{16, LHS_PROBE_DOUBLE, 0, 0};
+    if (cfg) {
+        c = *cfg;
+        if (c.line_slots == 0)
+            c.line_slots = 16;
+    }
     if (!out || !is_pow2(capacity) || capacity < kLineSlots || capacity > (1ull << 32) ||
-        state_words < 1 || state_words > 32)
+        state_words < 1 || state_words > 32 || !valid_line_slots(c.line_slots) ||
+        c.probe > LHS_PROBE_QUADRATIC || !valid_tps(c.tps_find_or_put) || !valid_tps(c.tps_expand) ||
+        capacity < c.line_slots)
         return LHS_EINVAL;
     *out = nullptr;
     lhs_table *t = new (std::nothrow) lhs_table();
@@ -277,7 +294,11 @@ lhs_status lhs_create(uint64_t capacity, uint32_t state_words, lhs_table **out) 
         return LHS_ENOMEM;
     t->capacity = capacity;
     t->W = state_words;
-    t->lines = (uint32_t)(capacity / kLineSlots);
+    t->line_slots = c.line_slots;
+    t->probe = c.probe;
+    t->tps_fop = c.tps_find_or_put;
+    t->tps_exp = c.tps_expand;
+    t->lines = (uint32_t)(capacity / c.line_slots);
     t->max_rounds = std::min<uint32_t>(t->lines, kMaxRounds);
     t->seed = kDefaultSeed;
     if (hipGetDevice(&t->device) != hipSuccess) {
@@ -335,9 +356,20 @@ lhs_status lhs_find_or_put(lhs_table *t, const uint32_t *d_states, uint64_t n, u
 }
 
 lhs_status lhs_set_threads_per_state(lhs_table *t, uint32_t tps) {
-    if (!t || (tps != 0 && tps != 1 && tps != 4 && tps != 8 && tps != 16))
+    if (!t || !valid_tps(tps))
         return LHS_EINVAL;
-    t->tps = tps;
+    t->tps_fop = tps;
+    t->tps_exp = tps;
+    return LHS_OK;
+}
+
+lhs_status lhs_get_config(lhs_table *t, lhs_config *out) {
+    if (!t || !out)
+        return LHS_EINVAL;
+    out->line_slots = t->line_slots;
+    out->probe = t->probe;
+    out->tps_find_or_put = t->tps_fop;
+    out->tps_expand = t->tps_exp;
     return LHS_OK;
 }
 
@@ -423,8 +455,10 @@ lhs_status lhs_get_info(lhs_table *t, lhs_info *out) {
     std::memset(out, 0, sizeof(*out));
     out->capacity = t->capacity;
     out->state_words = t->W;
-    out->line_slots = kLineSlots;
-    out->threads_per_state = t->tps;   // 0 = per-kernel defaults
+    out->line_slots = t->line_slots;
+    out->probe = t->probe;
+    out->tps_find_or_put = tps_find_or_put(t);
+    out->tps_expand = tps_expand(t);
     out->hash_seed = t->seed;
     out->wait_hits = st.wait_hits;
     out->cas_failures = st.cas_failures;

@@ -16,7 +16,7 @@ using namespace lhs;
 namespace {
 
 // Expand frontier[0, n_front) of one model (one BFS level).
-template <int G>
+template <int G, uint32_t LS>
 __global__ __launch_bounds__(kExpandBlock) void k_expand(TableView t, ModelView m,
                                                          const uint32_t *__restrict__ front,
                                                          uint32_t n_front, uint32_t *__restrict__ next,
@@ -26,7 +26,7 @@ __global__ __launch_bounds__(kExpandBlock) void k_expand(TableView t, ModelView 
     for (uint64_t base = (uint64_t)blockIdx.x * kExpandBlock; base < n_front;
          base += (uint64_t)gridDim.x * kExpandBlock) {
         const uint32_t rows = (uint32_t)min<uint64_t>(kExpandBlock, n_front - base);
-        if (expand_tile<G, false, true>(smem, t, m, front, base, rows, next, lc, limit, tcap))
+        if (expand_tile<G, LS, false, true>(smem, t, m, front, base, rows, next, lc, limit, tcap))
             break;
     }
     expand_end(lc);
@@ -110,13 +110,13 @@ lhs_status launch_expand(lhs_table *t, const TableView &tv, const ModelView &mv,
     const uint32_t tc = trans_lds_entries(mv.P, mv.L, mv.K);
     const size_t lds = expand_lds_bytes(mv.W, tc);
     const dim3 grid(std::max(blocks, 1u)), block(kExpandBlock);
-    switch (tps_expand(t)) {
-    case 1: hipLaunchKernelGGL(k_expand<1>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit, tc); break;
-    case 4: hipLaunchKernelGGL(k_expand<4>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit, tc); break;
-    case 8: hipLaunchKernelGGL(k_expand<8>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit, tc); break;
-    case 16: hipLaunchKernelGGL(k_expand<16>, grid, block, lds, s, tv, mv, front, n_front, next, lc, limit, tc); break;
-    default: return LHS_EINVAL;
-    }
+    const lhs_status rc = with_shape(tps_expand(t), t->line_slots, [&](auto G, auto L) {
+        hipLaunchKernelGGL((k_expand<decltype(G)::value, decltype(L)::value>), grid, block, lds, s, tv, mv,
+                           front, n_front, next, lc, limit, tc);
+        return LHS_OK;
+    });
+    if (rc != LHS_OK)
+        return rc;
     return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
 }
 

@@ -77,6 +77,7 @@ uint64_t table_bytes(uint64_t capacity, uint32_t W) {
 
 struct reach_server {
     reach_server_opts opts{};
+    lhs_config cfg{};           // shape of every query table (one launch serves all)
     int device = 0;
     hipStream_t stream = nullptr;
     std::thread worker;
@@ -169,7 +170,7 @@ bool acquire_table(reach_server *s, Query *q) {
     if (s->bytes_alloc + q->bytes > s->opts.budget_bytes)
         return false;
     lhs_table *t = nullptr;
-    if (lhs_create(q->capacity, q->W, &t) != LHS_OK || ensure_bfs_buffers(t) != LHS_OK) {
+    if (lhs_create_ex(q->capacity, q->W, &s->cfg, &t) != LHS_OK || ensure_bfs_buffers(t) != LHS_OK) {
         lhs_destroy(t);
         return false;
     }
@@ -236,8 +237,8 @@ lhs_status start_queries(reach_server *s, const std::vector<Query *> &qs) {
         hipMemcpyAsync(s->d_slots, s->h_slots, n * sizeof(BatchSlot), hipMemcpyHostToDevice, s->stream) !=
             hipSuccess)
         return LHS_EDEVICE;
-    hipLaunchKernelGGL(k_insert_roots, dim3(n), dim3(64), 0, s->stream, s->d_slots, s->d_roots, s->d_root_off,
-                       n);
+    if (launch_insert_roots(s->cfg.line_slots, s->stream, s->d_slots, s->d_roots, s->d_root_off, n) != LHS_OK)
+        return LHS_EDEVICE;
     // host buffers are reused by the next step: wait for the copies
     return (hipGetLastError() == hipSuccess && hipStreamSynchronize(s->stream) == hipSuccess) ? LHS_OK
                                                                                             : LHS_EDEVICE;
@@ -275,8 +276,9 @@ lhs_status step_queries(reach_server *s, std::vector<Query *> &finished) {
             hipSuccess)
         return LHS_EDEVICE;
     hipLaunchKernelGGL(k_zero_step, dim3((na + 255) / 256), dim3(256), 0, s->stream, s->d_lc, s->d_st, na);
-    launch_expand_multi(tps, tiles, maxW, tcap, s->stream, s->d_slots, s->d_begin, na);
-    if (hipGetLastError() != hipSuccess ||
+    if (launch_expand_multi(tps, s->cfg.line_slots, tiles, maxW, tcap, s->stream, s->d_slots, s->d_begin, na) !=
+            LHS_OK ||
+        hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(s->h_lc, s->d_lc, na * sizeof(LevelCounters), hipMemcpyDeviceToHost, s->stream) !=
             hipSuccess ||
         hipMemcpyAsync(s->h_st, s->d_st, na * sizeof(DevStatus), hipMemcpyDeviceToHost, s->stream) !=
@@ -448,8 +450,18 @@ lhs_status reach_server_create(const reach_server_opts *o, reach_server **out) {
         s->opts.budget_bytes = kDefaultBudget;
     if (!s->opts.max_active)
         s->opts.max_active = kDefaultMaxActive;
-    if (s->opts.capacity && (!is_pow2(s->opts.capacity) || s->opts.capacity < kLineSlots ||
-                             s->opts.capacity > (1ull << 32))) {
+    const lhs_config &c = s->opts.table;
+    if (c.line_slots == 0 && c.probe == 0 && c.tps_find_or_put == 0 && c.tps_expand == 0) {
+        s->cfg = tuned_config(LHS_TUNE_BATCH, 32, s->opts.capacity ? s->opts.capacity : (1ull << 21));
+    } else {
+        s->cfg = c;
+        if (s->cfg.line_slots == 0)
+            s->cfg.line_slots = 16;
+    }
+    if ((s->opts.capacity && (!is_pow2(s->opts.capacity) || s->opts.capacity < kLineSlots ||
+                              s->opts.capacity > (1ull << 32))) ||
+        !valid_line_slots(s->cfg.line_slots) || s->cfg.probe > LHS_PROBE_QUADRATIC ||
+        !valid_tps(s->cfg.tps_find_or_put) || !valid_tps(s->cfg.tps_expand)) {
         delete s;
         return LHS_EINVAL;
     }

@@ -65,23 +65,29 @@ def check_table_invariants(table, sample=None, seed=0):
         assert len(np.unique(rows, axis=0)) == len(rows), "duplicate vector"
     h = table_hash(rows, info["hash_seed"])
     assert np.array_equal(slots[idx] & MEMO, h & MEMO), "memo differs from the row hash"
-    lines = info["capacity"] // 16
-    line = (h >> np.uint64(4)) & np.uint64(lines - 1)
-    start = h & np.uint64(15)
+    LS = info["line_slots"]
+    lines = info["capacity"] // LS
+    shift = np.uint64(LS.bit_length() - 1)
+    line = (h >> shift) & np.uint64(lines - 1)
+    start = h & np.uint64(LS - 1)
+    # line-to-line moves: double hashing (odd step from the high half),
+    # linear (+1) or quadratic (the r-th move goes r lines on)
     step = (h >> np.uint64(32)) | np.uint64(1)
+    probe = info["probe"]
     pending = np.ones(len(idx), dtype=bool)
     target = idx.astype(np.uint64)
-    for _ in range(lines):
+    for r in range(1, lines + 1):
         if not pending.any():
             break
-        for k in range(16):
-            slot = line * np.uint64(16) + ((start + np.uint64(k)) & np.uint64(15))
+        for k in range(LS):
+            slot = line * np.uint64(LS) + ((start + np.uint64(k)) & np.uint64(LS - 1))
             hit = pending & (slot == target)
             before = pending & ~hit
             assert np.all(slots[slot[before].astype(np.int64)] != 0), "empty slot ahead of a stored row"
             pending &= ~hit
         with np.errstate(over="ignore"):
-            line = (line + step) & np.uint64(lines - 1)
+            move = step if probe == 0 else np.uint64(1 if probe == 1 else r)
+            line = (line + move) & np.uint64(lines - 1)
     assert not pending.any(), "stored row not on its probe sequence"
     return all_rows, all_idx
 

@@ -8,6 +8,8 @@
 * the raw stream: 2^26 rows of 16 words (2^25 distinct, each twice) into a
   2^28-slot table, as one call and as 2^22-row calls, against the sequential
   oracle run on the same stream.
+Both run with the package's tuning table loaded (the shapes the benchmark
+times) and with the default shape.
 """
 import json
 import os
@@ -32,15 +34,29 @@ def lhs():
     return paper_1004_2772_amd
 
 
-@pytest.mark.parametrize("tps", [0, 4])
-def test_big_model_2p27(lhs, tps):
-    print(f"\n[full] big model, cap 2^27, tps={tps}", flush=True)
+def _table(lhs, shape, capacity, W):
+    """'tuned': lhs_create with the package's tuning table loaded (as the
+    benchmark runs); 'default': the default shape."""
+    if shape == "tuned":
+        lhs.tune_load_default()
+        try:
+            t = lhs.Table(capacity, W)
+        finally:
+            lhs.tune_clear()
+    else:
+        t = lhs.Table(capacity, W, lhs.config())
+    print(f"table shape {t.config()}", flush=True)
+    return t
+
+
+@pytest.mark.parametrize("shape", ["tuned", "default"])
+def test_big_model_2p27(lhs, shape):
+    print(f"\n[full] big model, cap 2^27, {shape} shape", flush=True)
     with open(os.path.join(GOLDEN, "big_model.json")) as f:
         g = json.load(f)
     m = gen.big_model()
     assert m.cap == g["cap"] == 1 << 27
-    with lhs.Table(gen.BIG_TABLE_SLOTS, m.W) as t:
-        t.set_threads_per_state(tps)
+    with _table(lhs, shape, gen.BIG_TABLE_SLOTS, m.W) as t:
         r = lhs.reach_explore(m, table=t)
         print(f"gpu {r.gpu_ms:.1f} ms, {r.total} states", flush=True)
         assert (r.total, r.n_levels, r.level_counts, r.edges, r.deadlocks, r.capped) == \
@@ -59,17 +75,17 @@ def full_stream():
     return stream, ids, distinct
 
 
-@pytest.mark.parametrize("batch", [1 << 26, 1 << 22])
-def test_stream_2p26(lhs, full_stream, batch):
+@pytest.mark.parametrize("shape,batch", [("tuned", 1 << 26), ("default", 1 << 26), ("tuned", 1 << 22)])
+def test_stream_2p26(lhs, full_stream, shape, batch):
     import torch
     stream, o_id, distinct = full_stream
-    print(f"\n[full] stream 2^26, batch {batch}", flush=True)
+    print(f"\n[full] stream 2^26, batch {batch}, {shape} shape", flush=True)
     n = len(stream)
     dev = dev_u32(stream)
     seen = torch.empty(n, dtype=torch.uint8, device="cuda")
     idx = torch.empty(n, dtype=torch.int32, device="cuda")
     bounds = []
-    with lhs.Table(gen.STREAM_TABLE_SLOTS, gen.STREAM_W) as t:
+    with _table(lhs, shape, gen.STREAM_TABLE_SLOTS, gen.STREAM_W) as t:
         for lo in range(0, n, batch):
             hi = min(n, lo + batch)
             t.find_or_put(dev[lo:hi], seen[lo:hi], idx[lo:hi])
