@@ -13,8 +13,10 @@ Extra legs in the same JSON line:
                  average duration (HIP events on the launch stream), against
                  the 8 TB/s HBM peak; hardware traffic from committed rocprofv3
                  counter summaries when they match the current kernel source.
-  probes       : measured ceilings: random 128-B line reads (per lane and
-                 8-lane cooperative) and random 64-bit CAS throughput.
+  probes       : measured ceilings: random line reads of 64/128/256 bytes
+                 (cooperative lanes, and 128 B by one lane) and random 64-bit
+                 CAS throughput; the find-or-put's algorithmic GB/s over the
+                 ceiling at its table's line width.
   bfs          : level-synchronous BFS of the 12-process x 16-local synthetic
                  model capped at 2^27 states (states/s, edges/s).
   batch        : the 64-model mix (2-16 processes, widths 4-32, 10^3-10^6
@@ -239,15 +241,15 @@ def main():
         sink = torch.zeros(1, dtype=torch.int64, device=dev)
         buf = torch.empty(1 << 32, dtype=torch.int32, device=dev)     # 16 GiB
         probes = {}
-        for lanes in (1, 8):
-            reads = 1 << 27
-            lhs.probe_random_lines(buf, lanes, reads, 1, sink)
+        for lb, lanes in ((128, 1), (64, 4), (128, 8), (256, 16)):
+            reads = (1 << 34) // lb // 8          # 2 GiB of lines per probe
+            lhs.probe_random_lines(buf, lb, lanes, reads, 1, sink)
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
-            lhs.probe_random_lines(buf, lanes, reads, 2, sink)
+            lhs.probe_random_lines(buf, lb, lanes, reads, 2, sink)
             b.record(stream)
             torch.cuda.synchronize()
-            probes[f"random_128B_lines_{lanes}lane_GBs"] = round(reads * 128 / (a.elapsed_time(b) / 1e3) / 1e9, 1)
+            probes[f"random_{lb}B_lines_{lanes}lane_GBs"] = round(reads * lb / (a.elapsed_time(b) / 1e3) / 1e9, 1)
         del buf
         slots = torch.zeros(1 << 28, dtype=torch.int64, device=dev)
         ops = 1 << 26
@@ -260,8 +262,10 @@ def main():
         torch.cuda.synchronize()
         probes["random_cas64_Gops"] = round(ops / (a.elapsed_time(b) / 1e3) / 1e9, 3)
         del slots
-        probes["fop_frac_of_random_line_1lane"] = round(
-            achieved / probes["random_128B_lines_1lane_GBs"], 4)
+        lb = 8 * info["line_slots"]
+        ceiling = probes[f"random_{lb}B_lines_{lb // 16}lane_GBs"]
+        probes["fop_frac_of_random_line"] = round(achieved / ceiling, 4)
+        probes["fop_frac_of_random_line_ceiling"] = f"random_{lb}B_lines_{lb // 16}lane_GBs"
         out["probes"] = probes
         log(f"probes: {probes}")
 

@@ -378,13 +378,14 @@ lhs_status reach_server_destroy(reach_server *s);
  * write to keep their loads alive.
  * ---------------------------------------------------------------------- */
 
-/* n_reads reads of uniformly random 128-byte-aligned lines of d_buf
- * (buf_bytes / 128 must be a power of two, d_buf 128-byte aligned), each line
- * read by one lane (lanes_per_line = 1, 8 x 16-byte loads) or by eight lanes
- * (lanes_per_line = 8, one 16-byte load each). */
-lhs_status lhs_probe_random_lines(const void *d_buf, uint64_t buf_bytes, uint32_t lanes_per_line,
-                                  uint64_t n_reads, uint64_t seed, uint64_t *d_sink,
-                                  void *hip_stream);
+/* n_reads reads of uniformly random lines of line_bytes (64, 128 or 256)
+ * bytes of d_buf (buf_bytes / line_bytes must be a power of two, d_buf
+ * line_bytes-aligned), each line read by one lane (lanes_per_line = 1,
+ * line_bytes/16 sixteen-byte loads) or by line_bytes/16 cooperating lanes
+ * (lanes_per_line = line_bytes/16, one 16-byte load each). */
+lhs_status lhs_probe_random_lines(const void *d_buf, uint64_t buf_bytes, uint32_t line_bytes,
+                                  uint32_t lanes_per_line, uint64_t n_reads, uint64_t seed,
+                                  uint64_t *d_sink, void *hip_stream);
 
 /* n_ops 64-bit compare-and-swap operations (0 -> random value with bit 63
  * set) at uniformly random slots of d_slots (n_slots a power of two). */

@@ -155,7 +155,7 @@ def lib() -> ctypes.CDLL:
         L.reach_server_wait.argtypes = [p, u64, ctypes.POINTER(ReachResultC), ctypes.POINTER(QueryTimes)]
         L.reach_server_get_stats.argtypes = [p, ctypes.POINTER(ServerStats)]
         L.reach_server_destroy.argtypes = [p]
-        L.lhs_probe_random_lines.argtypes = [p, u64, u32, u64, u64, p, p]
+        L.lhs_probe_random_lines.argtypes = [p, u64, u32, u32, u64, u64, p, p]
         L.lhs_probe_random_cas.argtypes = [p, u64, u64, u64, p, p]
         L.lhs_probe_copy.argtypes = [p, p, u64, p]
         for name in ("lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_copy",
@@ -453,10 +453,11 @@ class Server:
         self.close()
 
 
-def probe_random_lines(buf, lanes_per_line: int, n_reads: int, seed: int, sink, stream=None):
-    _check(lib().lhs_probe_random_lines(_ptr(buf), buf.numel() * buf.element_size(), lanes_per_line,
-                                        n_reads, seed, _ptr(sink), _stream_handle(stream)),
-           "lhs_probe_random_lines")
+def probe_random_lines(buf, line_bytes: int, lanes_per_line: int, n_reads: int, seed: int, sink,
+                       stream=None):
+    _check(lib().lhs_probe_random_lines(_ptr(buf), buf.numel() * buf.element_size(), line_bytes,
+                                        lanes_per_line, n_reads, seed, _ptr(sink),
+                                        _stream_handle(stream)), "lhs_probe_random_lines")
 
 
 def probe_random_cas(slots, n_ops: int, seed: int, sink, stream=None):

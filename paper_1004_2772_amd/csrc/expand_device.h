@@ -43,16 +43,19 @@ struct SuccVec {
 //   tr       [tcap] u64  the model's packed transitions (when they fit)
 //   masks    [256] u64   enabled transitions of each tile state (P*K <= 64)
 //   offs     [258]       exclusive prefix of successor counts (+ total)
-//   queue    [kQueue]    (P*K > 64) enabled (state, process, transition)
+//     (queue [kQueue]    enabled (state, process, transition) when P*K > 64,
+//                        in the same words as masks/offs)
 //   succ_cnt [256]       successors per tile state (edges, deadlocks)
 //   hq       [256] u64   hash of each successor of the current pass
 //   d0, d1   [256]       successor descriptors of the pass
 //   nbuf     [kNewBuf]   slots of new states, flushed to next[] in bulk
-constexpr uint32_t kNewBuf = 1024;
+constexpr uint32_t kNewBuf = 2048;
 constexpr uint32_t kEagerRoom = 1u << 22;
+constexpr uint32_t kMaskArea = 2 * kExpandBlock + 258;
+static_assert(kQueue <= kMaskArea, "queue shares the mask area");
 __host__ __device__ constexpr uint32_t expand_lds_words(uint32_t W, uint32_t tcap = 0) {
-    return kExpandBlock * (W | 1u) + 2 * tcap + 2 * kExpandBlock + 258 + kQueue + kExpandBlock +
-           2 * kExpandBlock + 2 * kExpandBlock + kNewBuf;
+    return kExpandBlock * (W | 1u) + 2 * tcap + kMaskArea + kExpandBlock + 2 * kExpandBlock +
+           2 * kExpandBlock + kNewBuf;
 }
 
 // Transitions that fit this many LDS entries are staged in LDS.
@@ -68,6 +71,9 @@ __host__ __device__ inline uint32_t trans_lds_entries(uint32_t P, uint32_t L, ui
 static __shared__ const uint2 *s_trans_staged;
 // Edge / deadlock counts accumulated over tiles (deferred mode).
 static __shared__ unsigned long long s_acc_edges, s_acc_dead;
+// New-state buffer fill, its reserved base in next[], and the level's abort
+// / near-the-cap flags as this workgroup last saw them.
+static __shared__ uint32_t s_nnew, s_nbase, s_abort, s_eager;
 
 // Call once at kernel start, before the first expand_tile.
 __device__ __forceinline__ void expand_begin() {
@@ -75,13 +81,64 @@ __device__ __forceinline__ void expand_begin() {
         s_trans_staged = nullptr;
         s_acc_edges = 0;
         s_acc_dead = 0;
+        s_nnew = 0;
+        s_abort = 0;
+        s_eager = 0;
     }
 }
 
-// Deferred mode: add the workgroup's accumulated counts to lc (one atomic
-// each).  Call by all threads after the last expand_tile of the launch.
-__device__ __forceinline__ void expand_end(LevelCounters *lc) {
+// The new-state buffer in the expansion's LDS layout.
+__device__ __forceinline__ uint32_t *expand_nbuf(uint32_t *smem, uint32_t W, uint32_t tcap) {
+    return smem + expand_lds_words(W, tcap) - kNewBuf;
+}
+
+// Append the buffered new slots to next[] with one atomic on the level's
+// cursor (block-wide, uniform call).  Flags the level aborted when the cursor
+// passes `limit`; within kEagerRoom of it the workgroup turns eager (flushes
+// every pass and rereads the abort flag).
+template <bool COHERENT>
+__device__ __forceinline__ void flush_new_slots(const uint32_t *nbuf, uint32_t *next, LevelCounters *lc,
+                                                uint32_t limit) {
     __syncthreads();
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nn = s_nnew;
+    if (tid == 0) {
+        if (nn) {
+            const uint32_t b = atomicAdd(&lc->n_next, nn);
+            s_nbase = b;
+            if ((uint64_t)b + nn > limit) {
+                __hip_atomic_store(&lc->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_abort = 1;
+            } else if (limit != 0xFFFFFFFFu && (uint64_t)b + nn + kEagerRoom > limit) {
+                s_eager = 1;
+            }
+        }
+        if (s_eager && !s_abort)
+            s_abort = __hip_atomic_load(&lc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (nn) {
+        const uint32_t b = s_nbase;
+        for (uint32_t i = tid; i < nn; i += kExpandBlock) {
+            if (COHERENT)
+                st_coherent(next + b + i, nbuf[i]);
+            else
+                next[b + i] = nbuf[i];
+        }
+        __syncthreads();
+        if (tid == 0)
+            s_nnew = 0;
+        __syncthreads();
+    }
+}
+
+// Deferred mode: append the workgroup's remaining new states and add its
+// accumulated edge/deadlock counts to lc.  Call by all threads after the
+// last expand_tile of the launch (also after an aborted tile: every claimed
+// slot must be listed in next[] for the rollback).
+__device__ __forceinline__ void expand_end(uint32_t *smem, uint32_t W, uint32_t tcap, uint32_t *next,
+                                           LevelCounters *lc, uint32_t limit) {
+    flush_new_slots<false>(expand_nbuf(smem, W, tcap), next, lc, limit);
     if (threadIdx.x == 0) {
         if (s_acc_edges)
             atomicAdd(&lc->edges, s_acc_edges);
@@ -129,9 +186,10 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
 // agent-scope (cross-XCD coherent) accesses.  Needed when the previous level
 // was produced inside the same launch by other workgroups (the persistent
 // driver); across launches the kernel boundary already makes them visible.
-// DEFER: edge/deadlock counts stay in LDS until expand_end (single-model
-// launches, whose counters are read only after the launch); otherwise they
-// are added to lc at the end of every tile.
+// DEFER: new states stay buffered across tiles (flushed when the buffer
+// nears full) and edge/deadlock counts stay in LDS until expand_end
+// (single-model launches, whose workgroups run many tiles of one level);
+// otherwise both go out at the end of every tile.
 template <int G, uint32_t LS, bool COHERENT = false, bool DEFER = false>
 __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, const ModelView &m,
                                             const uint32_t *__restrict__ front, uint64_t base,
@@ -143,14 +201,14 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
     uint2 *tr_lds = reinterpret_cast<uint2 *>(tile + kBlock * stride);
     uint64_t *masks = reinterpret_cast<uint64_t *>(tr_lds + tcap);
     uint32_t *offs = reinterpret_cast<uint32_t *>(masks + kBlock);
-    uint32_t *queue = offs + 258;
-    uint32_t *succ_cnt = queue + kQueue;
+    uint32_t *queue = reinterpret_cast<uint32_t *>(masks);     // wide models only
+    uint32_t *succ_cnt = reinterpret_cast<uint32_t *>(masks) + kMaskArea;
     uint64_t *hq = reinterpret_cast<uint64_t *>(succ_cnt + kBlock);   // 8-byte aligned
     uint32_t *d0 = reinterpret_cast<uint32_t *>(hq + kBlock);
     uint32_t *d1 = d0 + kBlock;
     uint32_t *nbuf = d1 + kBlock;
-    __shared__ uint32_t s_tail, s_abort, s_eager, s_wtot[kBlock / 64], s_nnew, s_nbase;
-    __shared__ WaveScratch ws[kBlock / 64];
+    __shared__ uint32_t s_tail, s_wtot[kBlock / 64];
+    __shared__ WaveScratch<LS> ws[kBlock / 64];
 
     constexpr uint32_t NG = kBlock / G;
     LaneCounters cnt;
@@ -164,7 +222,6 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
     const bool restage = tr_in_lds && s_trans_staged != m.trans;
     if (tid == 0) {
         s_tail = 0;
-        s_nnew = 0;
         s_abort = __hip_atomic_load(&lc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t nn = __hip_atomic_load(&lc->n_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_eager = limit != 0xFFFFFFFFu && (uint64_t)nn + kEagerRoom > limit;
@@ -209,39 +266,7 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
         return true;
     const uint2 *tr = tr_in_lds ? tr_lds : m.trans;
 
-    // ---- append the buffered new slots to next[] (block-wide) --------------
-    auto flush_new = [&]() {
-        __syncthreads();
-        const uint32_t nn = s_nnew;
-        if (tid == 0) {
-            if (nn) {
-                const uint32_t b = atomicAdd(&lc->n_next, nn);
-                s_nbase = b;
-                if ((uint64_t)b + nn > limit) {
-                    __hip_atomic_store(&lc->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    s_abort = 1;
-                } else if (limit != 0xFFFFFFFFu && (uint64_t)b + nn + kEagerRoom > limit) {
-                    s_eager = 1;
-                }
-            }
-            if (s_eager && !s_abort)
-                s_abort = __hip_atomic_load(&lc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __syncthreads();
-        if (nn) {
-            const uint32_t b = s_nbase;
-            for (uint32_t i = tid; i < nn; i += kBlock) {
-                if (COHERENT)
-                    st_coherent(next + b + i, nbuf[i]);
-                else
-                    next[b + i] = nbuf[i];
-            }
-            __syncthreads();
-            if (tid == 0)
-                s_nnew = 0;
-            __syncthreads();
-        }
-    };
+    auto flush_new = [&]() { flush_new_slots<COHERENT>(nbuf, next, lc, limit); };
     // ---- find-or-put of successors d0/d1/hq[0, take); new slots to nbuf ----
     auto fop_pass = [&](uint32_t take) {
         for (uint32_t r = 0; r < G; ++r) {
@@ -394,7 +419,9 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
             }
         }
     }
-    flush_new();
+    // a workgroup that runs several tiles of one level keeps its buffer
+    if constexpr (!DEFER)
+        flush_new();
     // ---- edge and deadlock counts of the tile -------------------------------
     const uint32_t mine = tid < rows ? succ_cnt[tid] : 0u;
     const uint32_t e32 = wave_sum(mine), d32 = wave_sum(tid < rows && mine == 0);

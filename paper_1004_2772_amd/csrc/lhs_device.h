@@ -423,12 +423,13 @@ __device__ __forceinline__ void find_or_put(const TableView &t, const Vec &v, ui
 // come back through the same per-wavefront LDS area.  The helpers need the
 // owner's vector: `Vec` has a two-word descriptor any lane can decode.
 
+template <uint32_t LS>
 struct WaveScratch {         // one per wavefront, in LDS
+    uint64_t key[64];        // memo per rank (line snapshots)
     uint32_t idx[64];        // listed line / slot per rank
     uint32_t aux[64];        // second word (row descriptor y)
-    uint64_t key[64];        // memo per rank (line snapshots)
     uint32_t desc[64];       // row descriptor x per rank
-    uint8_t res[64 * 16];    // per (rank, helper lane) result bits
+    uint8_t res[64 * (LS / 2 > 8 ? LS / 2 : 8)];   // per (rank, helper lane) result bits
 };
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -440,7 +441,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // for every lane with `need`; other lanes only help.  Wavefront-uniform call.
 // C = LS/2 helper lanes per line, 64/C lines per load instruction, C rounds.
 template <uint32_t LS>
-__device__ __forceinline__ void coop_line_masks(WaveScratch *ws, const uint64_t *bucket, bool need,
+__device__ __forceinline__ void coop_line_masks(WaveScratch<LS> *ws, const uint64_t *bucket, bool need,
                                                 uint32_t line, uint64_t memo, uint32_t &empty,
                                                 uint32_t &match, uint32_t &done) {
     constexpr uint32_t C = LS / 2, CS = line_shift<LS>() - 1, LPQ = 64 / C;
@@ -495,8 +496,8 @@ __device__ __forceinline__ void coop_line_masks(WaveScratch *ws, const uint64_t 
 
 // Write the rows of every lane with `go` (slot, descriptor); eight lanes per
 // row, 64-bit coherent stores when W is even, 32-bit otherwise.
-template <class Vec>
-__device__ __forceinline__ void coop_write_rows(WaveScratch *ws, const uint32_t *smem, uint32_t *data,
+template <class Vec, class WS>
+__device__ __forceinline__ void coop_write_rows(WS *ws, const uint32_t *smem, uint32_t *data,
                                                 uint32_t W, bool go, uint32_t slot, uint2 d) {
     const uint32_t lane = __lane_id();
     const uint64_t gm = __ballot(go);
@@ -529,8 +530,8 @@ __device__ __forceinline__ void coop_write_rows(WaveScratch *ws, const uint32_t 
 
 // Compare the stored rows of every lane with `go` against its vector;
 // returns equality for those lanes.  Same layout as coop_write_rows.
-template <class Vec>
-__device__ __forceinline__ bool coop_rows_equal(WaveScratch *ws, const uint32_t *smem,
+template <class Vec, class WS>
+__device__ __forceinline__ bool coop_rows_equal(WS *ws, const uint32_t *smem,
                                                 const uint32_t *data, uint32_t W, bool go,
                                                 uint32_t slot, uint2 d) {
     const uint32_t lane = __lane_id();
@@ -584,7 +585,7 @@ __device__ __forceinline__ bool coop_rows_equal(WaveScratch *ws, const uint32_t 
 // All 64 lanes must call this together (inactive lanes only help).  `d` is
 // the lane's vector descriptor (Vec::decode(smem, d) rebuilds it in any lane).
 template <uint32_t LS, class Vec>
-__device__ __forceinline__ void find_or_put_wave(const TableView &t, WaveScratch *ws,
+__device__ __forceinline__ void find_or_put_wave(const TableView &t, WaveScratch<LS> *ws,
                                                  const uint32_t *smem, uint2 d, uint64_t h,
                                                  bool active, uint32_t &out_slot,
                                                  uint32_t &out_code, LaneCounters &cnt) {

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_find_or_put(TableView t, const uint3
             hs[tid] = hash_vec(LdsRow{tile + tid * stride}, W, t.seed);
         __syncthreads();
         if constexpr (G == 1) {
-            __shared__ WaveScratch ws[kBlock / 64];
+            __shared__ WaveScratch<LS> ws[kBlock / 64];
             const bool active = tid < rows;
             uint32_t slot, code;
             find_or_put_wave<LS, LdsRow>(t, &ws[tid / 64], smem, make_uint2(tid * stride, 0u),

@@ -1,8 +1,9 @@
 // Roofline probes: the memory-system ceilings the find-or-put kernel is
 // measured against.
-//   random lines : uniformly random 128-byte-aligned lines of a large buffer,
-//                  read either by one lane (8 x 16 B, the find-or-put access
-//                  pattern) or by 8 cooperating lanes (16 B each).
+//   random lines : uniformly random line-aligned lines (64, 128 or 256 bytes)
+//                  of a large buffer, read either by one lane (16-byte loads,
+//                  one after another) or by line/16 cooperating lanes (16 B
+//                  each, one coalesced access: the find-or-put pattern).
 //   random CAS   : 64-bit compare-and-swap at uniformly random slots.
 //   copy         : a plain streaming copy, the reference for hardware
 //                  traffic counters.
@@ -19,6 +20,8 @@ __device__ __forceinline__ uint64_t splitmix(uint64_t z) {
     return z ^ (z >> 31);
 }
 
+// C = 16-byte chunks per line (4, 8, 16).
+template <uint32_t C>
 __global__ __launch_bounds__(256) void k_probe_lines_lane(const uint4 *buf, uint64_t n_lines,
                                                           uint64_t n_reads, uint64_t seed,
                                                           uint64_t *sink) {
@@ -26,9 +29,9 @@ __global__ __launch_bounds__(256) void k_probe_lines_lane(const uint4 *buf, uint
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_reads;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t line = splitmix(seed ^ i) & (n_lines - 1);
-        const uint4 *p = buf + line * 8;
+        const uint4 *p = buf + line * C;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (uint32_t q = 0; q < C; ++q) {
             const uint4 x = p[q];
             acc ^= x.x ^ x.y ^ x.z ^ x.w;
         }
@@ -37,15 +40,17 @@ __global__ __launch_bounds__(256) void k_probe_lines_lane(const uint4 *buf, uint
         sink[0] = acc;
 }
 
+template <uint32_t C>
 __global__ __launch_bounds__(256) void k_probe_lines_coop(const uint4 *buf, uint64_t n_lines,
                                                           uint64_t n_reads, uint64_t seed,
                                                           uint64_t *sink) {
+    constexpr uint32_t CS = C == 4 ? 2u : (C == 8 ? 3u : 4u);
     uint32_t acc = 0;
-    const uint32_t sub = threadIdx.x & 7u;
-    for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3; i < n_reads;
-         i += ((uint64_t)gridDim.x * blockDim.x) >> 3) {
+    const uint32_t sub = threadIdx.x & (C - 1);
+    for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> CS; i < n_reads;
+         i += ((uint64_t)gridDim.x * blockDim.x) >> CS) {
         const uint64_t line = splitmix(seed ^ i) & (n_lines - 1);
-        const uint4 x = buf[line * 8 + sub];
+        const uint4 x = buf[line * C + sub];
         acc ^= x.x ^ x.y ^ x.z ^ x.w;
     }
     if (acc == 0x9E3779B9u)
@@ -82,20 +87,27 @@ uint32_t probe_grid(uint64_t items) {
 
 extern "C" {
 
-lhs_status lhs_probe_random_lines(const void *d_buf, uint64_t buf_bytes, uint32_t lanes_per_line,
-                                  uint64_t n_reads, uint64_t seed, uint64_t *d_sink,
-                                  void *hip_stream) {
-    const uint64_t n_lines = buf_bytes / 128;
-    if (!d_buf || !d_sink || !lhs::is_pow2(n_lines) || (lanes_per_line != 1 && lanes_per_line != 8) ||
-        ((uintptr_t)d_buf & 127))
+lhs_status lhs_probe_random_lines(const void *d_buf, uint64_t buf_bytes, uint32_t line_bytes,
+                                  uint32_t lanes_per_line, uint64_t n_reads, uint64_t seed,
+                                  uint64_t *d_sink, void *hip_stream) {
+    if (line_bytes != 64 && line_bytes != 128 && line_bytes != 256)
+        return LHS_EINVAL;
+    const uint64_t n_lines = buf_bytes / line_bytes;
+    const uint32_t C = line_bytes / 16;
+    if (!d_buf || !d_sink || !lhs::is_pow2(n_lines) || (lanes_per_line != 1 && lanes_per_line != C) ||
+        ((uintptr_t)d_buf & (line_bytes - 1)))
         return LHS_EINVAL;
     hipStream_t s = (hipStream_t)hip_stream;
-    if (lanes_per_line == 1)
-        hipLaunchKernelGGL(k_probe_lines_lane, dim3(probe_grid(n_reads)), dim3(256), 0, s,
-                           (const uint4 *)d_buf, n_lines, n_reads, seed, d_sink);
-    else
-        hipLaunchKernelGGL(k_probe_lines_coop, dim3(probe_grid(n_reads * 8)), dim3(256), 0, s,
-                           (const uint4 *)d_buf, n_lines, n_reads, seed, d_sink);
+    const uint4 *b = (const uint4 *)d_buf;
+    const uint32_t gl = probe_grid(n_reads), gc = probe_grid(n_reads * C);
+    switch (C * (lanes_per_line == 1 ? 1 : 100)) {
+    case 4: hipLaunchKernelGGL(k_probe_lines_lane<4>, dim3(gl), dim3(256), 0, s, b, n_lines, n_reads, seed, d_sink); break;
+    case 8: hipLaunchKernelGGL(k_probe_lines_lane<8>, dim3(gl), dim3(256), 0, s, b, n_lines, n_reads, seed, d_sink); break;
+    case 16: hipLaunchKernelGGL(k_probe_lines_lane<16>, dim3(gl), dim3(256), 0, s, b, n_lines, n_reads, seed, d_sink); break;
+    case 400: hipLaunchKernelGGL(k_probe_lines_coop<4>, dim3(gc), dim3(256), 0, s, b, n_lines, n_reads, seed, d_sink); break;
+    case 800: hipLaunchKernelGGL(k_probe_lines_coop<8>, dim3(gc), dim3(256), 0, s, b, n_lines, n_reads, seed, d_sink); break;
+    default: hipLaunchKernelGGL(k_probe_lines_coop<16>, dim3(gc), dim3(256), 0, s, b, n_lines, n_reads, seed, d_sink); break;
+    }
     return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
 }
 

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kExpandBlock) void k_expand(TableView t, ModelView 
         if (expand_tile<G, LS, false, true>(smem, t, m, front, base, rows, next, lc, limit, tcap))
             break;
     }
-    expand_end(lc);
+    expand_end(smem, m.W, tcap, next, lc, limit);
 }
 
 // Undo the inserts of a discarded level: zero the slots listed in next[].
@@ -106,13 +106,22 @@ size_t expand_lds_bytes(uint32_t W, uint32_t tcap) {
 lhs_status launch_expand(lhs_table *t, const TableView &tv, const ModelView &mv, const uint32_t *front,
                          uint32_t n_front, uint32_t *next, LevelCounters *lc, uint32_t limit,
                          hipStream_t s) {
-    const uint32_t blocks = (uint32_t)std::min<uint64_t>((n_front + kExpandBlock - 1) / kExpandBlock, 1u << 16);
+    const uint64_t tiles = (n_front + kExpandBlock - 1) / kExpandBlock;
     const uint32_t tc = trans_lds_entries(mv.P, mv.L, mv.K);
     const size_t lds = expand_lds_bytes(mv.W, tc);
-    const dim3 grid(std::max(blocks, 1u)), block(kExpandBlock);
     const lhs_status rc = with_shape(tps_expand(t), t->line_slots, [&](auto G, auto L) {
-        hipLaunchKernelGGL((k_expand<decltype(G)::value, decltype(L)::value>), grid, block, lds, s, tv, mv,
-                           front, n_front, next, lc, limit, tc);
+        const void *fn = (const void *)k_expand<decltype(G)::value, decltype(L)::value>;
+        // workgroups loop over tiles: as many as are resident at once, so that
+        // each keeps its new-state buffer across many tiles
+        int ncu = 0, per_cu = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kExpandBlock, lds) != hipSuccess ||
+            per_cu < 1)
+            return LHS_EDEVICE;
+        const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, (uint64_t)ncu * per_cu));
+        hipLaunchKernelGGL((k_expand<decltype(G)::value, decltype(L)::value>), dim3(blocks), dim3(kExpandBlock),
+                           lds, s, tv, mv, front, n_front, next, lc, limit, tc);
         return LHS_OK;
     });
     if (rc != LHS_OK)
