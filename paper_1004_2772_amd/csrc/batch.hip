@@ -255,12 +255,49 @@ uint64_t batch_auto_capacity(const reach_model *m) {
     return 1ull << 21;
 }
 
+// One table to empty: its slots and its status word.
+struct TableZero {
+    uint4 *bucket;
+    unsigned long long chunks;   // 16-byte chunks of the slot array
+    DevStatus *status;
+};
+
+// Empty every table of the batch in one launch: blockIdx.y = table.
+__global__ void k_clear_tables(const TableZero *z) {
+    const TableZero tz = z[blockIdx.y];
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < tz.chunks;
+         i += (unsigned long long)gridDim.x * blockDim.x)
+        tz.bucket[i] = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *tz.status = DevStatus{0, 0, 0, 0};
+}
+
+// Copy levels 1 .. n_levels-1 of every model into one compact array, model
+// after model (one workgroup; n <= kMaxBatch).
+__global__ __launch_bounds__(1024) void k_gather_levels(const ModelState *ms, const ModelProgress *mp,
+                                                        uint32_t n, unsigned long long *out) {
+    __shared__ uint32_t off[kMaxBatch + 1];
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) {
+        uint32_t acc = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            off[i] = acc;
+            acc += mp[i].n_levels - 1;
+        }
+        off[n] = acc;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += blockDim.x)
+        for (uint32_t k = 1; k < mp[i].n_levels; ++k)
+            out[off[i] + k - 1] = ms[i].levels[k];
+}
+
 struct BatchModel {
     const reach_model *m = nullptr;
     uint32_t W = 0;
     lhs_table *t = nullptr;
     bool own = false;
-    uint2 *d_trans = nullptr;
+    size_t trans_off = 0;        // entries into the packed transition area
     // host-loop state
     uint32_t n_cur = 1, cur = 0, limit = 0;
     std::vector<uint64_t> levels;
@@ -289,29 +326,23 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
     const uint32_t max_levels = opts.max_levels ? opts.max_levels : (1u << 16);
     const bool host_loop = (opts.flags & REACH_F_HOST_LOOP) != 0;
     hipStream_t s = (hipStream_t)opts.hip_stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return LHS_EDEVICE;
 
     std::vector<BatchModel> bm(n);
     lhs_status rc = LHS_OK;
-    DevStatus *d_status = nullptr;
-    LevelCounters *d_lc = nullptr, *h_lc = nullptr;
-    BatchSlot *d_slots = nullptr, *h_slots = nullptr;
-    uint32_t *d_begin = nullptr, *h_begin = nullptr, *d_roots = nullptr, *d_root_off = nullptr;
-    ModelState *d_ms = nullptr;
-    ModelProgress *d_mp = nullptr;
-    LevelState *d_lv = nullptr;
-    QueueState *d_qs = nullptr;
-    QCell *d_ring = nullptr;
-    uint64_t *d_levels = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    uint32_t max_W = 1, tcap = 0;
-    uint32_t tps = 0, ls = 0;
+    uint32_t max_W = 1, tcap = 0, tps = 0, ls = 0;
     // shape of the internal tables: the tuned batch choice for the widest model
     uint32_t widest = 1;
     for (uint32_t i = 0; i < n; ++i)
         widest = std::max(widest, models[i]->n_procs + models[i]->n_shared);
     const lhs_config batch_cfg = tuned_config(LHS_TUNE_BATCH, widest, opts.capacity ? opts.capacity : (1ull << 21));
 
-    // ---- set-up: tables, models, roots (outside the timed exploration) --
+    // ---- tables and host-side packing (no device work yet) -----------------
+    std::vector<uint2> trans_all;
+    std::vector<uint32_t> roots, root_off(n);
+    uint64_t pending = n;    // ring cells: at most one level's tiles per model
     for (uint32_t i = 0; i < n && rc == LHS_OK; ++i) {
         BatchModel &b = bm[i];
         b.m = models[i];
@@ -343,46 +374,81 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
             break;
         std::vector<uint2> packed;
         pack_model(b.m, packed);
-        if (hipMalloc(&b.d_trans, packed.size() * sizeof(uint2)) != hipSuccess ||
-            hipMemcpy(b.d_trans, packed.data(), packed.size() * sizeof(uint2), hipMemcpyHostToDevice) !=
-                hipSuccess)
-            rc = LHS_EDEVICE;
+        b.trans_off = trans_all.size();
+        trans_all.insert(trans_all.end(), packed.begin(), packed.end());
+        root_off[i] = (uint32_t)roots.size();
+        roots.insert(roots.end(), b.m->init, b.m->init + b.W);
         b.limit = b.m->state_cap ? (uint32_t)std::min<uint64_t>(b.m->state_cap - 1, 0xFFFFFFFFull)
                                  : 0xFFFFFFFFu;
         b.levels.push_back(1);
+        pending += b.t->capacity / kExpandBlock + 1;
     }
-    std::vector<uint32_t> roots, root_off(n);
+    uint64_t cells = 1024;
+    while (cells < 2 * pending)
+        cells <<= 1;
+
+    // ---- one device region: [uploaded part | device-only part] -------------
+    Carve c;
+    const size_t o_status = c.take<DevStatus>(1), o_qs = c.take<QueueState>(1),
+                 o_mp = c.take<ModelProgress>(n), o_lc = c.take<LevelCounters>(n),
+                 o_slots = c.take<BatchSlot>(n), o_begin = c.take<uint32_t>(n + 1),
+                 o_roots = c.take<uint32_t>(roots.size()), o_root_off = c.take<uint32_t>(n),
+                 o_trans = c.take<uint2>(trans_all.size()), o_ms = c.take<ModelState>(n),
+                 o_lv = c.take<LevelState>(n), o_zero = c.take<TableZero>(n);
+    const size_t up_bytes = c.off;
+    const size_t o_ring = host_loop ? 0 : c.take<QCell>(cells);
+    const size_t o_levels = host_loop ? 0 : c.take<unsigned long long>((uint64_t)n * max_levels);
+    const size_t o_clevels = host_loop ? 0 : c.take<unsigned long long>((uint64_t)n * max_levels);
+    const size_t dev_bytes = c.off;
+    // pinned host region: a mirror of the uploaded part, then host-loop buffers
+    Carve hc;
+    hc.off = up_bytes;
+    const size_t h_lc_off = hc.take<LevelCounters>(n), h_slots_off = hc.take<BatchSlot>(n),
+                 h_begin_off = hc.take<uint32_t>(n + 1);
+    const size_t host_bytes = hc.off;
+
+    Workspace &ws = workspace(dev);
+    std::unique_lock<std::mutex> lock(ws.mu);
+    if (rc == LHS_OK)
+        rc = ws_reserve(ws, dev_bytes, host_bytes);
+    if (rc != LHS_OK) {
+        lock.unlock();
+        for (auto &b : bm)
+            if (b.own)
+                lhs_destroy(b.t);
+        return rc;
+    }
+    void *D = ws.dev, *H = ws.host;
+    DevStatus *d_status = at<DevStatus>(D, o_status);
+    QueueState *d_qs = at<QueueState>(D, o_qs);
+    ModelProgress *d_mp = at<ModelProgress>(D, o_mp);
+    LevelCounters *d_lc = at<LevelCounters>(D, o_lc);
+    BatchSlot *d_slots = at<BatchSlot>(D, o_slots);
+    uint32_t *d_begin = at<uint32_t>(D, o_begin);
+    uint2 *d_trans = at<uint2>(D, o_trans);
+    ModelState *d_ms = at<ModelState>(D, o_ms);
+    LevelState *d_lv = at<LevelState>(D, o_lv);
+    QCell *d_ring = at<QCell>(D, o_ring);
+    unsigned long long *d_levels = at<unsigned long long>(D, o_levels);
+    LevelCounters *h_lc = at<LevelCounters>(H, h_lc_off);
+    BatchSlot *h_slots = at<BatchSlot>(H, h_slots_off);
+    uint32_t *h_begin = at<uint32_t>(H, h_begin_off);
+
+    // ---- fill the upload mirror ---------------------------------------------
+    std::memset(H, 0, up_bytes);   // status, level counters: zero
+    std::memcpy(at<void>(H, o_roots), roots.data(), roots.size() * sizeof(uint32_t));
+    std::memcpy(at<void>(H, o_root_off), root_off.data(), n * sizeof(uint32_t));
+    std::memcpy(at<void>(H, o_trans), trans_all.data(), trans_all.size() * sizeof(uint2));
+    BatchSlot *u_slots = at<BatchSlot>(H, o_slots);
+    TableZero *u_zero = at<TableZero>(H, o_zero);
+    uint64_t max_chunks = 1;
     for (uint32_t i = 0; i < n; ++i) {
-        root_off[i] = (uint32_t)roots.size();
-        if (bm[i].m)
-            roots.insert(roots.end(), bm[i].m->init, bm[i].m->init + bm[i].W);
-    }
-    if (rc == LHS_OK &&
-        (hipMalloc(&d_status, sizeof(DevStatus)) != hipSuccess ||
-         hipMalloc(&d_lc, n * sizeof(LevelCounters)) != hipSuccess ||
-         hipHostMalloc(&h_lc, n * sizeof(LevelCounters), hipHostMallocDefault) != hipSuccess ||
-         hipMalloc(&d_slots, n * sizeof(BatchSlot)) != hipSuccess ||
-         hipHostMalloc(&h_slots, n * sizeof(BatchSlot), hipHostMallocDefault) != hipSuccess ||
-         hipMalloc(&d_begin, (n + 1) * sizeof(uint32_t)) != hipSuccess ||
-         hipHostMalloc(&h_begin, (n + 1) * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
-         hipMalloc(&d_roots, roots.size() * sizeof(uint32_t)) != hipSuccess ||
-         hipMalloc(&d_root_off, n * sizeof(uint32_t)) != hipSuccess ||
-         hipMemcpy(d_roots, roots.data(), roots.size() * sizeof(uint32_t), hipMemcpyHostToDevice) !=
-             hipSuccess ||
-         hipMemcpy(d_root_off, root_off.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice) !=
-             hipSuccess ||
-         hipMemset(d_status, 0, sizeof(DevStatus)) != hipSuccess ||
-         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
-        rc = LHS_ENOMEM;
-    // all tables of the batch report into one status word
-    for (uint32_t i = 0; i < n && rc == LHS_OK; ++i) {
         BatchModel &b = bm[i];
         b.t->last_stream = s;
-        rc = lhs_clear(b.t, s);
-        BatchSlot &sl = h_slots[i];
+        BatchSlot &sl = u_slots[i];
         sl.t = view(b.t);
-        sl.t.status = d_status;
-        sl.m = model_view(b.m, b.d_trans);
+        sl.t.status = d_status;   // all tables of the batch report into one status word
+        sl.m = model_view(b.m, d_trans + b.trans_off);
         sl.front = b.t->frontier[0];
         sl.next = b.t->frontier[1];
         sl.lc = d_lc + i;
@@ -390,58 +456,30 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
         sl.limit = b.limit;
         sl.tile_begin = 0;
         sl.pad = 0;
+        u_zero[i] = TableZero{reinterpret_cast<uint4 *>(b.t->bucket), b.t->capacity / 2, b.t->status};
+        max_chunks = std::max<uint64_t>(max_chunks, b.t->capacity / 2);
     }
-    if (rc == LHS_OK) {
-        if (hipMemcpyAsync(d_slots, h_slots, n * sizeof(BatchSlot), hipMemcpyHostToDevice, s) != hipSuccess)
-            rc = LHS_EDEVICE;
-        hipLaunchKernelGGL(k_zero_levels, dim3((n + 255) / 256), dim3(256), 0, s, d_lc, n);
-        if (launch_insert_roots(ls, s, d_slots, d_roots, d_root_off, n) != LHS_OK ||
-            hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
-            rc = LHS_EDEVICE;
-    }
-    const size_t lds = (size_t)expand_lds_words(max_W, tcap) * sizeof(uint32_t);
-
-    // ---- exploration -------------------------------------------------------
-    if (rc == LHS_OK && !host_loop) {
-        std::vector<ModelState> hms(n);
-        std::vector<ModelProgress> hmp(n);
-        std::vector<LevelState> hlv(n);
-        // ring: at most one level's tiles per model are pending at a time
-        uint64_t pending = n;
-        for (uint32_t i = 0; i < n; ++i)
-            pending += bm[i].t->capacity / kExpandBlock + 1;
-        uint64_t cells = 1024;
-        while (cells < 2 * pending)
-            cells <<= 1;
-        QueueState hq{};
-        hq.head = 0;
-        hq.tail = n;
-        hq.remaining = n;
-        hq.error = 0;
-        hq.mask = cells - 1;
-        if (hipMalloc(&d_ms, n * sizeof(ModelState)) != hipSuccess ||
-            hipMalloc(&d_mp, n * sizeof(ModelProgress)) != hipSuccess ||
-            hipMalloc(&d_lv, n * sizeof(LevelState)) != hipSuccess ||
-            hipMalloc(&d_qs, sizeof(QueueState)) != hipSuccess ||
-            hipMalloc(&d_ring, cells * sizeof(QCell)) != hipSuccess ||
-            hipMalloc(&d_levels, (uint64_t)n * max_levels * sizeof(uint64_t)) != hipSuccess)
-            rc = LHS_ENOMEM;
-        for (uint32_t i = 0; i < n && rc == LHS_OK; ++i) {
-            ModelState &M = hms[i];
-            std::memset(&M, 0, sizeof(M));
-            M.t = h_slots[i].t;
-            M.m = h_slots[i].m;
-            M.lc = h_slots[i].lc;
+    if (!host_loop) {
+        QueueState &q = *at<QueueState>(H, o_qs);
+        q.head = 0;
+        q.tail = n;
+        q.remaining = n;
+        q.error = 0;
+        q.mask = cells - 1;
+        for (uint32_t i = 0; i < n; ++i) {
+            ModelState &M = at<ModelState>(H, o_ms)[i];
+            M.t = u_slots[i].t;
+            M.m = u_slots[i].m;
+            M.lc = u_slots[i].lc;
             M.fr[0] = bm[i].t->frontier[0];
             M.fr[1] = bm[i].t->frontier[1];
-            M.levels = reinterpret_cast<unsigned long long *>(d_levels + (uint64_t)i * max_levels);
+            M.levels = d_levels + (uint64_t)i * max_levels;
             M.cap = bm[i].m->state_cap;
             M.max_levels = max_levels;
-            ModelProgress &P = hmp[i];
-            std::memset(&P, 0, sizeof(P));
+            ModelProgress &P = at<ModelProgress>(H, o_mp)[i];
             P.total = 1;
             P.n_levels = 1;
-            LevelState &L = hlv[i];
+            LevelState &L = at<LevelState>(H, o_lv)[i];
             L.front = (unsigned long long)M.fr[0];
             L.next = (unsigned long long)M.fr[1];
             L.n_front = 1;
@@ -449,59 +487,75 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
             L.tiles_total = 1;
             L.tiles_done = 0;
         }
-        std::vector<uint64_t> lvl_host((uint64_t)n * max_levels, 0);
-        for (uint32_t i = 0; i < n; ++i)
-            lvl_host[(uint64_t)i * max_levels] = 1;
-        int dev = 0, ncu = 0, per_cu = 0;
+    }
+
+    // ---- one upload, clear every table, insert the roots --------------------
+    if (hipMemcpyAsync(D, H, up_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+        rc = LHS_EDEVICE;
+    if (rc == LHS_OK) {
+        const uint32_t gx = (uint32_t)std::min<uint64_t>((max_chunks + 255) / 256, 2048);
+        hipLaunchKernelGGL(k_clear_tables, dim3(gx, n), dim3(256), 0, s, at<TableZero>(D, o_zero));
+        if (hipGetLastError() != hipSuccess ||
+            launch_insert_roots(ls, s, d_slots, at<uint32_t>(D, o_roots), at<uint32_t>(D, o_root_off), n) !=
+                LHS_OK)
+            rc = LHS_EDEVICE;
+    }
+    const size_t lds = (size_t)expand_lds_words(max_W, tcap) * sizeof(uint32_t);
+
+    // ---- exploration -------------------------------------------------------
+    if (rc == LHS_OK && !host_loop) {
+        int ncu = 0, per_cu = 0;
         const void *fn = nullptr;
         (void)with_shape(tps, ls, [&](auto G, auto L) {
             fn = (const void *)k_batch_persistent<decltype(G)::value, decltype(L)::value>;
             return LHS_OK;
         });
-        if (rc == LHS_OK &&
-            (hipMemcpy(d_ms, hms.data(), n * sizeof(ModelState), hipMemcpyHostToDevice) != hipSuccess ||
-             hipMemcpy(d_mp, hmp.data(), n * sizeof(ModelProgress), hipMemcpyHostToDevice) != hipSuccess ||
-             hipMemcpy(d_lv, hlv.data(), n * sizeof(LevelState), hipMemcpyHostToDevice) != hipSuccess ||
-             hipMemcpy(d_qs, &hq, sizeof(hq), hipMemcpyHostToDevice) != hipSuccess ||
-             hipMemcpy(d_levels, lvl_host.data(), lvl_host.size() * sizeof(uint64_t),
-                       hipMemcpyHostToDevice) != hipSuccess ||
-             hipGetDevice(&dev) != hipSuccess ||
-             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kExpandBlock, lds) != hipSuccess ||
-             per_cu < 1))
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kExpandBlock, lds) != hipSuccess ||
+            per_cu < 1)
             rc = LHS_EDEVICE;
+        float ms = 0;
         if (rc == LHS_OK) {
             hipLaunchKernelGGL(k_init_ring, dim3((uint32_t)std::min<uint64_t>((cells + 255) / 256, 4096)),
                                dim3(256), 0, s, d_ring, (unsigned long long)cells, n);
             const uint32_t grid = (uint32_t)(ncu * per_cu);
             void *args[] = {&d_ms, &d_mp, &d_lv, &d_qs, &d_ring, &tcap};
-            (void)hipEventRecord(e0, s);
+            (void)hipEventRecord(ws.ev[0], s);
             if (hipGetLastError() != hipSuccess ||
                 hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kExpandBlock), args, lds, s) != hipSuccess)
                 rc = LHS_EDEVICE;
-            (void)hipEventRecord(e1, s);
-            if (rc == LHS_OK && hipStreamSynchronize(s) != hipSuccess)
-                rc = LHS_EDEVICE;
+            (void)hipEventRecord(ws.ev[1], s);
+            if (rc == LHS_OK) {
+                hipLaunchKernelGGL(k_gather_levels, dim3(1), dim3(1024), 0, s, d_ms, d_mp, n,
+                                   at<unsigned long long>(D, o_clevels));
+                // status, queue state and progress are the region's first bytes
+                if (hipGetLastError() != hipSuccess ||
+                    hipMemcpyAsync(H, D, o_lc, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess)
+                    rc = LHS_EDEVICE;
+            }
+            if (rc == LHS_OK)
+                (void)hipEventElapsedTime(&ms, ws.ev[0], ws.ev[1]);
         }
-        DevStatus st{};
-        if (rc == LHS_OK &&
-            (hipMemcpy(&hq, d_qs, sizeof(hq), hipMemcpyDeviceToHost) != hipSuccess ||
-             hipMemcpy(&st, d_status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess ||
-             hipMemcpy(hmp.data(), d_mp, n * sizeof(ModelProgress), hipMemcpyDeviceToHost) != hipSuccess ||
-             hipMemcpy(lvl_host.data(), d_levels, lvl_host.size() * sizeof(uint64_t),
-                       hipMemcpyDeviceToHost) != hipSuccess))
-            rc = LHS_EDEVICE;
+        const DevStatus &st = *at<DevStatus>(H, o_status);
+        const QueueState &hq = *at<QueueState>(H, o_qs);
+        const ModelProgress *hmp = at<ModelProgress>(H, o_mp);
         if (rc == LHS_OK && (hq.error || st.error))
             rc = (lhs_status)(hq.error ? hq.error : st.error);
-        float ms = 0;
-        if (rc == LHS_OK)
-            (void)hipEventElapsedTime(&ms, e0, e1);
+        uint64_t n_lvl = 0;
+        for (uint32_t i = 0; i < n && rc == LHS_OK; ++i) {
+            if (hmp[i].overflow || !hmp[i].done)
+                rc = hmp[i].overflow ? LHS_EINVAL : LHS_EDEVICE;
+            n_lvl += hmp[i].n_levels - 1;
+        }
+        std::vector<uint64_t> lv(n_lvl);
+        if (rc == LHS_OK && n_lvl &&
+            hipMemcpy(lv.data(), at<void>(D, o_clevels), n_lvl * sizeof(uint64_t), hipMemcpyDeviceToHost) !=
+                hipSuccess)
+            rc = LHS_EDEVICE;
+        uint64_t at_lvl = 0;
         for (uint32_t i = 0; i < n && rc == LHS_OK; ++i) {
             const ModelProgress &M = hmp[i];
-            if (M.overflow || !M.done) {
-                rc = M.overflow ? LHS_EINVAL : LHS_EDEVICE;
-                break;
-            }
             reach_result &r = results[i];
             r.total_states = M.total;
             r.edges = M.edges;
@@ -515,12 +569,14 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
                 rc = LHS_ENOMEM;
                 break;
             }
-            std::memcpy(r.level_counts, lvl_host.data() + (uint64_t)i * max_levels,
-                        M.n_levels * sizeof(uint64_t));
+            r.level_counts[0] = 1;
+            std::memcpy(r.level_counts + 1, lv.data() + at_lvl, (M.n_levels - 1) * sizeof(uint64_t));
+            at_lvl += M.n_levels - 1;
         }
     } else if (rc == LHS_OK) {
-        (void)hipEventRecord(e0, s);
+        (void)hipEventRecord(ws.ev[0], s);
         std::vector<uint32_t> act;
+        DevStatus *h_st = at<DevStatus>(H, o_status);
         while (rc == LHS_OK) {
             act.clear();
             uint32_t tiles = 0;
@@ -529,9 +585,7 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
                 if (b.done)
                     continue;
                 BatchSlot &sl = h_slots[act.size()];
-                sl.t = view(b.t);
-                sl.t.status = d_status;
-                sl.m = model_view(b.m, b.d_trans);
+                sl = u_slots[i];
                 sl.front = b.t->frontier[b.cur];
                 sl.next = b.t->frontier[b.cur ^ 1];
                 sl.lc = d_lc + act.size();
@@ -557,16 +611,15 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
                 rc = LHS_EDEVICE;
                 break;
             }
-            DevStatus st{};
             if (hipGetLastError() != hipSuccess ||
                 hipMemcpyAsync(h_lc, d_lc, na * sizeof(LevelCounters), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipMemcpyAsync(&st, d_status, sizeof(st), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipMemcpyAsync(h_st, d_status, sizeof(DevStatus), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess) {
                 rc = LHS_EDEVICE;
                 break;
             }
-            if (st.error) {
-                rc = (lhs_status)st.error;
+            if (h_st->error) {
+                rc = (lhs_status)h_st->error;
                 break;
             }
             for (uint32_t a = 0; a < na; ++a) {
@@ -597,12 +650,12 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
                     b.limit = (uint32_t)std::min<uint64_t>(b.m->state_cap - b.total, 0xFFFFFFFFull);
             }
         }
-        (void)hipEventRecord(e1, s);
+        (void)hipEventRecord(ws.ev[1], s);
         float ms = 0;
-        if (hipEventSynchronize(e1) == hipSuccess)
-            (void)hipEventElapsedTime(&ms, e0, e1);
-        DevStatus st{};
-        (void)hipMemcpy(&st, d_status, sizeof(st), hipMemcpyDeviceToHost);
+        if (hipEventSynchronize(ws.ev[1]) == hipSuccess)
+            (void)hipEventElapsedTime(&ms, ws.ev[0], ws.ev[1]);
+        if (hipMemcpy(h_st, d_status, sizeof(DevStatus), hipMemcpyDeviceToHost) != hipSuccess && rc == LHS_OK)
+            rc = LHS_EDEVICE;
         for (uint32_t i = 0; i < n && rc == LHS_OK; ++i) {
             BatchModel &b = bm[i];
             reach_result &r = results[i];
@@ -611,7 +664,7 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
             r.deadlocks = b.dead;
             r.capped = b.capped;
             r.n_levels = (uint32_t)b.levels.size();
-            r.wait_hits = st.wait_hits;
+            r.wait_hits = h_st->wait_hits;
             r.gpu_ms = ms;
             r.level_counts = (uint64_t *)std::malloc(b.levels.size() * sizeof(uint64_t));
             if (!r.level_counts) {
@@ -621,35 +674,15 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
             std::memcpy(r.level_counts, b.levels.data(), b.levels.size() * sizeof(uint64_t));
         }
     }
+    // the workspace may be reused by the next call once this one's work is done
+    if (hipStreamSynchronize(s) != hipSuccess && rc == LHS_OK)
+        rc = LHS_EDEVICE;
+    lock.unlock();
 
     // ---- tear-down ---------------------------------------------------------
-    for (auto &b : bm) {
-        (void)hipFree(b.d_trans);
+    for (auto &b : bm)
         if (b.own)
             lhs_destroy(b.t);
-    }
-    (void)hipFree(d_status);
-    (void)hipFree(d_lc);
-    (void)hipFree(d_slots);
-    (void)hipFree(d_begin);
-    (void)hipFree(d_roots);
-    (void)hipFree(d_root_off);
-    (void)hipFree(d_ms);
-    (void)hipFree(d_mp);
-    (void)hipFree(d_lv);
-    (void)hipFree(d_qs);
-    (void)hipFree(d_ring);
-    (void)hipFree(d_levels);
-    if (h_lc)
-        (void)hipHostFree(h_lc);
-    if (h_slots)
-        (void)hipHostFree(h_slots);
-    if (h_begin)
-        (void)hipHostFree(h_begin);
-    if (e0)
-        (void)hipEventDestroy(e0);
-    if (e1)
-        (void)hipEventDestroy(e1);
     if (rc != LHS_OK)
         for (uint32_t i = 0; i < n; ++i)
             reach_result_free(&results[i]);

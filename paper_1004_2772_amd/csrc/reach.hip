@@ -135,7 +135,7 @@ lhs_status ensure_bfs_buffers(lhs_table *t) {
     if (hipMalloc(&t->frontier[0], t->capacity * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&t->frontier[1], t->capacity * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&t->level, sizeof(LevelCounters)) != hipSuccess ||
-        hipHostMalloc(&t->level_host, sizeof(LevelCounters), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(&t->level_host, 256 + sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipFree(t->frontier[0]);
         (void)hipFree(t->frontier[1]);
@@ -144,6 +144,7 @@ lhs_status ensure_bfs_buffers(lhs_table *t) {
         t->level = nullptr;
         return LHS_ENOMEM;
     }
+    t->status_host = reinterpret_cast<DevStatus *>(reinterpret_cast<char *>(t->level_host) + 256);
     return LHS_OK;
 }
 
@@ -182,11 +183,10 @@ lhs_status explore_host_loop(lhs_table *t, const reach_model *m, const uint2 *d_
         if (rc != LHS_OK)
             return rc;
         LHS_HIP(hipMemcpyAsync(t->level_host, t->level, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
+        LHS_HIP(hipMemcpyAsync(t->status_host, t->status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
         LHS_HIP(hipStreamSynchronize(s));
-        DevStatus st;
-        LHS_HIP(hipMemcpy(&st, t->status, sizeof(st), hipMemcpyDeviceToHost));
-        if (st.error)
-            return (lhs_status)st.error;
+        if (t->status_host->error)
+            return (lhs_status)t->status_host->error;
         const LevelCounters lc = *t->level_host;
         if (m->state_cap && lc.n_next > limit) {
             hipLaunchKernelGGL(k_rollback, dim3(std::min<uint32_t>((lc.n_next + 255) / 256, 4096)),
@@ -256,17 +256,26 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
     }
     std::vector<uint2> packed;
     pack_model(m, packed);
-    uint2 *d_trans = nullptr;
-    uint32_t *d_init = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        if (own)
+            lhs_destroy(t);
+        return LHS_EDEVICE;
+    }
+    // model upload through the device's workspace: one copy, no allocation
+    Carve c;
+    const size_t o_trans = c.take<uint2>(packed.size()), o_init = c.take<uint32_t>(W);
+    Workspace &ws = workspace(dev);
+    std::unique_lock<std::mutex> lock(ws.mu);
     rc = ensure_bfs_buffers(t);
+    if (rc == LHS_OK)
+        rc = ws_reserve(ws, c.off, c.off);
+    uint2 *d_trans = at<uint2>(ws.dev, o_trans);
+    uint32_t *d_init = at<uint32_t>(ws.dev, o_init);
     if (rc == LHS_OK) {
-        if (hipMalloc(&d_trans, packed.size() * sizeof(uint2)) != hipSuccess ||
-            hipMalloc(&d_init, W * sizeof(uint32_t)) != hipSuccess ||
-            hipMemcpy(d_trans, packed.data(), packed.size() * sizeof(uint2), hipMemcpyHostToDevice) !=
-                hipSuccess ||
-            hipMemcpy(d_init, m->init, W * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
-            hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        std::memcpy(at<void>(ws.host, o_trans), packed.data(), packed.size() * sizeof(uint2));
+        std::memcpy(at<void>(ws.host, o_init), m->init, W * sizeof(uint32_t));
+        if (hipMemcpyAsync(ws.dev, ws.host, c.off, hipMemcpyHostToDevice, s) != hipSuccess)
             rc = LHS_EDEVICE;
     }
     if (rc == LHS_OK) {
@@ -274,12 +283,12 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
         rc = lhs_clear(t, s);
     }
     if (rc == LHS_OK) {
-        (void)hipEventRecord(e0, s);
+        (void)hipEventRecord(ws.ev[0], s);
         rc = explore_host_loop(t, m, d_trans, max_levels, s, r, d_init);
-        (void)hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) == hipSuccess) {
+        (void)hipEventRecord(ws.ev[1], s);
+        if (hipEventSynchronize(ws.ev[1]) == hipSuccess) {
             float ms = 0;
-            (void)hipEventElapsedTime(&ms, e0, e1);
+            (void)hipEventElapsedTime(&ms, ws.ev[0], ws.ev[1]);
             r->gpu_ms = ms;
         }
         if (rc == LHS_OK) {
@@ -288,12 +297,9 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
                 r->wait_hits = st.wait_hits;
         }
     }
-    if (e0)
-        (void)hipEventDestroy(e0);
-    if (e1)
-        (void)hipEventDestroy(e1);
-    (void)hipFree(d_trans);
-    (void)hipFree(d_init);
+    if (hipStreamSynchronize(s) != hipSuccess && rc == LHS_OK)
+        rc = LHS_EDEVICE;
+    lock.unlock();
     if (own)
         lhs_destroy(t);
     if (rc != LHS_OK)
