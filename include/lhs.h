@@ -259,6 +259,12 @@ typedef struct reach_opts {
 } reach_opts;
 
 #define REACH_F_NONE 0u
+#define REACH_F_GRAPH 2u       /* reach_explore: the level loop runs from a
+                                  captured HIP graph of 8 levels (expand,
+                                  finalise, rollback kernels driven by a
+                                  device-side level record), replayed until
+                                  the exploration ends; the host waits once
+                                  per replay instead of once per level      */
 #define REACH_F_HOST_LOOP 1u   /* batch: one launch per level step, the host
                                   reads the counters after each (default: one
                                   persistent launch for all levels)           */

@@ -25,6 +25,7 @@ STATUS = {0: "LHS_OK", 1: "LHS_EINVAL", 2: "LHS_ENOMEM", 3: "LHS_EFULL", 4: "LHS
           5: "LHS_EDEVICE", 6: "LHS_EBUDGET", 7: "LHS_ENOTFOUND", 8: "LHS_EAGAIN"}
 REACH_NONE = 0xFFFFFFFF
 REACH_F_HOST_LOOP = 1
+REACH_F_GRAPH = 2
 PROBES = {"double": 0, "linear": 1, "quadratic": 2}
 TUNE_TABLE, TUNE_BATCH = 0, 1
 

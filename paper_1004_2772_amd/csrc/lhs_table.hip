@@ -332,6 +332,12 @@ lhs_status lhs_destroy(lhs_table *t) {
     (void)hipFree(t->level);
     if (t->level_host)
         (void)hipHostFree(t->level_host);
+    if (t->gexec)
+        (void)hipGraphExecDestroy(t->gexec);
+    if (t->gstream)
+        (void)hipStreamDestroy(t->gstream);
+    (void)hipFree(t->gctx);
+    (void)hipFree(t->glevels);
     delete t;
     return LHS_OK;
 }

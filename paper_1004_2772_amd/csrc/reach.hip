@@ -41,6 +41,85 @@ __global__ void k_rollback(uint64_t *bucket, const uint32_t *next, uint32_t n) {
         bucket[next[i]] = 0;
 }
 
+// ---- graph-driven levels (REACH_F_GRAPH) ----------------------------------
+// One level = k_expand_graph, k_finalize_graph, k_rollback_graph, all reading
+// the table's GraphCtx; once the exploration is done every kernel returns at
+// once, so a replay may run past the last level.
+
+template <int G, uint32_t LS>
+__global__ __launch_bounds__(kExpandBlock) void k_expand_graph(const GraphCtx *ctx, uint32_t tcap) {
+    extern __shared__ uint32_t smem[];
+    __shared__ uint32_t s_go, s_cur, s_nf, s_lim;
+    if (threadIdx.x == 0) {
+        s_go = !ctx->ctl.done;
+        s_cur = ctx->ctl.cur;
+        s_nf = ctx->ctl.n_front;
+        s_lim = ctx->ctl.limit;
+    }
+    __syncthreads();
+    if (!s_go)
+        return;
+    const TableView t = ctx->t;
+    const ModelView m = ctx->m;
+    const uint32_t *front = ctx->fr[s_cur];
+    uint32_t *next = ctx->fr[s_cur ^ 1u];
+    LevelCounters *lc = ctx->lc;
+    const uint32_t n_front = s_nf, limit = s_lim;
+    expand_begin();
+    for (uint64_t base = (uint64_t)blockIdx.x * kExpandBlock; base < n_front;
+         base += (uint64_t)gridDim.x * kExpandBlock) {
+        const uint32_t rows = (uint32_t)min<uint64_t>(kExpandBlock, n_front - base);
+        if (expand_tile<G, LS, false, true>(smem, t, m, front, base, rows, next, lc, limit, tcap))
+            break;
+    }
+    expand_end(smem, m.W, tcap, next, lc, limit);
+}
+
+// The host loop's per-level bookkeeping, on the device (one thread).
+__global__ void k_finalize_graph(GraphCtx *ctx) {
+    LevelCtl &c = ctx->ctl;
+    LevelCounters *lc = ctx->lc;
+    if (c.done) {
+        c.rollback_n = 0;
+        return;
+    }
+    const uint32_t n_next = lc->n_next;
+    if (c.cap && n_next > c.limit) {
+        c.rollback_n = n_next;      // k_rollback_graph discards the level
+        c.capped = 1;
+        c.done = 1;
+    } else {
+        c.edges += lc->edges;
+        c.deadlocks += lc->deadlocks;
+        if (n_next == 0) {
+            c.done = 1;
+        } else if (c.n_levels == c.max_levels) {
+            c.overflow = 1;
+            c.done = 1;
+        } else {
+            c.levels[c.n_levels++] = n_next;
+            c.total += n_next;
+            c.n_front = n_next;
+            c.cur ^= 1u;
+            c.limit = c.cap ? (uint32_t)min<unsigned long long>(c.cap - c.total, 0xFFFFFFFFull) : 0xFFFFFFFFu;
+        }
+    }
+    lc->n_next = 0;
+    lc->abort = 0;
+    lc->edges = 0;
+    lc->deadlocks = 0;
+}
+
+__global__ void k_rollback_graph(const GraphCtx *ctx) {
+    const uint32_t n = ctx->ctl.rollback_n;
+    const uint32_t *next = ctx->fr[ctx->ctl.cur ^ 1u];
+    uint64_t *bucket = ctx->t.bucket;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        bucket[next[i]] = 0;
+}
+
+constexpr uint32_t kGraphLevels = 8;
+
 __global__ void k_zero_level(LevelCounters *lc) {
     lc->n_next = 0;
     lc->abort = 0;
@@ -219,6 +298,129 @@ lhs_status explore_host_loop(lhs_table *t, const reach_model *m, const uint2 *d_
     return LHS_OK;
 }
 
+// Graph-driven level loop (REACH_F_GRAPH) on table t: the levels run from a
+// captured graph of kGraphLevels levels, replayed until the device-side
+// level record says done.  h_ctx is pinned host memory for the record.
+lhs_status explore_graph(lhs_table *t, const reach_model *m, const uint2 *d_trans, uint32_t max_levels,
+                         hipStream_t s, reach_result *r, uint32_t *d_init, GraphCtx *h_ctx) {
+    if (!t->gctx && hipMalloc(&t->gctx, sizeof(GraphCtx)) != hipSuccess) {
+        (void)hipGetLastError();
+        t->gctx = nullptr;
+        return LHS_ENOMEM;
+    }
+    if (t->glevels_cap < max_levels) {
+        (void)hipFree(t->glevels);
+        t->glevels_cap = 0;
+        if (hipMalloc(&t->glevels, (size_t)max_levels * sizeof(unsigned long long)) != hipSuccess) {
+            (void)hipGetLastError();
+            t->glevels = nullptr;
+            return LHS_ENOMEM;
+        }
+        t->glevels_cap = max_levels;
+    }
+    if (!t->gstream && hipStreamCreateWithFlags(&t->gstream, hipStreamNonBlocking) != hipSuccess)
+        return LHS_EDEVICE;
+    GraphCtx *d_ctx = static_cast<GraphCtx *>(t->gctx);
+    const uint32_t tcap = trans_lds_entries(m->n_procs, m->n_locals, m->trans_per_local);
+    const uint32_t W = m->n_procs + m->n_shared;
+
+    // level 0 and the level record
+    lhs_status rc = launch_find_or_put(t, d_init, 1, reinterpret_cast<uint8_t *>(t->frontier[1]),
+                                       t->frontier[0], s);
+    if (rc != LHS_OK)
+        return rc;
+    hipLaunchKernelGGL(k_zero_level, dim3(1), dim3(1), 0, s, t->level);
+    GraphCtx &h = *h_ctx;
+    std::memset(&h, 0, sizeof(h));
+    h.t = view(t);
+    h.m = model_view(m, d_trans);
+    h.fr[0] = t->frontier[0];
+    h.fr[1] = t->frontier[1];
+    h.lc = t->level;
+    h.ctl.total = 1;
+    h.ctl.cap = m->state_cap;
+    h.ctl.levels = t->glevels;
+    h.ctl.n_front = 1;
+    h.ctl.limit = m->state_cap ? (uint32_t)std::min<uint64_t>(m->state_cap - 1, 0xFFFFFFFFull) : 0xFFFFFFFFu;
+    h.ctl.n_levels = 1;
+    h.ctl.max_levels = max_levels;
+    LHS_HIP(hipMemcpyAsync(d_ctx, &h, sizeof(h), hipMemcpyHostToDevice, s));
+
+    // the captured graph depends on the table, its lanes per state and the
+    // LDS layout (W is the table's)
+    const uint32_t tps = tps_expand(t), key = tcap * 32u + tps;
+    if (!t->gexec || t->gexec_tcap != key) {
+        if (t->gexec) {
+            (void)hipGraphExecDestroy(t->gexec);
+            t->gexec = nullptr;
+        }
+        const size_t lds = expand_lds_bytes(W, tcap);
+        hipGraph_t g = nullptr;
+        rc = with_shape(tps, t->line_slots, [&](auto G, auto L) {
+            const void *fn = (const void *)k_expand_graph<decltype(G)::value, decltype(L)::value>;
+            int ncu = 0, per_cu = 0, dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kExpandBlock, lds) != hipSuccess ||
+                per_cu < 1)
+                return LHS_EDEVICE;
+            if (hipStreamBeginCapture(t->gstream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return LHS_EDEVICE;
+            for (uint32_t k = 0; k < kGraphLevels; ++k) {
+                hipLaunchKernelGGL((k_expand_graph<decltype(G)::value, decltype(L)::value>),
+                                   dim3((uint32_t)(ncu * per_cu)), dim3(kExpandBlock), lds, t->gstream,
+                                   (const GraphCtx *)d_ctx, tcap);
+                hipLaunchKernelGGL(k_finalize_graph, dim3(1), dim3(1), 0, t->gstream, d_ctx);
+                hipLaunchKernelGGL(k_rollback_graph, dim3((uint32_t)ncu * 4), dim3(256), 0, t->gstream,
+                                   (const GraphCtx *)d_ctx);
+            }
+            const bool ok = hipStreamEndCapture(t->gstream, &g) == hipSuccess && g;
+            return ok ? LHS_OK : LHS_EDEVICE;
+        });
+        if (rc == LHS_OK && hipGraphInstantiate(&t->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+            t->gexec = nullptr;
+            rc = LHS_EDEVICE;
+        }
+        if (g)
+            (void)hipGraphDestroy(g);
+        if (rc != LHS_OK) {
+            (void)hipGetLastError();
+            return rc;
+        }
+        t->gexec_tcap = key;
+    }
+
+    // replay until done; the host waits once per replay
+    const uint64_t max_replays = (uint64_t)max_levels / kGraphLevels + 2;
+    for (uint64_t rep = 0;; ++rep) {
+        if (rep == max_replays)
+            return LHS_EDEVICE;
+        LHS_HIP(hipGraphLaunch(t->gexec, s));
+        LHS_HIP(hipMemcpyAsync(&h.ctl, &d_ctx->ctl, sizeof(LevelCtl), hipMemcpyDeviceToHost, s));
+        LHS_HIP(hipMemcpyAsync(t->status_host, t->status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+        LHS_HIP(hipStreamSynchronize(s));
+        if (t->status_host->error)
+            return (lhs_status)t->status_host->error;
+        if (h.ctl.done)
+            break;
+    }
+    if (h.ctl.overflow)
+        return LHS_EINVAL;
+    r->total_states = h.ctl.total;
+    r->edges = h.ctl.edges;
+    r->deadlocks = h.ctl.deadlocks;
+    r->capped = (int32_t)h.ctl.capped;
+    r->n_levels = h.ctl.n_levels;
+    r->level_counts = (uint64_t *)std::malloc(h.ctl.n_levels * sizeof(uint64_t));
+    if (!r->level_counts)
+        return LHS_ENOMEM;
+    r->level_counts[0] = 1;
+    if (h.ctl.n_levels > 1)
+        LHS_HIP(hipMemcpy(r->level_counts + 1, t->glevels + 1, (h.ctl.n_levels - 1) * sizeof(uint64_t),
+                          hipMemcpyDeviceToHost));
+    return LHS_OK;
+}
+
 }  // namespace lhs
 
 extern "C" {
@@ -265,6 +467,7 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
     // model upload through the device's workspace: one copy, no allocation
     Carve c;
     const size_t o_trans = c.take<uint2>(packed.size()), o_init = c.take<uint32_t>(W);
+    const size_t upload = c.off, o_ctx = c.take<GraphCtx>(1);
     Workspace &ws = workspace(dev);
     std::unique_lock<std::mutex> lock(ws.mu);
     rc = ensure_bfs_buffers(t);
@@ -275,7 +478,7 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
     if (rc == LHS_OK) {
         std::memcpy(at<void>(ws.host, o_trans), packed.data(), packed.size() * sizeof(uint2));
         std::memcpy(at<void>(ws.host, o_init), m->init, W * sizeof(uint32_t));
-        if (hipMemcpyAsync(ws.dev, ws.host, c.off, hipMemcpyHostToDevice, s) != hipSuccess)
+        if (hipMemcpyAsync(ws.dev, ws.host, upload, hipMemcpyHostToDevice, s) != hipSuccess)
             rc = LHS_EDEVICE;
     }
     if (rc == LHS_OK) {
@@ -284,7 +487,10 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
     }
     if (rc == LHS_OK) {
         (void)hipEventRecord(ws.ev[0], s);
-        rc = explore_host_loop(t, m, d_trans, max_levels, s, r, d_init);
+        if (opts.flags & REACH_F_GRAPH)
+            rc = explore_graph(t, m, d_trans, max_levels, s, r, d_init, at<GraphCtx>(ws.host, o_ctx));
+        else
+            rc = explore_host_loop(t, m, d_trans, max_levels, s, r, d_init);
         (void)hipEventRecord(ws.ev[1], s);
         if (hipEventSynchronize(ws.ev[1]) == hipSuccess) {
             float ms = 0;

@@ -15,6 +15,26 @@ struct ModelView {
     uint32_t magic_K;
 };
 
+// Device-side state of a graph-driven exploration (REACH_F_GRAPH): the level
+// loop's bookkeeping, advanced by a kernel after every level so that levels
+// can be replayed from a captured graph without the host.
+struct LevelCtl {
+    unsigned long long total, edges, deadlocks, cap;
+    unsigned long long *levels;    // [max_levels] level counts (levels[0] = 1)
+    uint32_t cur, n_front, limit, n_levels, max_levels;
+    uint32_t done, capped, overflow, rollback_n, pad;
+};
+
+// Everything the graph's kernels read: one device struct per table, so a
+// captured graph stays valid for any model explored on that table.
+struct GraphCtx {
+    lhs::TableView t;
+    ModelView m;
+    uint32_t *fr[2];
+    LevelCounters *lc;
+    LevelCtl ctl;
+};
+
 namespace lhs {
 
 lhs_status validate_model(const reach_model *m);
