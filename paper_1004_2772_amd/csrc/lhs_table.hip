@@ -19,9 +19,6 @@ namespace {
 constexpr int kBlock = 256;
 constexpr uint64_t kDefaultSeed = 0x5851F42D4C957F2Dull;
 constexpr uint32_t kMaxGrid = 1u << 19;
-// A find-or-put gives up with EFULL after probing this many lines (or every
-// line of a smaller table).
-constexpr uint32_t kMaxRounds = 1u << 16;
 
 // A vector staged in LDS (row of W words); descriptor x = word offset of
 // the row from the LDS base.
@@ -299,7 +296,9 @@ lhs_status lhs_create_ex(uint64_t capacity, uint32_t state_words, const lhs_conf
     t->tps_fop = c.tps_find_or_put;
     t->tps_exp = c.tps_expand;
     t->lines = (uint32_t)(capacity / c.line_slots);
-    t->max_rounds = std::min<uint32_t>(t->lines, kMaxRounds);
+    // a find-or-put gives up (EFULL) only after its probe sequence has
+    // visited every line, i.e. when the table has no empty slot
+    t->max_rounds = t->lines;
     t->seed = kDefaultSeed;
     if (hipGetDevice(&t->device) != hipSuccess) {
         delete t;
