@@ -15,8 +15,9 @@ through the library's C-ABI:
     at 2^c/4 states, for every line width x probe x lanes;
 and for the batch kind, the 64-model mix explored in one persistent launch.
 Per key it keeps the line width and probe whose times, each divided by the
-best time of its workload, sum lowest, and with them the fastest lanes for
-each workload.  Every shape gives identical results; only speed differs.
+best time of its workload, sum lowest (double hashing preferred within 3 %),
+and with them the fastest lanes for each workload.  Every shape gives
+identical results; only speed differs.
 
 The file it writes is read by lhs_tune_load (format "lhs-tune-1"); the
 measured times are kept in each entry.
@@ -167,12 +168,22 @@ def time_batch(reps: int) -> tuple[dict, dict]:
     return out, {"models": len(models), "states": sum(r[0] for r in ref)}
 
 
+# Probe sequences in order of preference when their times are within
+# TOLERANCE of each other: double hashing keeps probe chains short as the
+# table fills (linear probing clusters), which the timed workloads, at load
+# factor 1/8, do not show.
+PROBE_PREFERENCE = ("double", "quadratic", "linear")
+TOLERANCE = 0.03
+
+
 def choose(times_a: dict, times_b: dict | None):
     """(line_slots, probe, best tps for a, best tps for b) minimising the sum of
-    each workload's best time at that (line, probe) over its overall best."""
+    each workload's best time at that (line, probe) over its overall best;
+    among (line, probe) pairs within TOLERANCE of the lowest sum, the
+    preferred probe sequence wins, then the lower sum."""
     best_a = min(times_a.values())
     best_b = min(times_b.values()) if times_b else None
-    pick, pick_score = None, None
+    scored = []
     for ls in LINES:
         for probe in PROBE_NAMES:
             ta = {tps: times_a[_key(ls, probe, tps)] for tps in TPS}
@@ -181,10 +192,30 @@ def choose(times_a: dict, times_b: dict | None):
             if times_b:
                 tb = {tps: times_b[_key(ls, probe, tps)] for tps in TPS}
                 score += min(tb.values()) / best_b
-            if pick_score is None or score < pick_score:
-                pick_score = score
-                pick = (ls, probe, min(ta, key=ta.get), min(tb, key=tb.get) if tb else None)
-    return pick, pick_score
+            scored.append((score, ls, probe, min(ta, key=ta.get), min(tb, key=tb.get) if tb else None))
+    low = min(x[0] for x in scored)
+    near = [x for x in scored if x[0] <= low * (1 + TOLERANCE)]
+    pick = min(near, key=lambda x: (PROBE_PREFERENCE.index(x[2]), x[0]))
+    return pick[1:], pick[0]
+
+
+def reselect(path: str):
+    """Apply the selection rule again to the times recorded in a tuning file."""
+    with open(path) as f:
+        doc = json.load(f)
+    for e in doc["entries"]:
+        if e["kind"] == "table":
+            (ls, probe, tf, te), score = choose(e["stream_ms"], e["bfs_ms"])
+        else:
+            (ls, probe, te, _), score = choose(e["batch_ms"], None)
+            tf = 0
+        e.update(line_slots=ls, probe=probe, tps_find_or_put=tf, tps_expand=te, score=round(score, 4))
+    doc["selection"] = f"probe preference {list(PROBE_PREFERENCE)} within {TOLERANCE:.0%}"
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(doc, f, indent=1)
+    os.replace(tmp, path)
+    return doc
 
 
 def main(argv=None):
@@ -194,7 +225,11 @@ def main(argv=None):
     ap.add_argument("--log2-caps", default="20,24,28")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--reselect", metavar="PATH",
+                    help="only re-apply the selection rule to the times recorded in PATH")
     a = ap.parse_args(argv)
+    if a.reselect:
+        return reselect(a.reselect)
 
     import torch
     assert torch.cuda.is_available(), "the autotuner times kernels on a GPU"
@@ -227,7 +262,9 @@ def main(argv=None):
                         "batch_ms": tb, "batch_workload": desc})
     doc = {"format": "lhs-tune-1", "device": arch, "cus": props.multi_processor_count,
            "generator": "python -m paper_1004_2772_amd.autotune " + " ".join(argv or sys.argv[1:]),
-           "seconds": round(time.time() - t_start, 1), "entries": entries}
+           "seconds": round(time.time() - t_start, 1),
+           "selection": f"probe preference {list(PROBE_PREFERENCE)} within {TOLERANCE:.0%}",
+           "entries": entries}
     tmp = a.out + ".tmp"
     with open(tmp, "w") as f:
         json.dump(doc, f, indent=1)

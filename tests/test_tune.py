@@ -149,3 +149,37 @@ def test_server_rejects_bad_shape():
     o = lhs.ServerOpts(0, 0, 0, 0, lhs.LhsConfig(24, 0, 0, 0))
     assert lhs.lib().reach_server_create(ctypes.byref(o), ctypes.byref(h)) == 1
     assert not h.value
+
+
+def _times(best, others=1.10, tweak=None):
+    from paper_1004_2772_amd import autotune
+    t = {autotune._key(ls, p, g): others for ls in autotune.LINES for p in autotune.PROBE_NAMES
+         for g in autotune.TPS}
+    for k, v in (tweak or {}).items():
+        t[k] = v
+    t[best] = 1.0
+    return t
+
+
+def test_autotune_prefers_double_hashing_within_tolerance():
+    from paper_1004_2772_amd import autotune
+    # linear is best by 1 %: double hashing at the same line width wins
+    a = _times("8/linear/1", tweak={"8/double/4": 1.01})
+    b = _times("8/linear/4", tweak={"8/double/1": 1.005})
+    (ls, probe, ta, tb), _ = autotune.choose(a, b)
+    assert (ls, probe, ta, tb) == (8, "double", 4, 1)
+    # by more than the tolerance the faster probe sequence is kept
+    a = _times("16/linear/1", tweak={"16/double/1": 1.2})
+    (ls, probe, ta, tb), _ = autotune.choose(a, None)
+    assert (ls, probe, ta) == (16, "linear", 1)
+
+
+def test_autotune_reselect_keeps_format(tmp_path):
+    import shutil
+
+    from paper_1004_2772_amd import TUNE_PATH_DEFAULT, autotune
+    p = tmp_path / "tune.json"
+    shutil.copy(TUNE_PATH_DEFAULT, p)
+    doc = autotune.reselect(str(p))
+    assert lhs.tune_load(str(p), device=doc["device"]) == len(doc["entries"])
+    lhs.tune_clear()
