@@ -500,7 +500,7 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
                 LHS_OK)
             rc = LHS_EDEVICE;
     }
-    const size_t lds = (size_t)expand_lds_words(max_W, tcap) * sizeof(uint32_t);
+    const size_t lds = (size_t)expand_lds_words(max_W, tcap, tps) * sizeof(uint32_t);
 
     // ---- exploration -------------------------------------------------------
     if (rc == LHS_OK && !host_loop) {

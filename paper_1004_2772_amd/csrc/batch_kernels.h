@@ -110,7 +110,7 @@ inline lhs_status launch_insert_roots(uint32_t ls, hipStream_t s, const BatchSlo
 inline lhs_status launch_expand_multi(uint32_t tps, uint32_t ls, uint32_t tiles, uint32_t max_W, uint32_t tcap,
                                       hipStream_t s, const BatchSlot *slots, const uint32_t *begin, uint32_t n) {
     const dim3 grid(std::min<uint32_t>(std::max(tiles, 1u), 1u << 16));
-    const size_t lds = (size_t)expand_lds_words(max_W, tcap) * sizeof(uint32_t);
+    const size_t lds = (size_t)expand_lds_words(max_W, tcap, tps) * sizeof(uint32_t);
     return with_shape(tps, ls, [&](auto G, auto L) {
         hipLaunchKernelGGL((k_expand_multi<decltype(G)::value, decltype(L)::value>), grid, dim3(kExpandBlock),
                            lds, s, slots, begin, n, tiles, tcap);

@@ -46,16 +46,19 @@ struct SuccVec {
 //     (queue [kQueue]    enabled (state, process, transition) when P*K > 64,
 //                        in the same words as masks/offs)
 //   succ_cnt [256]       successors per tile state (edges, deadlocks)
-//   hq       [256] u64   hash of each successor of the current pass
-//   d0, d1   [256]       successor descriptors of the pass
+//   hq       [256] u64   hash of each successor of the current pass  } G > 1
+//   d0, d1   [256]       successor descriptors of the pass          } only
 //   nbuf     [kNewBuf]   slots of new states, flushed to next[] in bulk
-constexpr uint32_t kNewBuf = 2048;
+// With one lane per operation (G = 1) the lane that stages a successor also
+// runs its find-or-put, so hash and descriptor stay in its registers; the
+// layout then fits four workgroups of a 16-word model per CU.
+constexpr uint32_t kNewBuf = 1536;
 constexpr uint32_t kEagerRoom = 1u << 22;
 constexpr uint32_t kMaskArea = 2 * kExpandBlock + 258;
 static_assert(kQueue <= kMaskArea, "queue shares the mask area");
-__host__ __device__ constexpr uint32_t expand_lds_words(uint32_t W, uint32_t tcap = 0) {
-    return kExpandBlock * (W | 1u) + 2 * tcap + kMaskArea + kExpandBlock + 2 * kExpandBlock +
-           2 * kExpandBlock + kNewBuf;
+__host__ __device__ constexpr uint32_t expand_lds_words(uint32_t W, uint32_t tcap, uint32_t G) {
+    return kExpandBlock * (W | 1u) + 2 * tcap + kMaskArea + kExpandBlock +
+           (G > 1 ? 4 * kExpandBlock : 0u) + kNewBuf;
 }
 
 // Transitions that fit this many LDS entries are staged in LDS.
@@ -88,8 +91,9 @@ __device__ __forceinline__ void expand_begin() {
 }
 
 // The new-state buffer in the expansion's LDS layout.
+template <int G>
 __device__ __forceinline__ uint32_t *expand_nbuf(uint32_t *smem, uint32_t W, uint32_t tcap) {
-    return smem + expand_lds_words(W, tcap) - kNewBuf;
+    return smem + expand_lds_words(W, tcap, G) - kNewBuf;
 }
 
 // Append the buffered new slots to next[] with one atomic on the level's
@@ -136,9 +140,10 @@ __device__ __forceinline__ void flush_new_slots(const uint32_t *nbuf, uint32_t *
 // accumulated edge/deadlock counts to lc.  Call by all threads after the
 // last expand_tile of the launch (also after an aborted tile: every claimed
 // slot must be listed in next[] for the rollback).
+template <int G>
 __device__ __forceinline__ void expand_end(uint32_t *smem, uint32_t W, uint32_t tcap, uint32_t *next,
                                            LevelCounters *lc, uint32_t limit) {
-    flush_new_slots<false>(expand_nbuf(smem, W, tcap), next, lc, limit);
+    flush_new_slots<false>(expand_nbuf<G>(smem, W, tcap), next, lc, limit);
     if (threadIdx.x == 0) {
         if (s_acc_edges)
             atomicAdd(&lc->edges, s_acc_edges);
@@ -203,10 +208,12 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
     uint32_t *offs = reinterpret_cast<uint32_t *>(masks + kBlock);
     uint32_t *queue = reinterpret_cast<uint32_t *>(masks);     // wide models only
     uint32_t *succ_cnt = reinterpret_cast<uint32_t *>(masks) + kMaskArea;
-    uint64_t *hq = reinterpret_cast<uint64_t *>(succ_cnt + kBlock);   // 8-byte aligned
+    uint64_t *hq = reinterpret_cast<uint64_t *>(succ_cnt + kBlock);   // 8-byte aligned (G > 1)
     uint32_t *d0 = reinterpret_cast<uint32_t *>(hq + kBlock);
     uint32_t *d1 = d0 + kBlock;
-    uint32_t *nbuf = d1 + kBlock;
+    uint32_t *nbuf = G > 1 ? d1 + kBlock : succ_cnt + kBlock;
+    uint64_t my_h = 0;           // G == 1: this lane's successor of the pass
+    uint32_t my_d0 = 0, my_d1 = 0;
     __shared__ uint32_t s_tail, s_wtot[kBlock / 64];
     __shared__ WaveScratch<LS> ws[kBlock / 64];
 
@@ -272,13 +279,14 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
         for (uint32_t r = 0; r < G; ++r) {
             const uint32_t q = r * NG + gi;
             const bool active = q < take;
-            const uint32_t o = active ? q : 0;
-            const uint2 dsc = make_uint2(d0[o], d1[o]);
             uint32_t slot, code;
             if constexpr (G == 1) {
-                find_or_put_wave<LS, SuccVec>(t, &ws[tid / 64], smem, dsc, hq[o], active, slot, code, cnt);
+                find_or_put_wave<LS, SuccVec>(t, &ws[tid / 64], smem, make_uint2(my_d0, my_d1), my_h, active,
+                                              slot, code, cnt);
             } else {
-                find_or_put<G, LS>(t, SuccVec::decode(smem, dsc), hq[o], active, slot, code, cnt);
+                const uint32_t o = active ? q : 0;
+                find_or_put<G, LS>(t, SuccVec::decode(smem, make_uint2(d0[o], d1[o])), hq[o], active, slot,
+                                   code, cnt);
             }
             const bool is_new = active && leader && code == kNew;
             const uint64_t nm = __ballot(is_new);
@@ -296,16 +304,26 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
             flush_new();
         return s_abort != 0;
     };
-    // decode successor (st, p, k) into hq/d0/d1[slot_i]
+    // decode successor (st, p, k) into hq/d0/d1[i] (G > 1) or this lane's
+    // registers (G == 1, i == tid)
     auto stage_successor = [&](uint32_t i, uint32_t st, uint32_t p, uint32_t k) {
         const uint32_t *row = tile + st * stride;
         const uint2 x = tr[((uint64_t)p * m.L + row[p]) * m.K + k];
         const uint32_t evar = x.x >> 24;
         const uint32_t ew = evar == 0xFFu ? 0xFFu : m.P + evar;
         const SuccVec v{row, p, x.x & 0xFFFFu, ew == 0xFFu ? 0xFFFFFFFFu : ew, x.y >> 16};
-        hq[i] = hash_vec(v, W, t.seed);
-        d0[i] = (st * stride) | (p << 16) | (ew << 24);
-        d1[i] = (x.x & 0xFFFFu) | ((x.y >> 16) << 16);
+        const uint64_t h = hash_vec(v, W, t.seed);
+        const uint32_t e0 = (st * stride) | (p << 16) | (ew << 24);
+        const uint32_t e1 = (x.x & 0xFFFFu) | ((x.y >> 16) << 16);
+        if constexpr (G == 1) {
+            my_h = h;
+            my_d0 = e0;
+            my_d1 = e1;
+        } else {
+            hq[i] = h;
+            d0[i] = e0;
+            d1[i] = e1;
+        }
     };
 
     bool aborted = false;

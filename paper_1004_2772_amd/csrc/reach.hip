@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kExpandBlock) void k_expand(TableView t, ModelView 
         if (expand_tile<G, LS, false, true>(smem, t, m, front, base, rows, next, lc, limit, tcap))
             break;
     }
-    expand_end(smem, m.W, tcap, next, lc, limit);
+    expand_end<G>(smem, m.W, tcap, next, lc, limit);
 }
 
 // Undo the inserts of a discarded level: zero the slots listed in next[].
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kExpandBlock) void k_expand_graph(const GraphCtx *c
         if (expand_tile<G, LS, false, true>(smem, t, m, front, base, rows, next, lc, limit, tcap))
             break;
     }
-    expand_end(smem, m.W, tcap, next, lc, limit);
+    expand_end<G>(smem, m.W, tcap, next, lc, limit);
 }
 
 // The host loop's per-level bookkeeping, on the device (one thread).
@@ -178,8 +178,8 @@ ModelView model_view(const reach_model *m, const uint2 *d_trans) {
     return v;
 }
 
-size_t expand_lds_bytes(uint32_t W, uint32_t tcap) {
-    return (size_t)expand_lds_words(W, tcap) * sizeof(uint32_t);
+size_t expand_lds_bytes(uint32_t W, uint32_t tcap, uint32_t tps) {
+    return (size_t)expand_lds_words(W, tcap, tps) * sizeof(uint32_t);
 }
 
 lhs_status launch_expand(lhs_table *t, const TableView &tv, const ModelView &mv, const uint32_t *front,
@@ -187,7 +187,7 @@ lhs_status launch_expand(lhs_table *t, const TableView &tv, const ModelView &mv,
                          hipStream_t s) {
     const uint64_t tiles = (n_front + kExpandBlock - 1) / kExpandBlock;
     const uint32_t tc = trans_lds_entries(mv.P, mv.L, mv.K);
-    const size_t lds = expand_lds_bytes(mv.W, tc);
+    const size_t lds = expand_lds_bytes(mv.W, tc, tps_expand(t));
     const lhs_status rc = with_shape(tps_expand(t), t->line_slots, [&](auto G, auto L) {
         const void *fn = (const void *)k_expand<decltype(G)::value, decltype(L)::value>;
         // workgroups loop over tiles: as many as are resident at once, so that
@@ -354,7 +354,7 @@ lhs_status explore_graph(lhs_table *t, const reach_model *m, const uint2 *d_tran
             (void)hipGraphExecDestroy(t->gexec);
             t->gexec = nullptr;
         }
-        const size_t lds = expand_lds_bytes(W, tcap);
+        const size_t lds = expand_lds_bytes(W, tcap, tps);
         hipGraph_t g = nullptr;
         rc = with_shape(tps, t->line_slots, [&](auto G, auto L) {
             const void *fn = (const void *)k_expand_graph<decltype(G)::value, decltype(L)::value>;

@@ -40,7 +40,7 @@ namespace lhs {
 lhs_status validate_model(const reach_model *m);
 void pack_model(const reach_model *m, std::vector<uint2> &out);
 ModelView model_view(const reach_model *m, const uint2 *d_trans);
-size_t expand_lds_bytes(uint32_t W, uint32_t tcap);
+size_t expand_lds_bytes(uint32_t W, uint32_t tcap, uint32_t tps);
 lhs_status ensure_bfs_buffers(lhs_table *t);
 uint64_t auto_capacity(const reach_model *m);
 
