@@ -35,9 +35,10 @@ struct LdsRow {
 // stride so that lanes reading different rows hit different banks), hashes
 // each row with one lane, then runs find-or-put.  G == 1: one operation per
 // lane with wavefront-cooperative line and row accesses (256 operations in
-// flight per workgroup).  G > 1: one group of G lanes per operation (256/G in
-// flight, G rounds per tile).  Results go through LDS so that seen/index are
-// written coalesced.
+// flight per workgroup); the lane keeps its hash and result in registers and
+// writes seen/index itself (lane i <-> row i: coalesced).  G > 1: one group
+// of G lanes per operation (256/G in flight, G rounds per tile); hashes and
+// results go through LDS so that seen/index are written coalesced.
 template <int G, uint32_t LS>
 __global__ __launch_bounds__(kBlock) void k_find_or_put(TableView t, const uint32_t *__restrict__ in,
                                                         uint64_t n, uint8_t *__restrict__ seen,
@@ -63,17 +64,25 @@ __global__ __launch_bounds__(kBlock) void k_find_or_put(TableView t, const uint3
             tile[r * stride + (f - r * W)] = src[f];
         }
         __syncthreads();
+        uint64_t h = 0;
         if (tid < rows)
-            hs[tid] = hash_vec(LdsRow{tile + tid * stride}, W, t.seed);
-        __syncthreads();
+            h = hash_vec(LdsRow{tile + tid * stride}, W, t.seed);
+        if constexpr (G > 1) {
+            if (tid < rows)
+                hs[tid] = h;
+            __syncthreads();
+        }
         if constexpr (G == 1) {
             __shared__ WaveScratch<LS> ws[kBlock / 64];
             const bool active = tid < rows;
             uint32_t slot, code;
-            find_or_put_wave<LS, LdsRow>(t, &ws[tid / 64], smem, make_uint2(tid * stride, 0u),
-                                     hs[active ? tid : 0], active, slot, code, cnt);
-            res_slot[tid] = slot;
-            res_code[tid] = code;
+            find_or_put_wave<LS, LdsRow>(t, &ws[tid / 64], smem, make_uint2(tid * stride, 0u), h, active,
+                                         slot, code, cnt);
+            if (active) {
+                seen[base + tid] = code == kSeen ? 1 : (code == kNew ? 0 : 0xFF);
+                if (index)
+                    index[base + tid] = slot;
+            }
         } else {
             for (uint32_t r = 0; r < G; ++r) {
                 const uint32_t op = r * NG + gi;
@@ -86,13 +95,13 @@ __global__ __launch_bounds__(kBlock) void k_find_or_put(TableView t, const uint3
                     res_code[op] = code;
                 }
             }
-        }
-        __syncthreads();
-        if (tid < rows) {
-            const uint32_t code = res_code[tid];
-            seen[base + tid] = code == kSeen ? 1 : (code == kNew ? 0 : 0xFF);
-            if (index)
-                index[base + tid] = res_slot[tid];
+            __syncthreads();
+            if (tid < rows) {
+                const uint32_t code = res_code[tid];
+                seen[base + tid] = code == kSeen ? 1 : (code == kNew ? 0 : 0xFF);
+                if (index)
+                    index[base + tid] = res_slot[tid];
+            }
         }
     }
     flush_counters(t.status, cnt);
@@ -221,11 +230,13 @@ lhs_status launch_find_or_put(lhs_table *t, const uint32_t *d_states, uint64_t n
                               uint32_t *d_index, hipStream_t s) {
     if (!n)
         return LHS_OK;
-    const size_t lds = (size_t)kBlock * ((t->W | 1u) + 2 + 2) * sizeof(uint32_t);
+    // G == 1 needs only the row tile; G > 1 also hashes and results
+    const uint32_t tps = tps_find_or_put(t);
+    const size_t lds = (size_t)kBlock * ((t->W | 1u) + (tps > 1 ? 4u : 0u)) * sizeof(uint32_t);
     const dim3 grid(grid_for(n, kBlock)), block(kBlock);
     const TableView v = view(t);
     const uint32_t mw = div_magic(t->W);
-    const lhs_status rc = with_shape(tps_find_or_put(t), t->line_slots, [&](auto G, auto L) {
+    const lhs_status rc = with_shape(tps, t->line_slots, [&](auto G, auto L) {
         hipLaunchKernelGGL((k_find_or_put<decltype(G)::value, decltype(L)::value>), grid, block, lds, s,
                            v, d_states, n, d_seen, d_index, mw);
         return LHS_OK;
