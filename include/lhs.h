@@ -315,11 +315,12 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
  * Serving: reachability queries with continuous batching.
  *
  * A server owns a worker thread and a HIP stream on the device that was
- * current at reach_server_create.  Between every BFS level step it admits
- * queued queries (first come, first served) while their tables fit the
- * device-memory budget, expands the current level of every admitted query
- * in one launch, and retires finished ones.  Tables stay resident in a pool
- * and are reused by later queries of the same capacity and width.  A query's
+ * current at reach_server_create.  It works in rounds of four BFS level
+ * steps run by the device alone; every step expands the current level of
+ * every active query in one launch.  Between rounds it retires finished
+ * queries and admits queued ones (first come, first served) while their
+ * tables fit the device-memory budget.  Tables stay resident in a pool and
+ * are reused by later queries of the same capacity and width.  A query's
  * result equals reach_explore on it alone.
  * ---------------------------------------------------------------------- */
 typedef struct reach_server reach_server;
@@ -329,7 +330,7 @@ typedef struct reach_server_opts {
     uint64_t capacity;     /* slots per query table (power of two); 0 = pow2 >=
                               2*state_cap + 2^16 if the model is capped, else
                               2^21                                               */
-    uint32_t max_active;   /* queries on the GPU at once (0 = 1024)             */
+    uint32_t max_active;   /* queries on the GPU at once, at most 1024 (0 = 1024) */
     uint32_t flags;        /* reserved, 0                                       */
     lhs_config table;      /* shape of every query table; all zero = the
                               tuning table's "batch" choice                   */

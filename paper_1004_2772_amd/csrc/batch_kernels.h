@@ -90,7 +90,7 @@ __global__ void k_insert_roots(const BatchSlot *slots, const uint32_t *roots, co
 }
 
 // Undo a discarded level of one model (see reach.hip).
-__global__ void k_rollback_one(uint64_t *bucket, const uint32_t *next, uint32_t n) {
+[[maybe_unused]] __global__ void k_rollback_one(uint64_t *bucket, const uint32_t *next, uint32_t n) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         bucket[next[i]] = 0;
 }

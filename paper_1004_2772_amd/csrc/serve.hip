@@ -1,17 +1,21 @@
 // Reachability server with continuous batching (reach_server_*).
 //
-// A worker thread owns the GPU side.  Between every BFS level step it
+// A worker thread owns the GPU side.  It works in rounds of kRoundSteps BFS
+// level steps; between rounds it
 //   * admits queued queries, first come first served, while their tables fit
 //     the device-memory budget (tables come from a resident pool keyed by
 //     capacity and width; pooled tables of other shapes are freed when room
-//     is needed), inserts their initial states,
-//   * expands the current level of every admitted, unfinished query in one
-//     launch (the multi-model step of the batch driver), and
+//     is needed), inserts their initial states, and
 //   * retires the queries whose exploration ended, returning their tables to
 //     the pool.
-// A query that arrives while others are on the GPU therefore joins at the
-// next level step and its work overlaps theirs; its result is exactly the one
-// reach_explore computes for it alone (same kernels, its own table).
+// A step expands the current level of every active query in one launch
+// (tiles mapped to queries by a prefix), then one workgroup does every
+// query's level bookkeeping on the device (level count, cap test, frontier
+// swap, the next step's tile prefix) and a third kernel undoes a capped
+// level, so a round runs without the host.  A query that arrives while
+// others are on the GPU joins at the next round and its work overlaps
+// theirs; its result is exactly the one reach_explore computes for it alone
+// (same kernels, its own table).
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -35,7 +39,108 @@ using namespace lhs;
 namespace {
 
 constexpr uint64_t kDefaultBudget = 200ull << 30;
-constexpr uint32_t kDefaultMaxActive = 1024;
+constexpr uint32_t kDefaultMaxActive = 1024;   // also the most a round can hold
+constexpr uint32_t kRoundSteps = 8;
+
+// Device-side bookkeeping of one active query during a round.
+struct StepCtl {
+    uint32_t *fr[2];
+    unsigned long long cap, total, edges, deadlocks, wait_hits;
+    unsigned long long lv[kRoundSteps];   // level counts found in this round
+    uint32_t lv_n, cur, done, capped, error, rollback_n;
+};
+
+// Expand the current level of every active query; the tile prefix and its
+// total come from device memory (written by k_step_finalize).
+template <int G, uint32_t LS>
+__global__ __launch_bounds__(kExpandBlock) void k_expand_step(const BatchSlot *__restrict__ slots,
+                                                              const uint32_t *__restrict__ begin, uint32_t n,
+                                                              uint32_t tcap) {
+    extern __shared__ uint32_t smem[];
+    expand_begin();
+    const uint32_t tiles = begin[n];
+    for (uint32_t g = blockIdx.x; g < tiles; g += gridDim.x) {
+        const BatchSlot &s = slots[find_slot_by_tile(begin, n, g)];
+        const uint64_t base = (uint64_t)(g - s.tile_begin) * kExpandBlock;
+        const uint32_t rows = (uint32_t)min<uint64_t>(kExpandBlock, s.n_front - base);
+        expand_tile<G, LS>(smem, s.t, s.m, s.front, base, rows, s.next, s.lc, s.limit, tcap);
+    }
+}
+
+// Every query's level bookkeeping after a step (thread a = query a, one
+// workgroup of kDefaultMaxActive threads), then the next step's tile prefix.
+__global__ __launch_bounds__(kDefaultMaxActive) void k_step_finalize(BatchSlot *slots, StepCtl *ctl,
+                                                                     LevelCounters *lc, DevStatus *st,
+                                                                     uint32_t *begin, uint32_t n) {
+    __shared__ uint32_t scan[kDefaultMaxActive];
+    const uint32_t a = threadIdx.x;
+    uint32_t tiles = 0;
+    if (a < n) {
+        StepCtl &C = ctl[a];
+        BatchSlot &S = slots[a];
+        if (!C.done) {
+            const LevelCounters L = lc[a];
+            C.wait_hits += st[a].wait_hits;
+            if (st[a].error) {
+                C.error = st[a].error;
+                C.done = 1;
+            } else if (C.cap && L.n_next > S.limit) {
+                C.rollback_n = L.n_next;      // k_step_rollback discards the level
+                C.capped = 1;
+                C.done = 1;
+            } else {
+                C.edges += L.edges;
+                C.deadlocks += L.deadlocks;
+                if (L.n_next == 0) {
+                    C.done = 1;
+                } else {
+                    C.lv[C.lv_n++] = L.n_next;
+                    C.total += L.n_next;
+                    C.cur ^= 1u;
+                    S.front = C.fr[C.cur];
+                    S.next = C.fr[C.cur ^ 1u];
+                    S.n_front = L.n_next;
+                    S.limit = C.cap ? (uint32_t)min<unsigned long long>(C.cap - C.total, 0xFFFFFFFFull)
+                                    : 0xFFFFFFFFu;
+                }
+            }
+        } else {
+            C.rollback_n = 0;
+        }
+        if (C.done)
+            S.n_front = 0;
+        lc[a] = LevelCounters{0, 0, 0, 0};
+        st[a].error = 0;
+        st[a].wait_hits = 0;
+        st[a].cas_failures = 0;
+        tiles = (S.n_front + kExpandBlock - 1) / kExpandBlock;
+    }
+    // inclusive scan of the tile counts (Hillis-Steele)
+    scan[a] = tiles;
+    __syncthreads();
+    for (uint32_t d = 1; d < kDefaultMaxActive; d <<= 1) {
+        const uint32_t v = a >= d ? scan[a - d] : 0u;
+        __syncthreads();
+        scan[a] += v;
+        __syncthreads();
+    }
+    if (a < n) {
+        begin[a] = scan[a] - tiles;
+        slots[a].tile_begin = scan[a] - tiles;
+    }
+    if (a == kDefaultMaxActive - 1)
+        begin[n] = scan[a];
+}
+
+// Zero the slots a capped level claimed: blockIdx.y = query.
+__global__ void k_step_rollback(const BatchSlot *slots, const StepCtl *ctl) {
+    const uint32_t a = blockIdx.y;
+    const uint32_t n = ctl[a].rollback_n;
+    const uint32_t *next = slots[a].next;
+    uint64_t *bucket = slots[a].t.bucket;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        bucket[next[i]] = 0;
+}
 
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -97,8 +202,14 @@ struct reach_server {
     uint32_t *d_begin = nullptr, *h_begin = nullptr;
     LevelCounters *d_lc = nullptr, *h_lc = nullptr;
     DevStatus *d_st = nullptr, *h_st = nullptr;
+    StepCtl *d_ctl = nullptr, *h_ctl = nullptr;
     uint32_t *d_roots = nullptr, *d_root_off = nullptr;
     uint32_t cap_roots = 0;
+    // admission: pinned staging of packed models, roots and root slots, and
+    // a pool of device transition buffers by power-of-two size class
+    void *h_stage = nullptr;
+    size_t cap_stage = 0;
+    std::multimap<size_t, uint2 *> trans_pool;
     // stats (under mu)
     reach_server_stats stats{};
     double busy_s = 0;
@@ -120,6 +231,10 @@ void free_step_buffers(reach_server *s) {
         (void)hipHostFree(s->h_lc);
     if (s->h_st)
         (void)hipHostFree(s->h_st);
+    (void)hipFree(s->d_ctl);
+    if (s->h_ctl)
+        (void)hipHostFree(s->h_ctl);
+    s->d_ctl = s->h_ctl = nullptr;
     s->d_slots = s->h_slots = nullptr;
     s->d_begin = s->h_begin = nullptr;
     s->d_lc = s->h_lc = nullptr;
@@ -141,7 +256,9 @@ lhs_status ensure_step_buffers(reach_server *s, uint32_t n) {
         hipMalloc(&s->d_lc, c * sizeof(LevelCounters)) != hipSuccess ||
         hipHostMalloc(&s->h_lc, c * sizeof(LevelCounters), hipHostMallocDefault) != hipSuccess ||
         hipMalloc(&s->d_st, c * sizeof(DevStatus)) != hipSuccess ||
-        hipHostMalloc(&s->h_st, c * sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(&s->h_st, c * sizeof(DevStatus), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&s->d_ctl, c * sizeof(StepCtl)) != hipSuccess ||
+        hipHostMalloc(&s->h_ctl, c * sizeof(StepCtl), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         free_step_buffers(s);
         return LHS_ENOMEM;
@@ -179,11 +296,21 @@ bool acquire_table(reach_server *s, Query *q) {
     return true;
 }
 
+size_t trans_class(size_t bytes) {
+    size_t c = 256;
+    while (c < bytes)
+        c <<= 1;
+    return c;
+}
+
 void release_table(reach_server *s, Query *q) {
     if (q->t)
         s->pool.emplace(std::make_pair(q->t->capacity, q->t->W), q->t);
     q->t = nullptr;
-    (void)hipFree(q->d_trans);
+    if (q->d_trans) {
+        const size_t bytes = (size_t)q->m.n_procs * q->m.n_locals * q->m.trans_per_local * sizeof(uint2);
+        s->trans_pool.emplace(trans_class(bytes), q->d_trans);
+    }
     q->d_trans = nullptr;
 }
 
@@ -191,23 +318,72 @@ void release_table(reach_server *s, Query *q) {
 lhs_status start_queries(reach_server *s, const std::vector<Query *> &qs) {
     if (qs.empty())
         return LHS_OK;
-    lhs_status rc = ensure_step_buffers(s, (uint32_t)qs.size());
+    const uint32_t n = (uint32_t)qs.size();
+    // pinned staging: [slots | root offsets | roots | packed models]
+    Carve c;
+    const size_t o_slots = c.take<BatchSlot>(n), o_off = c.take<uint32_t>(n);
+    size_t n_roots = 0, n_trans = 0;
+    for (Query *q : qs) {
+        n_roots += q->W;
+        n_trans += (size_t)q->m.n_procs * q->m.n_locals * q->m.trans_per_local;
+    }
+    const size_t o_roots = c.take<uint32_t>(n_roots), o_trans = c.take<uint2>(n_trans);
+    if (c.off > s->cap_stage) {
+        if (s->h_stage)
+            (void)hipHostFree(s->h_stage);
+        s->h_stage = nullptr;
+        s->cap_stage = 0;
+        size_t cap = 1 << 20;
+        while (cap < c.off)
+            cap <<= 1;
+        if (hipHostMalloc(&s->h_stage, cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            s->h_stage = nullptr;
+            return LHS_ENOMEM;
+        }
+        s->cap_stage = cap;
+    }
+    if (n_roots > s->cap_roots || n > s->cap_roots) {
+        (void)hipFree(s->d_roots);
+        (void)hipFree(s->d_root_off);
+        s->cap_roots = 0;
+        const uint32_t cap = (uint32_t)std::max<size_t>(1024, std::max<size_t>(n_roots, n) * 2);
+        if (hipMalloc(&s->d_roots, cap * sizeof(uint32_t)) != hipSuccess ||
+            hipMalloc(&s->d_root_off, cap * sizeof(uint32_t)) != hipSuccess)
+            return LHS_ENOMEM;
+        s->cap_roots = cap;
+    }
+    // room for the whole next round now: growing the step buffers later
+    // would free them under this admission's queued work
+    lhs_status rc = ensure_step_buffers(s, (uint32_t)s->active.size() + n);
     if (rc != LHS_OK)
         return rc;
-    std::vector<uint32_t> roots, off;
-    std::vector<std::vector<uint2>> packed_all(qs.size());   // alive until the sync below
-    for (uint32_t i = 0; i < qs.size(); ++i) {
+    BatchSlot *slots = at<BatchSlot>(s->h_stage, o_slots);
+    uint32_t *off = at<uint32_t>(s->h_stage, o_off), *roots = at<uint32_t>(s->h_stage, o_roots);
+    uint2 *trans = at<uint2>(s->h_stage, o_trans);
+    size_t r_at = 0, t_at = 0;
+    std::vector<uint2> packed;
+    for (uint32_t i = 0; i < n; ++i) {
         Query *q = qs[i];
-        std::vector<uint2> &packed = packed_all[i];
         pack_model(&q->m, packed);
-        if (hipMalloc(&q->d_trans, packed.size() * sizeof(uint2)) != hipSuccess ||
-            hipMemcpyAsync(q->d_trans, packed.data(), packed.size() * sizeof(uint2), hipMemcpyHostToDevice,
-                           s->stream) != hipSuccess)
+        const size_t bytes = packed.size() * sizeof(uint2);
+        auto it = s->trans_pool.find(trans_class(bytes));
+        if (it != s->trans_pool.end()) {
+            q->d_trans = it->second;
+            s->trans_pool.erase(it);
+        } else if (hipMalloc(&q->d_trans, trans_class(bytes)) != hipSuccess) {
+            (void)hipGetLastError();
+            q->d_trans = nullptr;
+            return LHS_ENOMEM;
+        }
+        std::memcpy(trans + t_at, packed.data(), bytes);
+        if (hipMemcpyAsync(q->d_trans, trans + t_at, bytes, hipMemcpyHostToDevice, s->stream) != hipSuccess)
             return LHS_EDEVICE;
+        t_at += packed.size();
         q->t->last_stream = s->stream;
         if (lhs_clear(q->t, s->stream) != LHS_OK)
             return LHS_EDEVICE;
-        BatchSlot &sl = s->h_slots[i];
+        BatchSlot &sl = slots[i];
         sl.t = view(q->t);
         sl.m = model_view(&q->m, q->d_trans);
         sl.front = q->t->frontier[0];
@@ -216,35 +392,26 @@ lhs_status start_queries(reach_server *s, const std::vector<Query *> &qs) {
         sl.n_front = 1;
         sl.limit = q->limit;
         sl.tile_begin = 0;
-        off.push_back((uint32_t)roots.size());
-        roots.insert(roots.end(), q->init.begin(), q->init.end());
+        sl.pad = 0;
+        off[i] = (uint32_t)r_at;
+        std::memcpy(roots + r_at, q->init.data(), q->W * sizeof(uint32_t));
+        r_at += q->W;
     }
-    if (roots.size() > s->cap_roots) {
-        (void)hipFree(s->d_roots);
-        (void)hipFree(s->d_root_off);
-        s->cap_roots = 0;
-        const uint32_t c = (uint32_t)std::max<size_t>(1024, roots.size() * 2);
-        if (hipMalloc(&s->d_roots, c * sizeof(uint32_t)) != hipSuccess ||
-            hipMalloc(&s->d_root_off, c * sizeof(uint32_t)) != hipSuccess)
-            return LHS_ENOMEM;
-        s->cap_roots = c;
-    }
-    const uint32_t n = (uint32_t)qs.size();
-    if (hipMemcpyAsync(s->d_roots, roots.data(), roots.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
-                       s->stream) != hipSuccess ||
-        hipMemcpyAsync(s->d_root_off, off.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, s->stream) !=
+    if (hipMemcpyAsync(s->d_roots, roots, n_roots * sizeof(uint32_t), hipMemcpyHostToDevice, s->stream) !=
             hipSuccess ||
-        hipMemcpyAsync(s->d_slots, s->h_slots, n * sizeof(BatchSlot), hipMemcpyHostToDevice, s->stream) !=
-            hipSuccess)
+        hipMemcpyAsync(s->d_root_off, off, n * sizeof(uint32_t), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(s->d_slots, slots, n * sizeof(BatchSlot), hipMemcpyHostToDevice, s->stream) != hipSuccess)
         return LHS_EDEVICE;
     if (launch_insert_roots(s->cfg.line_slots, s->stream, s->d_slots, s->d_roots, s->d_root_off, n) != LHS_OK)
         return LHS_EDEVICE;
-    // host buffers are reused by the next step: wait for the copies
-    return (hipGetLastError() == hipSuccess && hipStreamSynchronize(s->stream) == hipSuccess) ? LHS_OK
-                                                                                            : LHS_EDEVICE;
+    // the staging buffer is rewritten only at the next admission, after the
+    // next round's synchronisation: no wait here
+    return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
 }
 
-// One level step over every active query.  Returns the queries that ended.
+// One round of kRoundSteps level steps over every active query, run on the
+// device without the host; afterwards the queries whose exploration ended
+// are returned in `finished`.
 lhs_status step_queries(reach_server *s, std::vector<Query *> &finished) {
     const uint32_t na = (uint32_t)s->active.size();
     lhs_status rc = ensure_step_buffers(s, na);
@@ -263,6 +430,16 @@ lhs_status step_queries(reach_server *s, std::vector<Query *> &finished) {
         sl.n_front = q->n_cur;
         sl.limit = q->limit;
         sl.tile_begin = tiles;
+        sl.pad = 0;
+        StepCtl &c = s->h_ctl[a];
+        std::memset(&c, 0, sizeof(c));
+        c.fr[0] = q->t->frontier[0];
+        c.fr[1] = q->t->frontier[1];
+        c.cap = q->m.state_cap;
+        c.total = q->total;
+        c.edges = q->edges;
+        c.deadlocks = q->dead;
+        c.cur = q->cur;
         s->h_begin[a] = tiles;
         tiles += (q->n_cur + kExpandBlock - 1) / kExpandBlock;
         maxW = std::max(maxW, q->W);
@@ -272,53 +449,59 @@ lhs_status step_queries(reach_server *s, std::vector<Query *> &finished) {
     s->h_begin[na] = tiles;
     if (hipMemcpyAsync(s->d_slots, s->h_slots, na * sizeof(BatchSlot), hipMemcpyHostToDevice, s->stream) !=
             hipSuccess ||
+        hipMemcpyAsync(s->d_ctl, s->h_ctl, na * sizeof(StepCtl), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemcpyAsync(s->d_begin, s->h_begin, (na + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s->stream) !=
             hipSuccess)
         return LHS_EDEVICE;
     hipLaunchKernelGGL(k_zero_step, dim3((na + 255) / 256), dim3(256), 0, s->stream, s->d_lc, s->d_st, na);
-    if (launch_expand_multi(tps, s->cfg.line_slots, tiles, maxW, tcap, s->stream, s->d_slots, s->d_begin, na) !=
-            LHS_OK ||
-        hipGetLastError() != hipSuccess ||
-        hipMemcpyAsync(s->h_lc, s->d_lc, na * sizeof(LevelCounters), hipMemcpyDeviceToHost, s->stream) !=
+    // workgroups for the expansion: enough for the round's first level four
+    // times over (later levels loop), at most as many as are resident
+    const size_t lds = (size_t)expand_lds_words(maxW, tcap, tps) * sizeof(uint32_t);
+    rc = with_shape(tps, s->cfg.line_slots, [&](auto G, auto L) {
+        const void *fn = (const void *)k_expand_step<decltype(G)::value, decltype(L)::value>;
+        int ncu = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kExpandBlock, lds) != hipSuccess ||
+            per_cu < 1)
+            return LHS_EDEVICE;
+        const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)ncu * per_cu,
+                                                           std::max<uint64_t>(64, 4ull * tiles));
+        for (uint32_t k = 0; k < kRoundSteps; ++k) {
+            hipLaunchKernelGGL((k_expand_step<decltype(G)::value, decltype(L)::value>), dim3(grid),
+                               dim3(kExpandBlock), lds, s->stream, s->d_slots, s->d_begin, na, tcap);
+            hipLaunchKernelGGL(k_step_finalize, dim3(1), dim3(kDefaultMaxActive), 0, s->stream, s->d_slots,
+                               s->d_ctl, s->d_lc, s->d_st, s->d_begin, na);
+            hipLaunchKernelGGL(k_step_rollback, dim3(32, na), dim3(256), 0, s->stream, s->d_slots, s->d_ctl);
+        }
+        return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
+    });
+    if (rc != LHS_OK)
+        return rc;
+    if (hipMemcpyAsync(s->h_slots, s->d_slots, na * sizeof(BatchSlot), hipMemcpyDeviceToHost, s->stream) !=
             hipSuccess ||
-        hipMemcpyAsync(s->h_st, s->d_st, na * sizeof(DevStatus), hipMemcpyDeviceToHost, s->stream) !=
-            hipSuccess ||
+        hipMemcpyAsync(s->h_ctl, s->d_ctl, na * sizeof(StepCtl), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess)
         return LHS_EDEVICE;
     std::vector<Query *> keep;
     keep.reserve(na);
     for (uint32_t a = 0; a < na; ++a) {
         Query *q = s->active[a];
-        const LevelCounters &lc = s->h_lc[a];
-        q->wait_hits += s->h_st[a].wait_hits;
-        bool end = false;
-        if (s->h_st[a].error) {
-            q->status = (lhs_status)s->h_st[a].error;
-            end = true;
-        } else if (q->m.state_cap && lc.n_next > q->limit) {
-            hipLaunchKernelGGL(k_rollback_one, dim3(std::min<uint32_t>((lc.n_next + 255) / 256, 4096)), dim3(256),
-                               0, s->stream, q->t->bucket, q->t->frontier[q->cur ^ 1], lc.n_next);
-            q->capped = 1;
-            end = true;
-        } else {
-            q->edges += lc.edges;
-            q->dead += lc.deadlocks;
-            if (lc.n_next == 0) {
-                end = true;
-            } else {
-                q->levels.push_back(lc.n_next);
-                q->total += lc.n_next;
-                q->n_cur = lc.n_next;
-                q->cur ^= 1;
-                if (q->m.state_cap)
-                    q->limit = (uint32_t)std::min<uint64_t>(q->m.state_cap - q->total, 0xFFFFFFFFull);
-            }
-        }
-        (end ? finished : keep).push_back(q);
+        const StepCtl &c = s->h_ctl[a];
+        const BatchSlot &sl = s->h_slots[a];
+        q->wait_hits += c.wait_hits;
+        q->levels.insert(q->levels.end(), c.lv, c.lv + c.lv_n);
+        q->total = c.total;
+        q->edges = c.edges;
+        q->dead = c.deadlocks;
+        q->cur = c.cur;
+        q->n_cur = sl.n_front;
+        q->limit = sl.limit;
+        if (c.error)
+            q->status = (lhs_status)c.error;
+        q->capped = (int)c.capped;
+        (c.done ? finished : keep).push_back(q);
     }
     s->active.swap(keep);
-    if (!finished.empty() && hipStreamSynchronize(s->stream) != hipSuccess)
-        return LHS_EDEVICE;
     return LHS_OK;
 }
 
@@ -450,6 +633,10 @@ lhs_status reach_server_create(const reach_server_opts *o, reach_server **out) {
         s->opts.budget_bytes = kDefaultBudget;
     if (!s->opts.max_active)
         s->opts.max_active = kDefaultMaxActive;
+    if (s->opts.max_active > kDefaultMaxActive) {
+        delete s;
+        return LHS_EINVAL;
+    }
     const lhs_config &c = s->opts.table;
     if (c.line_slots == 0 && c.probe == 0 && c.tps_find_or_put == 0 && c.tps_expand == 0) {
         s->cfg = tuned_config(LHS_TUNE_BATCH, 32, s->opts.capacity ? s->opts.capacity : (1ull << 21));
@@ -567,6 +754,10 @@ lhs_status reach_server_destroy(reach_server *s) {
     free_step_buffers(s);
     (void)hipFree(s->d_roots);
     (void)hipFree(s->d_root_off);
+    for (auto &e : s->trans_pool)
+        (void)hipFree(e.second);
+    if (s->h_stage)
+        (void)hipHostFree(s->h_stage);
     (void)hipStreamDestroy(s->stream);
     const lhs_status rc = s->fatal;
     delete s;
