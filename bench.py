@@ -27,6 +27,9 @@ Extra legs in the same JSON line:
                  query at a time; p50/p99 latency from scheduled arrival.
   cpu_baseline : the CPU oracle (sequential find-or-put) timed on a bounded
                  prefix of the same stream, one host thread.
+  cpu_lockless : the paper's lockless table and level-synchronous BFS on all
+                 host cores (cpu_table/), on the same stream and on the model
+                 capped at 2^22 states.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -88,6 +91,8 @@ def main():
     ap.add_argument("--batch", type=int, default=0, help="rows per call (0 = whole stream)")
     ap.add_argument("--no-bfs", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu-lockless", action="store_true",
+                    help="skip the multi-core CPU lockless-table leg")
     ap.add_argument("--no-probes", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -418,6 +423,26 @@ def main():
                                "sample": f"first {S} rows of the same stream ({d} distinct), "
                                          f"sequential std::unordered_map find-or-put, {cdt:.1f} s"}
         log(f"cpu baseline: {S / cdt:.0f} ops/s over {S} rows")
+    if not args.no_cpu_lockless:
+        # the paper's method on every host core (multi-core lockless table)
+        import cpu_table
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+        full = gen.gather(rows, order)
+        cpu_table.stream(full[: 1 << 20], args.table_log2 - 8, threads)      # warm-up
+        _, _, csec = cpu_table.stream(full, args.table_log2, threads)
+        del full
+        mb = gen.big_model(cap=1 << 22)
+        cr = cpu_table.reach(mb, None, 24, threads)
+        out["cpu_lockless"] = {
+            "threads": threads,
+            "stream_ops_per_s": round(n / csec, 1),
+            "stream": f"the same {n}-row stream into a 2^{args.table_log2}-slot table, one pass",
+            "bfs_states_per_s": round(cr.total / cr.seconds, 1),
+            "bfs": f"the same model capped at 2^22 states ({cr.total} states, {cr.n_levels} levels), "
+                   f"table 2^24",
+            "gpu_speedup_stream": round(ops_per_s / (n / csec), 2)}
+        log(f"cpu lockless ({threads} threads): stream {n / csec:.0f} ops/s, "
+            f"bfs {cr.total / cr.seconds:.0f} states/s")
     print(json.dumps(out), flush=True)
 
 
