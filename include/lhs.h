@@ -265,6 +265,14 @@ typedef struct reach_opts {
                                   device-side level record), replayed until
                                   the exploration ends; the host waits once
                                   per replay instead of once per level      */
+#define REACH_F_PARENTS 4u     /* reach_explore on a caller table (o->table):
+                                  also record, for every new state, the slot
+                                  of the state it was generated from (one
+                                  uint32 per slot, allocated in the table on
+                                  first use) and the slots of the first 1024
+                                  deadlock states expanded, for reach_trace
+                                  and reach_deadlock_slots.  Without a caller
+                                  table: LHS_EINVAL                          */
 #define REACH_F_HOST_LOOP 1u   /* batch: one launch per level step, the host
                                   reads the counters after each (default: one
                                   persistent launch for all levels)           */
@@ -286,6 +294,26 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
 
 /* Free what reach_explore / reach_explore_batch allocated in r. */
 void reach_result_free(reach_result *r);
+
+/* Counterexample trace (Algorithm 1's deadlock report made concrete): after
+ * reach_explore with REACH_F_PARENTS on table t, the path of slots from s0 to
+ * the state stored in `slot` along the recorded predecessors, s0 first;
+ * every step is one transition and the path has BFS-depth + 1 states.
+ *   h_path : host, max_len uint32 (may be NULL): the slots;
+ *   h_rows : host, max_len * state_words uint32 (may be NULL): the vectors;
+ *   *len   : path length (also when it exceeds max_len, in which case
+ *            nothing is copied and LHS_EINVAL is returned if a buffer was
+ *            given).
+ * LHS_EINVAL if the table holds no records of its last exploration or
+ * `slot` holds no stored state.  Synchronous (one small copy per step). */
+lhs_status reach_trace(lhs_table *t, uint32_t slot, uint32_t *h_path, uint32_t *h_rows,
+                       uint32_t max_len, uint32_t *len);
+
+/* Deadlock states recorded by the last reach_explore with REACH_F_PARENTS
+ * on t: *n = how many were expanded (including those of a level discarded by
+ * the cap); the slots of the first min(*n, 1024, max) go to h_slots (host,
+ * may be NULL).  Synchronous. */
+lhs_status reach_deadlock_slots(lhs_table *t, uint32_t *h_slots, uint32_t max, uint32_t *n);
 
 /* Explore n models (1..1024) together: every model has its own table region
  * (slots, rows, frontiers) and results identical to reach_explore on it

@@ -26,6 +26,7 @@ STATUS = {0: "LHS_OK", 1: "LHS_EINVAL", 2: "LHS_ENOMEM", 3: "LHS_EFULL", 4: "LHS
 REACH_NONE = 0xFFFFFFFF
 REACH_F_HOST_LOOP = 1
 REACH_F_GRAPH = 2
+REACH_F_PARENTS = 4
 PROBES = {"double": 0, "linear": 1, "quadratic": 2}
 TUNE_TABLE, TUNE_BATCH = 0, 1
 
@@ -34,7 +35,8 @@ EXPORTS = ["lhs_strerror", "lhs_create", "lhs_create_ex", "lhs_get_config", "lhs
            "lhs_clear", "lhs_find_or_put", "lhs_set_threads_per_state",
            "lhs_tune_load", "lhs_tune_clear", "lhs_tune_lookup",
            "lhs_check", "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info",
-           "reach_explore", "reach_result_free", "reach_explore_batch",
+           "reach_explore", "reach_result_free", "reach_explore_batch", "reach_trace",
+           "reach_deadlock_slots",
            "reach_server_clock", "reach_server_create", "reach_server_submit", "reach_server_poll",
            "reach_server_wait", "reach_server_get_stats", "reach_server_destroy",
            "lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_copy"]
@@ -144,6 +146,8 @@ def lib() -> ctypes.CDLL:
         L.reach_explore.argtypes = [ctypes.POINTER(ReachModel), ctypes.POINTER(ReachOpts),
                                     ctypes.POINTER(ReachResultC)]
         L.reach_result_free.argtypes = [ctypes.POINTER(ReachResultC)]
+        L.reach_trace.argtypes = [p, u32, p, p, u32, ctypes.POINTER(u32)]
+        L.reach_deadlock_slots.argtypes = [p, p, u32, ctypes.POINTER(u32)]
         L.reach_explore_batch.argtypes = [ctypes.POINTER(ctypes.POINTER(ReachModel)), u32,
                                           ctypes.POINTER(ReachOpts), ctypes.POINTER(p),
                                           ctypes.POINTER(ReachResultC)]
@@ -164,7 +168,8 @@ def lib() -> ctypes.CDLL:
                      "lhs_set_threads_per_state", "lhs_create_ex", "lhs_get_config",
                      "lhs_tune_load", "lhs_tune_clear", "lhs_tune_lookup",
                      "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info", "reach_explore",
-                     "reach_explore_batch", "reach_server_create", "reach_server_submit",
+                     "reach_explore_batch", "reach_trace", "reach_deadlock_slots",
+                     "reach_server_create", "reach_server_submit",
                      "reach_server_poll", "reach_server_wait", "reach_server_get_stats",
                      "reach_server_destroy"):
             getattr(L, name).restype = st
@@ -302,6 +307,26 @@ class Table:
         i = LhsInfo()
         _check(lib().lhs_get_info(self.handle, ctypes.byref(i)), "lhs_get_info")
         return {f: getattr(i, f) for f, _ in LhsInfo._fields_}
+
+    def trace(self, slot: int):
+        """(slots [n], rows [n, W]) from s0 to the state in `slot` (needs the
+        last reach_explore on this table to have used REACH_F_PARENTS)."""
+        n = ctypes.c_uint32()
+        _check(lib().reach_trace(self.handle, slot, None, None, 0, ctypes.byref(n)), "reach_trace")
+        path = np.empty(n.value, dtype=np.uint32)
+        rows = np.empty((n.value, self.W), dtype=np.uint32)
+        _check(lib().reach_trace(self.handle, slot, _ptr(path), _ptr(rows), n.value, ctypes.byref(n)),
+               "reach_trace")
+        return path, rows
+
+    def deadlock_slots(self):
+        """(number of deadlock states expanded, slots of the first <= 1024)."""
+        n = ctypes.c_uint32()
+        _check(lib().reach_deadlock_slots(self.handle, None, 0, ctypes.byref(n)), "reach_deadlock_slots")
+        out = np.empty(min(n.value, 1024), dtype=np.uint32)
+        _check(lib().reach_deadlock_slots(self.handle, _ptr(out), len(out), ctypes.byref(n)),
+               "reach_deadlock_slots")
+        return n.value, out
 
     def config(self) -> dict:
         c = LhsConfig()

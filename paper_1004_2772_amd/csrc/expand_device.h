@@ -289,6 +289,11 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
                                    code, cnt);
             }
             const bool is_new = active && leader && code == kNew;
+            if (t.parent && is_new) {
+                // predecessor record: the frontier slot of the expanded row
+                const uint32_t row_off = (G == 1 ? my_d0 : d0[q]) & 0xFFFFu;
+                t.parent[slot] = front[base + row_off / stride];
+            }
             const uint64_t nm = __ballot(is_new);
             if (nm) {
                 uint32_t wbase = 0;
@@ -443,6 +448,11 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
     // ---- edge and deadlock counts of the tile -------------------------------
     const uint32_t mine = tid < rows ? succ_cnt[tid] : 0u;
     const uint32_t e32 = wave_sum(mine), d32 = wave_sum(tid < rows && mine == 0);
+    if (t.dead_rec && tid < rows && mine == 0) {
+        const uint32_t k = atomicAdd(t.dead_rec, 1u);
+        if (k < kDeadRecord)
+            t.dead_rec[1 + k] = front[base + tid];
+    }
     if (__lane_id() == 0) {
         atomicAdd(&s_acc_edges, (unsigned long long)e32);
         atomicAdd(&s_acc_dead, (unsigned long long)d32);

@@ -62,7 +62,13 @@ struct TableView {
     uint32_t max_rounds;     // lines probed before EFULL
     uint32_t probe;          // kProbe*
     DevStatus *status;
+    // BFS with predecessor records (else null): parent[slot] = the slot the
+    // state was first generated from; dead_rec = [count, slots of the first
+    // kDeadRecord deadlock states expanded]
+    uint32_t *parent;
+    uint32_t *dead_rec;
 };
+constexpr uint32_t kDeadRecord = 1024;
 
 // log2 of the line width in slots (8, 16 or 32).
 template <uint32_t LS>

@@ -342,6 +342,8 @@ lhs_status lhs_destroy(lhs_table *t) {
     (void)hipFree(t->level);
     if (t->level_host)
         (void)hipHostFree(t->level_host);
+    (void)hipFree(t->parent);
+    (void)hipFree(t->dead_rec);
     if (t->gexec)
         (void)hipGraphExecDestroy(t->gexec);
     if (t->gstream)
@@ -357,6 +359,7 @@ lhs_status lhs_clear(lhs_table *t, void *hip_stream) {
         return LHS_EINVAL;
     hipStream_t s = (hipStream_t)hip_stream;
     t->last_stream = s;
+    t->has_parents = false;
     if (launch_zero_u64(t->bucket, t->capacity, s) != LHS_OK)
         return LHS_EDEVICE;
     hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(1), 0, s, t->status);

@@ -120,6 +120,23 @@ __global__ void k_rollback_graph(const GraphCtx *ctx) {
 
 constexpr uint32_t kGraphLevels = 8;
 
+// Start of a BFS with predecessor records: s0 is its own predecessor, no
+// deadlock recorded yet.
+__global__ void k_begin_parents(uint32_t *parent, const uint32_t *front, uint32_t *dead_rec) {
+    parent[front[0]] = front[0];
+    dead_rec[0] = 0;
+}
+
+// The view a BFS on t expands with: predecessor records when requested.
+TableView bfs_view(lhs_table *t, bool parents) {
+    TableView v = view(t);
+    if (parents) {
+        v.parent = t->parent;
+        v.dead_rec = t->dead_rec;
+    }
+    return v;
+}
+
 __global__ void k_zero_level(LevelCounters *lc) {
     lc->n_next = 0;
     lc->abort = 0;
@@ -239,9 +256,9 @@ uint64_t auto_capacity(const reach_model *m) {
 // Host-driven level loop on table t (already sized, W matching).
 lhs_status explore_host_loop(lhs_table *t, const reach_model *m, const uint2 *d_trans,
                              uint32_t max_levels, hipStream_t s, reach_result *r,
-                             uint32_t *d_init) {
+                             uint32_t *d_init, bool parents) {
     const ModelView mv = model_view(m, d_trans);
-    const TableView tv = view(t);
+    const TableView tv = bfs_view(t, parents);
     std::vector<uint64_t> levels;
     // s0 is level 0: insert it with the batched find-or-put; its slot is the
     // first frontier (the seen byte lands in the other frontier buffer).
@@ -249,6 +266,8 @@ lhs_status explore_host_loop(lhs_table *t, const reach_model *m, const uint2 *d_
                                        t->frontier[0], s);
     if (rc != LHS_OK)
         return rc;
+    if (parents)
+        hipLaunchKernelGGL(k_begin_parents, dim3(1), dim3(1), 0, s, t->parent, t->frontier[0], t->dead_rec);
     levels.push_back(1);
     uint64_t total = 1, edges = 0, dead = 0;
     uint32_t n_cur = 1, cur = 0;
@@ -302,7 +321,7 @@ lhs_status explore_host_loop(lhs_table *t, const reach_model *m, const uint2 *d_
 // captured graph of kGraphLevels levels, replayed until the device-side
 // level record says done.  h_ctx is pinned host memory for the record.
 lhs_status explore_graph(lhs_table *t, const reach_model *m, const uint2 *d_trans, uint32_t max_levels,
-                         hipStream_t s, reach_result *r, uint32_t *d_init, GraphCtx *h_ctx) {
+                         hipStream_t s, reach_result *r, uint32_t *d_init, GraphCtx *h_ctx, bool parents) {
     if (!t->gctx && hipMalloc(&t->gctx, sizeof(GraphCtx)) != hipSuccess) {
         (void)hipGetLastError();
         t->gctx = nullptr;
@@ -329,10 +348,12 @@ lhs_status explore_graph(lhs_table *t, const reach_model *m, const uint2 *d_tran
                                        t->frontier[0], s);
     if (rc != LHS_OK)
         return rc;
+    if (parents)
+        hipLaunchKernelGGL(k_begin_parents, dim3(1), dim3(1), 0, s, t->parent, t->frontier[0], t->dead_rec);
     hipLaunchKernelGGL(k_zero_level, dim3(1), dim3(1), 0, s, t->level);
     GraphCtx &h = *h_ctx;
     std::memset(&h, 0, sizeof(h));
-    h.t = view(t);
+    h.t = bfs_view(t, parents);
     h.m = model_view(m, d_trans);
     h.fr[0] = t->frontier[0];
     h.fr[1] = t->frontier[1];
@@ -438,9 +459,12 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
         opts = *o;
     const uint32_t max_levels = opts.max_levels ? opts.max_levels : (1u << 20);
     hipStream_t s = (hipStream_t)opts.hip_stream;
+    const bool parents = (opts.flags & REACH_F_PARENTS) != 0;
 
     lhs_table *t = opts.table;
     bool own = false;
+    if (parents && !t)
+        return LHS_EINVAL;   // the records live in the caller's table
     if (t) {
         if (t->W != W)
             return LHS_EINVAL;
@@ -471,6 +495,14 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
     Workspace &ws = workspace(dev);
     std::unique_lock<std::mutex> lock(ws.mu);
     rc = ensure_bfs_buffers(t);
+    if (rc == LHS_OK && parents && !t->parent &&
+        (hipMalloc(&t->parent, t->capacity * sizeof(uint32_t)) != hipSuccess ||
+         hipMalloc(&t->dead_rec, (1 + kDeadRecord) * sizeof(uint32_t)) != hipSuccess)) {
+        (void)hipGetLastError();
+        (void)hipFree(t->parent);
+        t->parent = nullptr;
+        rc = LHS_ENOMEM;
+    }
     if (rc == LHS_OK)
         rc = ws_reserve(ws, c.off, c.off);
     uint2 *d_trans = at<uint2>(ws.dev, o_trans);
@@ -488,9 +520,9 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
     if (rc == LHS_OK) {
         (void)hipEventRecord(ws.ev[0], s);
         if (opts.flags & REACH_F_GRAPH)
-            rc = explore_graph(t, m, d_trans, max_levels, s, r, d_init, at<GraphCtx>(ws.host, o_ctx));
+            rc = explore_graph(t, m, d_trans, max_levels, s, r, d_init, at<GraphCtx>(ws.host, o_ctx), parents);
         else
-            rc = explore_host_loop(t, m, d_trans, max_levels, s, r, d_init);
+            rc = explore_host_loop(t, m, d_trans, max_levels, s, r, d_init, parents);
         (void)hipEventRecord(ws.ev[1], s);
         if (hipEventSynchronize(ws.ev[1]) == hipSuccess) {
             float ms = 0;
@@ -503,6 +535,7 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
                 r->wait_hits = st.wait_hits;
         }
     }
+    t->has_parents = parents && rc == LHS_OK;
     if (hipStreamSynchronize(s) != hipSuccess && rc == LHS_OK)
         rc = LHS_EDEVICE;
     lock.unlock();
@@ -511,6 +544,58 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
     if (rc != LHS_OK)
         reach_result_free(r);
     return rc;
+}
+
+lhs_status reach_trace(lhs_table *t, uint32_t slot, uint32_t *h_path, uint32_t *h_rows, uint32_t max_len,
+                       uint32_t *len) {
+    if (!t || !len || !t->has_parents || slot >= t->capacity)
+        return LHS_EINVAL;
+    if (hipStreamSynchronize(t->last_stream) != hipSuccess)
+        return LHS_EDEVICE;
+    uint64_t word = 0;
+    LHS_HIP(hipMemcpy(&word, t->bucket + slot, sizeof(word), hipMemcpyDeviceToHost));
+    if ((word >> 62) != 3u)
+        return LHS_EINVAL;   // no stored state in this slot
+    // walk the predecessor records back to s0 (its own predecessor)
+    std::vector<uint32_t> rev{slot};
+    for (uint64_t hops = 0;; ++hops) {
+        if (hops > t->capacity)
+            return LHS_EDEVICE;   // not a chain to s0
+        uint32_t p = 0;
+        LHS_HIP(hipMemcpy(&p, t->parent + rev.back(), sizeof(p), hipMemcpyDeviceToHost));
+        if (p == rev.back())
+            break;
+        if (p >= t->capacity)
+            return LHS_EDEVICE;
+        rev.push_back(p);
+    }
+    *len = (uint32_t)rev.size();
+    if (rev.size() > max_len)
+        return (h_path || h_rows) ? LHS_EINVAL : LHS_OK;
+    for (size_t i = 0; i < rev.size(); ++i) {
+        const uint32_t sl = rev[rev.size() - 1 - i];
+        if (h_path)
+            h_path[i] = sl;
+        if (h_rows)
+            LHS_HIP(hipMemcpy(h_rows + i * t->W, t->data + (uint64_t)sl * t->W, t->W * sizeof(uint32_t),
+                              hipMemcpyDeviceToHost));
+    }
+    return LHS_OK;
+}
+
+lhs_status reach_deadlock_slots(lhs_table *t, uint32_t *h_slots, uint32_t max, uint32_t *n) {
+    if (!t || !n || !t->has_parents)
+        return LHS_EINVAL;
+    if (hipStreamSynchronize(t->last_stream) != hipSuccess)
+        return LHS_EDEVICE;
+    uint32_t count = 0;
+    LHS_HIP(hipMemcpy(&count, t->dead_rec, sizeof(count), hipMemcpyDeviceToHost));
+    const uint32_t kept = std::min(count, kDeadRecord);
+    *n = count;
+    const uint32_t k = std::min(kept, max);
+    if (h_slots && k)
+        LHS_HIP(hipMemcpy(h_slots, t->dead_rec + 1, k * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    return LHS_OK;
 }
 
 void reach_result_free(reach_result *r) {

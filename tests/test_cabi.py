@@ -99,3 +99,17 @@ def test_server_rejects_bad_arguments():
     assert L.reach_server_submit(None, None, ctypes.byref(t)) == 1
     assert L.reach_server_poll(None, 1, None, None) == 1
     assert L.reach_server_destroy(None) == 0
+
+
+def test_trace_calls_reject_bad_arguments():
+    import gen
+    L = lhs.lib()
+    n = ctypes.c_uint32()
+    assert L.reach_trace(None, 0, None, None, 0, ctypes.byref(n)) == 1
+    assert L.reach_deadlock_slots(None, None, 0, ctypes.byref(n)) == 1
+    # predecessor records need a caller table
+    m = gen.tiny_cyclic()
+    st, keep = lhs._model_struct(m, None)
+    o = lhs.ReachOpts(0, 0, lhs.REACH_F_PARENTS, None, None)
+    r = lhs.ReachResultC()
+    assert L.reach_explore(ctypes.byref(st), ctypes.byref(o), ctypes.byref(r)) == 1
