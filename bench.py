@@ -223,6 +223,13 @@ def main():
         if traffic:
             roofline["traffic_over_algorithmic"] = round(traffic / (bpo * launch_ops), 3)
 
+    props = torch.cuda.get_device_properties(0)
+    cpu_name = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_name = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     out = {
         "metric": METRIC, "value": round(ops_per_s, 1), "unit": "find-or-put ops/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -240,6 +247,9 @@ def main():
         "table_shape": {"tuning_entries": n_tuned, "stream_table": table.config(),
                         "tps_in_effect": [info["tps_find_or_put"], info["tps_expand"]]},
         "wall_s_timed": round(wall, 3),
+        "host": {"gpu": props.name, "arch": props.gcnArchName, "cus": props.multi_processor_count,
+                 "hbm_gib": round(props.total_memory / 2**30, 1), "cpu": cpu_name,
+                 "nproc": os.cpu_count()},
     }
 
     if not args.no_probes:

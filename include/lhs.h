@@ -168,10 +168,19 @@ typedef struct lhs_info {
     uint32_t tps_find_or_put; /* lanes per operation in effect (defaults
                                  resolved)                                   */
     uint32_t tps_expand;
+    uint64_t lines_probed; /* lines examined by find-or-puts while counted
+                              (lhs_set_counters); the paper's probe count     */
 } lhs_info;
 
 /* Table geometry and device counters (synchronises the last stream). */
 lhs_status lhs_get_info(lhs_table *t, lhs_info *out);
+
+/* Optional device counters for later calls on t: LHS_COUNT_LINES adds the
+ * number of lines every find-or-put examines to lhs_info.lines_probed (one
+ * more atomic per wavefront; off by default).  0 turns them off; the counts
+ * restart at lhs_clear.  LHS_EINVAL for unknown bits. */
+#define LHS_COUNT_LINES 1u
+lhs_status lhs_set_counters(lhs_table *t, uint32_t flags);
 
 /* ------------------------------------------------------------------------
  * Tuning table: table shapes chosen by the autotuner

@@ -32,7 +32,7 @@ TUNE_TABLE, TUNE_BATCH = 0, 1
 
 #: every symbol include/lhs.h declares
 EXPORTS = ["lhs_strerror", "lhs_create", "lhs_create_ex", "lhs_get_config", "lhs_destroy",
-           "lhs_clear", "lhs_find_or_put", "lhs_set_threads_per_state",
+           "lhs_clear", "lhs_find_or_put", "lhs_set_threads_per_state", "lhs_set_counters",
            "lhs_tune_load", "lhs_tune_clear", "lhs_tune_lookup",
            "lhs_check", "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info",
            "reach_explore", "reach_result_free", "reach_explore_batch", "reach_trace",
@@ -54,7 +54,8 @@ class LhsInfo(ctypes.Structure):
                 ("line_slots", ctypes.c_uint32), ("hash_seed", ctypes.c_uint64),
                 ("wait_hits", ctypes.c_uint64), ("cas_failures", ctypes.c_uint64),
                 ("error", ctypes.c_uint32), ("probe", ctypes.c_uint32),
-                ("tps_find_or_put", ctypes.c_uint32), ("tps_expand", ctypes.c_uint32)]
+                ("tps_find_or_put", ctypes.c_uint32), ("tps_expand", ctypes.c_uint32),
+                ("lines_probed", ctypes.c_uint64)]
 
 
 class LhsConfig(ctypes.Structure):
@@ -139,6 +140,7 @@ def lib() -> ctypes.CDLL:
         L.lhs_find_or_put.argtypes = [p, p, u64, p, p, p]
         L.lhs_check.argtypes = [p]
         L.lhs_set_threads_per_state.argtypes = [p, u32]
+        L.lhs_set_counters.argtypes = [p, u32]
         L.lhs_count.argtypes = [p, ctypes.POINTER(u64)]
         L.lhs_dump.argtypes = [p, p, p, u64, ctypes.POINTER(u64)]
         L.lhs_dump_slots.argtypes = [p, p]
@@ -165,7 +167,7 @@ def lib() -> ctypes.CDLL:
         L.lhs_probe_copy.argtypes = [p, p, u64, p]
         for name in ("lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_copy",
                      "lhs_create", "lhs_destroy", "lhs_clear", "lhs_find_or_put", "lhs_check",
-                     "lhs_set_threads_per_state", "lhs_create_ex", "lhs_get_config",
+                     "lhs_set_threads_per_state", "lhs_set_counters", "lhs_create_ex", "lhs_get_config",
                      "lhs_tune_load", "lhs_tune_clear", "lhs_tune_lookup",
                      "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info", "reach_explore",
                      "reach_explore_batch", "reach_trace", "reach_deadlock_slots",
@@ -209,11 +211,13 @@ def tune_load(path: str, device: str | None = None) -> int:
 
 
 def tune_load_default() -> int:
-    """Load the package's tuning table if it exists; returns the entries kept
-    (0 if there is none or it was measured on another device)."""
-    if not os.path.exists(TUNE_PATH_DEFAULT):
+    """Load the tuning table named by the LHS_TUNE_FILE environment variable,
+    else the package's own if it exists; returns the entries kept (0 if there
+    is none or it was measured on another device)."""
+    path = os.environ.get("LHS_TUNE_FILE") or TUNE_PATH_DEFAULT
+    if not os.path.exists(path):
         return 0
-    return tune_load(TUNE_PATH_DEFAULT)
+    return tune_load(path)
 
 
 def tune_clear():
@@ -281,6 +285,10 @@ class Table:
 
     def set_threads_per_state(self, tps: int):
         _check(lib().lhs_set_threads_per_state(self.handle, tps), "lhs_set_threads_per_state")
+
+    def set_counters(self, flags: int):
+        """LHS_COUNT_LINES (1): count lines probed (lhs_info.lines_probed)."""
+        _check(lib().lhs_set_counters(self.handle, flags), "lhs_set_counters")
 
     def count(self) -> int:
         c = ctypes.c_uint64()

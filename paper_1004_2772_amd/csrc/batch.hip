@@ -269,7 +269,7 @@ __global__ void k_clear_tables(const TableZero *z) {
          i += (unsigned long long)gridDim.x * blockDim.x)
         tz.bucket[i] = make_uint4(0, 0, 0, 0);
     if (blockIdx.x == 0 && threadIdx.x == 0)
-        *tz.status = DevStatus{0, 0, 0, 0};
+        *tz.status = DevStatus{0, 0, 0, 0, 0};
 }
 
 // Copy levels 1 .. n_levels-1 of every model into one compact array, model

@@ -468,7 +468,7 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
             s_acc_dead = 0;
         }
     }
-    flush_counters(t.status, cnt);
+    flush_counters(t, cnt);
     return s_abort != 0;
 }
 

@@ -42,12 +42,16 @@ struct DevStatus {
     uint32_t pad;
     unsigned long long wait_hits;
     unsigned long long cas_failures;
+    unsigned long long lines;   // lines probed (only while counted, see TableView::flags)
 };
+
+enum : uint32_t { kCountLines = 1 };
 
 // Per-lane event counts, reduced per wavefront before touching DevStatus.
 struct LaneCounters {
     uint32_t waits = 0;
     uint32_t cas_failures = 0;
+    uint32_t lines = 0;
 };
 
 // Probe sequence across lines (after the home line's walk).
@@ -67,6 +71,7 @@ struct TableView {
     // kDeadRecord deadlock states expanded]
     uint32_t *parent;
     uint32_t *dead_rec;
+    uint32_t flags;          // kCountLines: add lines probed to status->lines
 };
 constexpr uint32_t kDeadRecord = 1024;
 
@@ -352,6 +357,7 @@ __device__ __forceinline__ void find_or_put(const TableView &t, const Vec &v, ui
             empty = rotr_line<LS>(e, start);
             cand = rotr_line<LS>(e | m, start);
             have_line = true;
+            cnt.lines += g.leader();
         }
         if (cand == 0) {
             have_line = false;
@@ -620,6 +626,7 @@ __device__ __forceinline__ void find_or_put_wave(const TableView &t, WaveScratch
                 cand = rotr_line<LS>(e | m, start);
                 donem = rotr_line<LS>(dn, start);
                 have_line = true;
+                ++cnt.lines;
             }
         }
         // ---- next candidate in walk order ---------------------------------
@@ -704,13 +711,18 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
 
 // Flush lane counters into the table status: one atomic per wavefront.
 // Must be called by all 64 lanes of the wavefront.
-__device__ __forceinline__ void flush_counters(DevStatus *st, const LaneCounters &c) {
+// Lines probed are added only when the table counts them (one more atomic
+// per wavefront, on by request: see lhs_set_counters).
+__device__ __forceinline__ void flush_counters(const TableView &t, const LaneCounters &c) {
     const uint32_t w = wave_sum(c.waits), f = wave_sum(c.cas_failures);
+    const uint32_t l = (t.flags & kCountLines) ? wave_sum(c.lines) : 0u;
     if (__lane_id() == 0) {
         if (w)
-            atomicAdd(&st->wait_hits, (unsigned long long)w);
+            atomicAdd(&t.status->wait_hits, (unsigned long long)w);
         if (f)
-            atomicAdd(&st->cas_failures, (unsigned long long)f);
+            atomicAdd(&t.status->cas_failures, (unsigned long long)f);
+        if (l)
+            atomicAdd(&t.status->lines, (unsigned long long)l);
     }
 }
 

@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_find_or_put(TableView t, const uint3
             }
         }
     }
-    flush_counters(t.status, cnt);
+    flush_counters(t, cnt);
 }
 
 __global__ void k_zero_u64(uint64_t *p, uint64_t n) {
@@ -117,6 +117,7 @@ __global__ void k_zero_status(DevStatus *st) {
     st->error = 0;
     st->wait_hits = 0;
     st->cas_failures = 0;
+    st->lines = 0;
 }
 
 // Done slots are scanned in chunks of kLineSlots slots (any line width).
@@ -382,6 +383,13 @@ lhs_status lhs_set_threads_per_state(lhs_table *t, uint32_t tps) {
     return LHS_OK;
 }
 
+lhs_status lhs_set_counters(lhs_table *t, uint32_t flags) {
+    if (!t || (flags & ~LHS_COUNT_LINES))
+        return LHS_EINVAL;
+    t->counters = flags;
+    return LHS_OK;
+}
+
 lhs_status lhs_get_config(lhs_table *t, lhs_config *out) {
     if (!t || !out)
         return LHS_EINVAL;
@@ -481,6 +489,7 @@ lhs_status lhs_get_info(lhs_table *t, lhs_info *out) {
     out->hash_seed = t->seed;
     out->wait_hits = st.wait_hits;
     out->cas_failures = st.cas_failures;
+    out->lines_probed = st.lines;
     out->error = st.error;
     return LHS_OK;
 }

@@ -113,6 +113,7 @@ __global__ __launch_bounds__(kDefaultMaxActive) void k_step_finalize(BatchSlot *
         st[a].error = 0;
         st[a].wait_hits = 0;
         st[a].cas_failures = 0;
+        st[a].lines = 0;
         tiles = (S.n_front + kExpandBlock - 1) / kExpandBlock;
     }
     // inclusive scan of the tile counts (Hillis-Steele)
@@ -152,6 +153,7 @@ __global__ void k_zero_step(LevelCounters *lc, DevStatus *st, uint32_t n) {
         st[i].error = 0;
         st[i].wait_hits = 0;
         st[i].cas_failures = 0;
+        st[i].lines = 0;
     }
 }
 

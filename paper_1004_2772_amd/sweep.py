@@ -10,7 +10,7 @@ band up to 99.9 % of its slots.  A band inserts its share of seeded distinct
 vectors and, mixed in at random positions, looks up n times as many vectors
 drawn uniformly from those stored before the band (capped at 2^24 reads per
 band); each band is one find-or-put call, timed with HIP events, into a
-table of the tuned shape.  Every band
+table of the tuned shape, counting the lines every operation probes.  Every band
 is checked: inserted rows must report new, looked-up rows seen, and the
 table count must equal the rows inserted so far.
 """
@@ -43,6 +43,8 @@ def run_one(W: int, log2cap: int, n_reads: int, seed: int) -> list:
     out = []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with Table(cap, W) as t:
+        t.set_counters(1)          # lines probed per operation
+        lines_before = 0
         lo = 0
         for b, frac in enumerate(BANDS):
             hi = int(cap * frac)
@@ -72,8 +74,11 @@ def run_one(W: int, log2cap: int, n_reads: int, seed: int) -> list:
             ok = bool(np.all(seen_h[is_write] == 0) and np.all(seen_h[~is_write] == 1))
             count = t.count()
             ok = ok and count == hi
+            lines = t.info()["lines_probed"]
             out.append({"fill_from": round(lo / cap, 4), "fill_to": frac, "writes": nw, "reads": nr,
-                        "ms": round(ms, 4), "Gops": round(ops / ms / 1e6, 3), "ok": ok})
+                        "ms": round(ms, 4), "Gops": round(ops / ms / 1e6, 3),
+                        "lines_per_op": round((lines - lines_before) / ops, 3), "ok": ok})
+            lines_before = lines
             if not ok:
                 raise RuntimeError(f"sweep W={W} 2^{log2cap} n={n_reads} band {frac}: wrong seen flags "
                                    f"or count {count} != {hi}")

@@ -133,3 +133,30 @@ def test_empty_batch(lhs):
                       torch.empty(0, dtype=torch.uint8, device="cuda"))
         t.check()
         assert t.count() == 0
+
+
+@pytest.mark.parametrize("tps", [1, 4])
+def test_lines_probed_counter(lhs, tps):
+    import torch
+    print(f"\n[fop] lines-probed counter tps={tps}", flush=True)
+    rows = np.unique(gen.words(19, 4100 * 8).reshape(4100, 8), axis=0)[:4000]
+    dev = dev_u32(rows)
+    seen = torch.empty(len(rows), dtype=torch.uint8, device="cuda")
+    with lhs.Table(1 << 16, 8, lhs.config(8, "double", tps, tps)) as t:
+        t.find_or_put(dev[:100], seen[:100])
+        assert t.info()["lines_probed"] == 0            # off by default
+        t.clear()
+        t.set_counters(1)
+        t.find_or_put(dev, seen)                        # 6 % fill: about one line each
+        lines = t.info()["lines_probed"]
+        assert len(rows) <= lines <= 1.05 * len(rows)
+        t.find_or_put(dev, seen)                        # all seen: one line each again
+        assert 2 * len(rows) <= t.info()["lines_probed"] <= 2.1 * len(rows)
+    with lhs.Table(1 << 12, 8, lhs.config(8, "double", tps, tps)) as t:
+        t.set_counters(1)
+        t.find_or_put(dev, seen)                        # 97.7 % fill: longer probe chains
+        # a simulation of random 8-slot lines under double hashing gives
+        # about 1.5 lines per insert when filling to 97.7 %
+        assert 1.3 * len(rows) < t.info()["lines_probed"] < 2.0 * len(rows)
+        with pytest.raises(lhs.LhsError):
+            t.set_counters(2)
