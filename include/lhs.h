@@ -282,6 +282,24 @@ typedef struct reach_opts {
                                   deadlock states expanded, for reach_trace
                                   and reach_deadlock_slots.  Without a caller
                                   table: LHS_EINVAL                          */
+#define REACH_F_ASYNC 8u       /* reach_explore without level barriers (the
+                                  paper's order-free exploration with shared
+                                  state storage and dynamic load balancing):
+                                  one persistent launch whose workgroups
+                                  expand states from a shared FIFO of slots in
+                                  discovery order (pseudo-BFS) and take new
+                                  work as soon as it is appended.  Result:
+                                  total_states, edges and deadlocks as for
+                                  the full BFS; n_levels = 0 and level_counts
+                                  = NULL (levels are not defined).  With a
+                                  state_cap the exploration stops once
+                                  state_cap states are stored; the result then
+                                  holds every state stored (state_cap plus at
+                                  most one pass of 256 per workgroup), the
+                                  counts cover the states expanded, and it is
+                                  flagged capped.  Traces (REACH_F_PARENTS)
+                                  are valid paths, not shortest ones.  Not
+                                  with REACH_F_GRAPH; capacity < 2^32.       */
 #define REACH_F_HOST_LOOP 1u   /* batch: one launch per level step, the host
                                   reads the counters after each (default: one
                                   persistent launch for all levels)           */

@@ -27,6 +27,7 @@ REACH_NONE = 0xFFFFFFFF
 REACH_F_HOST_LOOP = 1
 REACH_F_GRAPH = 2
 REACH_F_PARENTS = 4
+REACH_F_ASYNC = 8
 PROBES = {"double": 0, "linear": 1, "quadratic": 2}
 TUNE_TABLE, TUNE_BATCH = 0, 1
 
@@ -404,7 +405,9 @@ def reach_explore_batch(models, capacity: int = 0, tables=None, stream=None, max
 
 def reach_explore(model, cap: int | None = None, capacity: int = 0, table: Table | None = None,
                   stream=None, max_levels: int = 0, flags: int = 0) -> ReachResult:
-    """Level-synchronous BFS of ``model`` on the GPU (synchronous).
+    """Level-synchronous BFS of ``model`` on the GPU (synchronous); with
+    flags=REACH_F_ASYNC the exploration without level barriers (no level
+    counts: n_levels 0).
 
     model: object with P, L, S, K, trans [P, L, K, 5] (uint32, 0xFFFFFFFF = none),
     init [P + S]; cap overrides model.cap (0 = none)."""

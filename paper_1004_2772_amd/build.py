@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblhs.so")
-SOURCES = ["lhs_table.hip", "reach.hip", "batch.hip", "serve.hip", "probes.hip", "tune.cpp",
+SOURCES = ["lhs_table.hip", "reach.hip", "async.hip", "batch.hip", "serve.hip", "probes.hip", "tune.cpp",
            "workspace.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

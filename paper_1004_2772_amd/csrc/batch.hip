@@ -325,6 +325,8 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
         opts = *o;
     const uint32_t max_levels = opts.max_levels ? opts.max_levels : (1u << 16);
     const bool host_loop = (opts.flags & REACH_F_HOST_LOOP) != 0;
+    if (opts.flags & REACH_F_ASYNC)
+        return LHS_EINVAL;   // the batch keeps levels: its results carry level counts
     hipStream_t s = (hipStream_t)opts.hip_stream;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess)

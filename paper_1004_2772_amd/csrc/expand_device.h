@@ -77,6 +77,8 @@ static __shared__ unsigned long long s_acc_edges, s_acc_dead;
 // New-state buffer fill, its reserved base in next[], and the level's abort
 // / near-the-cap flags as this workgroup last saw them.
 static __shared__ uint32_t s_nnew, s_nbase, s_abort, s_eager;
+// New states appended to next[] since the caller last reset it.
+static __shared__ uint32_t s_pushed;
 
 // Call once at kernel start, before the first expand_tile.
 __device__ __forceinline__ void expand_begin() {
@@ -87,6 +89,7 @@ __device__ __forceinline__ void expand_begin() {
         s_nnew = 0;
         s_abort = 0;
         s_eager = 0;
+        s_pushed = 0;
     }
 }
 
@@ -110,6 +113,7 @@ __device__ __forceinline__ void flush_new_slots(const uint32_t *nbuf, uint32_t *
         if (nn) {
             const uint32_t b = atomicAdd(&lc->n_next, nn);
             s_nbase = b;
+            s_pushed += nn;
             if ((uint64_t)b + nn > limit) {
                 __hip_atomic_store(&lc->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 s_abort = 1;
@@ -194,8 +198,10 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
 // DEFER: new states stay buffered across tiles (flushed when the buffer
 // nears full) and edge/deadlock counts stay in LDS until expand_end
 // (single-model launches, whose workgroups run many tiles of one level);
-// otherwise both go out at the end of every tile.
-template <int G, uint32_t LS, bool COHERENT = false, bool DEFER = false>
+// otherwise both go out at the end of every tile.  DEFER_COUNTS alone keeps
+// only the counts in LDS (the exploration without levels, which must
+// publish every tile's new states at once).
+template <int G, uint32_t LS, bool COHERENT = false, bool DEFER = false, bool DEFER_COUNTS = DEFER>
 __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, const ModelView &m,
                                             const uint32_t *__restrict__ front, uint64_t base,
                                             uint32_t rows, uint32_t *__restrict__ next,
@@ -292,7 +298,8 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
             if (t.parent && is_new) {
                 // predecessor record: the frontier slot of the expanded row
                 const uint32_t row_off = (G == 1 ? my_d0 : d0[q]) & 0xFFFFu;
-                t.parent[slot] = front[base + row_off / stride];
+                const uint32_t *src = front + base + row_off / stride;
+                t.parent[slot] = COHERENT ? ld_coherent(src) : *src;
             }
             const uint64_t nm = __ballot(is_new);
             if (nm) {
@@ -451,13 +458,13 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
     if (t.dead_rec && tid < rows && mine == 0) {
         const uint32_t k = atomicAdd(t.dead_rec, 1u);
         if (k < kDeadRecord)
-            t.dead_rec[1 + k] = front[base + tid];
+            t.dead_rec[1 + k] = COHERENT ? ld_coherent(front + base + tid) : front[base + tid];
     }
     if (__lane_id() == 0) {
         atomicAdd(&s_acc_edges, (unsigned long long)e32);
         atomicAdd(&s_acc_dead, (unsigned long long)d32);
     }
-    if constexpr (!DEFER) {
+    if constexpr (!DEFER_COUNTS) {
         __syncthreads();
         if (tid == 0) {
             if (s_acc_edges)

@@ -127,16 +127,6 @@ __global__ void k_begin_parents(uint32_t *parent, const uint32_t *front, uint32_
     dead_rec[0] = 0;
 }
 
-// The view a BFS on t expands with: predecessor records when requested.
-TableView bfs_view(lhs_table *t, bool parents) {
-    TableView v = view(t);
-    if (parents) {
-        v.parent = t->parent;
-        v.dead_rec = t->dead_rec;
-    }
-    return v;
-}
-
 __global__ void k_zero_level(LevelCounters *lc) {
     lc->n_next = 0;
     lc->abort = 0;
@@ -147,6 +137,20 @@ __global__ void k_zero_level(LevelCounters *lc) {
 }  // namespace
 
 namespace lhs {
+
+TableView bfs_view(lhs_table *t, bool parents) {
+    TableView v = view(t);
+    if (parents) {
+        v.parent = t->parent;
+        v.dead_rec = t->dead_rec;
+    }
+    return v;
+}
+
+lhs_status begin_parents(lhs_table *t, hipStream_t s) {
+    hipLaunchKernelGGL(k_begin_parents, dim3(1), dim3(1), 0, s, t->parent, t->frontier[0], t->dead_rec);
+    return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
+}
 
 lhs_status validate_model(const reach_model *m) {
     if (!m || !m->trans || !m->init || m->n_procs == 0 || m->n_locals == 0 ||
@@ -266,8 +270,8 @@ lhs_status explore_host_loop(lhs_table *t, const reach_model *m, const uint2 *d_
                                        t->frontier[0], s);
     if (rc != LHS_OK)
         return rc;
-    if (parents)
-        hipLaunchKernelGGL(k_begin_parents, dim3(1), dim3(1), 0, s, t->parent, t->frontier[0], t->dead_rec);
+    if (parents && (rc = begin_parents(t, s)) != LHS_OK)
+        return rc;
     levels.push_back(1);
     uint64_t total = 1, edges = 0, dead = 0;
     uint32_t n_cur = 1, cur = 0;
@@ -348,8 +352,8 @@ lhs_status explore_graph(lhs_table *t, const reach_model *m, const uint2 *d_tran
                                        t->frontier[0], s);
     if (rc != LHS_OK)
         return rc;
-    if (parents)
-        hipLaunchKernelGGL(k_begin_parents, dim3(1), dim3(1), 0, s, t->parent, t->frontier[0], t->dead_rec);
+    if (parents && (rc = begin_parents(t, s)) != LHS_OK)
+        return rc;
     hipLaunchKernelGGL(k_zero_level, dim3(1), dim3(1), 0, s, t->level);
     GraphCtx &h = *h_ctx;
     std::memset(&h, 0, sizeof(h));
@@ -460,6 +464,9 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
     const uint32_t max_levels = opts.max_levels ? opts.max_levels : (1u << 20);
     hipStream_t s = (hipStream_t)opts.hip_stream;
     const bool parents = (opts.flags & REACH_F_PARENTS) != 0;
+    const bool async = (opts.flags & REACH_F_ASYNC) != 0;
+    if (async && (opts.flags & REACH_F_GRAPH))
+        return LHS_EINVAL;   // no levels to capture
 
     lhs_table *t = opts.table;
     bool own = false;
@@ -491,7 +498,7 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
     // model upload through the device's workspace: one copy, no allocation
     Carve c;
     const size_t o_trans = c.take<uint2>(packed.size()), o_init = c.take<uint32_t>(W);
-    const size_t upload = c.off, o_ctx = c.take<GraphCtx>(1);
+    const size_t upload = c.off, o_ctx = c.take<GraphCtx>(1), o_actl = c.take<AsyncCtl>(1);
     Workspace &ws = workspace(dev);
     std::unique_lock<std::mutex> lock(ws.mu);
     rc = ensure_bfs_buffers(t);
@@ -519,7 +526,10 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
     }
     if (rc == LHS_OK) {
         (void)hipEventRecord(ws.ev[0], s);
-        if (opts.flags & REACH_F_GRAPH)
+        if (async)
+            rc = explore_async(t, m, d_trans, s, r, d_init, at<AsyncCtl>(ws.dev, o_actl),
+                               at<AsyncCtl>(ws.host, o_actl), parents);
+        else if (opts.flags & REACH_F_GRAPH)
             rc = explore_graph(t, m, d_trans, max_levels, s, r, d_init, at<GraphCtx>(ws.host, o_ctx), parents);
         else
             rc = explore_host_loop(t, m, d_trans, max_levels, s, r, d_init, parents);

@@ -35,6 +35,18 @@ struct GraphCtx {
     LevelCtl ctl;
 };
 
+// Shared state of an exploration without level barriers (REACH_F_ASYNC).
+// Each counter sits on a 128-byte line of its own: all workgroups poll or
+// update them.
+struct alignas(128) AsyncCtl {
+    unsigned long long work;   // states discovered and not yet expanded
+    char pad0[120];
+    uint32_t chunk;            // next queue chunk to hand out
+    char pad1[124];
+    uint32_t error;            // LHS_ESTALL when a bounded wait ran out
+    char pad2[124];
+};
+
 namespace lhs {
 
 lhs_status validate_model(const reach_model *m);
@@ -43,5 +55,13 @@ ModelView model_view(const reach_model *m, const uint2 *d_trans);
 size_t expand_lds_bytes(uint32_t W, uint32_t tcap, uint32_t tps);
 lhs_status ensure_bfs_buffers(lhs_table *t);
 uint64_t auto_capacity(const reach_model *m);
+// The view a BFS on t expands with: predecessor records when requested.
+TableView bfs_view(lhs_table *t, bool parents);
+// s0 (the first entry of frontier[0]) is its own predecessor; no deadlock
+// recorded yet.
+lhs_status begin_parents(lhs_table *t, hipStream_t s);
+lhs_status explore_async(lhs_table *t, const reach_model *m, const uint2 *d_trans, hipStream_t s,
+                         reach_result *r, const uint32_t *d_init, AsyncCtl *d_ctl, AsyncCtl *h_ctl,
+                         bool parents);
 
 }  // namespace lhs

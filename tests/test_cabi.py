@@ -113,3 +113,19 @@ def test_trace_calls_reject_bad_arguments():
     o = lhs.ReachOpts(0, 0, lhs.REACH_F_PARENTS, None, None)
     r = lhs.ReachResultC()
     assert L.reach_explore(ctypes.byref(st), ctypes.byref(o), ctypes.byref(r)) == 1
+
+
+def test_async_flag_conflicts_rejected():
+    import gen
+    L = lhs.lib()
+    m = gen.tiny_cyclic()
+    st, keep = lhs._model_struct(m, None)
+    r = lhs.ReachResultC()
+    # no levels to capture in a graph
+    o = lhs.ReachOpts(0, 0, lhs.REACH_F_ASYNC | lhs.REACH_F_GRAPH, None, None)
+    assert L.reach_explore(ctypes.byref(st), ctypes.byref(o), ctypes.byref(r)) == 1
+    # the batch keeps levels
+    arr = (ctypes.POINTER(lhs.ReachModel) * 1)(ctypes.pointer(st))
+    res = (lhs.ReachResultC * 1)()
+    o = lhs.ReachOpts(0, 0, lhs.REACH_F_ASYNC, None, None)
+    assert L.reach_explore_batch(arr, 1, ctypes.byref(o), None, res) == 1
