@@ -95,6 +95,7 @@ def main():
                     help="skip the multi-core CPU lockless-table leg")
     ap.add_argument("--no-probes", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-async", action="store_true", help="skip the exploration-without-levels leg")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="query arrivals per second")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
@@ -333,6 +334,47 @@ def main():
                 log(f"tps={tps}: bfs {r.gpu_ms:.1f} ms")
             table.set_threads_per_state(0)
         out["bfs"] = bfs
+
+    if not args.no_async:
+        # exploration without level barriers vs the level loops, on an
+        # uncapped model (same result by definition) and on a chain of
+        # one-state levels
+        def median_ms(m, t, flags, reps):
+            ms, r = [], None
+            for i in range(1 + reps):
+                r = lhs.reach_explore(m, table=t, flags=flags)
+                if i:
+                    ms.append(r.gpu_ms)
+            return sorted(ms)[len(ms) // 2], r
+        reps = max(1, min(args.steps, 3))
+        wm = gen.wide_model()
+        with lhs.Table(gen.WIDE_TABLE_SLOTS, wm.W) as wt:
+            b_ms, rb = median_ms(wm, wt, 0, reps)
+            g_ms, rg = median_ms(wm, wt, lhs.REACH_F_GRAPH, reps)
+            a_ms, ra = median_ms(wm, wt, lhs.REACH_F_ASYNC, reps)
+        nl = {"workload": f"{wm.name}: G(seed={wm.seed}, P={wm.P}, L={wm.L}, S={wm.S}, D={wm.D}, K={wm.K}) "
+                          f"explored to exhaustion, table 2^{gen.WIDE_TABLE_SLOTS.bit_length() - 1}",
+              "states": ra.total, "edges": ra.edges, "deadlocks": ra.deadlocks, "bfs_levels": rb.n_levels,
+              "no_levels_ms": round(a_ms, 2), "states_per_s": round(ra.total / (a_ms / 1e3), 1),
+              "level_loop_ms": round(b_ms, 2), "graph_levels_ms": round(g_ms, 2),
+              "same_result": (ra.total, ra.edges, ra.deadlocks) == (rb.total, rb.edges, rb.deadlocks) ==
+                             (rg.total, rg.edges, rg.deadlocks)}
+        golden = os.path.join(ROOT, "tests", "golden", "wide_model.json")
+        if os.path.exists(golden):
+            with open(golden) as f:
+                g = json.load(f)
+            nl["matches_oracle"] = (g["total"], g["edges"], g["deadlocks"]) == (ra.total, ra.edges, ra.deadlocks)
+        log(f"wide model: level loop {b_ms:.2f} ms, graph levels {g_ms:.2f} ms, no levels {a_ms:.2f} ms")
+        cm = gen.chain_model()
+        with lhs.Table(1 << 16, cm.W) as ct:
+            cg_ms, rcg = median_ms(cm, ct, lhs.REACH_F_GRAPH, 1)
+            ca_ms, rca = median_ms(cm, ct, lhs.REACH_F_ASYNC, 1)
+        nl["chain"] = {"workload": f"chain of {cm.L} one-state levels", "states": rca.total,
+                       "no_levels_ms": round(ca_ms, 2), "graph_levels_ms": round(cg_ms, 2),
+                       "us_per_state_no_levels": round(ca_ms * 1e3 / rca.total, 2),
+                       "same_result": (rca.total, rca.edges) == (rcg.total, rcg.edges)}
+        log(f"chain: graph levels {cg_ms:.1f} ms, no levels {ca_ms:.1f} ms")
+        out["no_levels"] = nl
     if sweep:
         out["tps_sweep"] = sweep
 

@@ -189,6 +189,25 @@ def big_model(cap: int = BIG_CAP) -> Model:
                          cap=cap, name="big12x16")
 
 
+#: Uncapped model explored to exhaustion (no cap, so the exploration without
+#: levels and the BFS define the same result): 8 processes x 6 local states,
+#: 4 shared variables of domain 4, 2 transitions per local state; the seed
+#: was picked from a scan of seeds for a full state space of a few 10^7
+#: states (32 518 299 states in 104 BFS levels).
+WIDE_SEED, WIDE_P, WIDE_L, WIDE_S, WIDE_D, WIDE_K = 78, 8, 6, 4, 4, 2
+WIDE_TABLE_SLOTS = 1 << 26
+
+
+def wide_model() -> Model:
+    return guarded_model(WIDE_SEED, WIDE_P, WIDE_L, WIDE_S, WIDE_D, WIDE_K, cap=0, name="wide8x6")
+
+
+def chain_model(n: int = 20000) -> Model:
+    """One process stepping through n local states: n BFS levels of one
+    state each (the narrowest state space, where level barriers cost most)."""
+    return cyclic_model(1, n)
+
+
 def batch_models() -> list[Model]:
     """The 64-model mix (manifests/batch_models.json): 2-16 processes,
     4-32 local states, state width 4-32, 10^3-10^6 reachable states each."""

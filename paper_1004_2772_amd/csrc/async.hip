@@ -13,7 +13,7 @@
 //                       the array never wraps); 0xFFFFFFFF = not written yet
 //   lc->n_next          append cursor (states stored so far)
 //   ctl->chunk          next 256-entry chunk to hand out
-//   ctl->work           states appended and not yet expanded
+//   ctl->work           states discovered and not yet expanded
 //
 // A workgroup owns one chunk at a time and expands the chunk's entries as
 // they are appended (all 256 at once in the common case, fewer while the
@@ -21,14 +21,17 @@
 // idle workgroups pick up new work as soon as it exists instead of at a
 // level boundary.  The expansion itself is the BFS tile (expand_tile):
 // LDS-staged rows, guarded successors, find-or-put, compaction of the new
-// states, appended with one atomic per tile.
+// states into an LDS buffer.  The buffer is appended to the queue with one
+// atomic when it nears full, and whenever the workgroup's own chunk has no
+// entry left to expand, so held-back states never starve an idle GPU.
 //
-// Termination: every tile adds (states it appended - states it expanded) to
-// ctl->work in one atomic after its appends, so work only reaches 0 when no
-// state is open and no tile is in flight; then no state can be appended
-// again and every workgroup leaves.  The order of expansion varies from run
-// to run, so per-level counts are not defined; the reachable set, edges and
-// deadlocks are (they do not depend on the order).
+// Termination: after every tile a workgroup adds (states it discovered,
+// appended or buffered - states it expanded) to ctl->work in one atomic, so
+// work only reaches 0 when no state is open anywhere (queued, buffered or
+// in a tile in flight); then no state can be discovered again and every
+// workgroup leaves.  The order of expansion varies from run to run, so
+// per-level counts are not defined; the reachable set, edges and deadlocks
+// are (they do not depend on the order).
 #include <algorithm>
 #include <cstring>
 
@@ -70,15 +73,18 @@ __global__ __launch_bounds__(kExpandBlock) void k_explore_async(TableView t, Mod
                                                                 uint32_t limit, uint32_t tcap) {
     extern __shared__ uint32_t smem[];
     expand_begin();
-    __shared__ uint32_t s_from, s_take, s_fail;
+    enum : uint32_t { kStop = 0, kExpand = 1, kPublish = 2 };
+    __shared__ uint32_t s_from, s_take, s_act;
     const uint32_t tid = threadIdx.x;
+    uint32_t *nbuf = expand_nbuf<G>(smem, m.W, tcap);
     // thread 0: the owned chunk is queue[base, base + kChunk), its first
-    // `used` entries already expanded
+    // `used` entries already taken; `found` = new states this workgroup has
+    // discovered (appended or still buffered) as of its last work update
     uint64_t base = 0;
-    uint32_t used = kChunk, polls = 0, last_tail = 0;
+    uint32_t used = kChunk, polls = 0, last_tail = 0, found = 0;
     while (true) {
         if (tid == 0) {
-            uint32_t take = 0;
+            uint32_t take = 0, act = kStop;
             while (true) {
                 if (used == kChunk) {
                     base = (uint64_t)atomicAdd(&ctl->chunk, 1u) * kChunk;
@@ -88,9 +94,15 @@ __global__ __launch_bounds__(kExpandBlock) void k_explore_async(TableView t, Mod
                 const uint64_t end = min<uint64_t>(tl, base + kChunk);
                 if (end > base + used) {
                     take = (uint32_t)(end - base - used);
+                    act = kExpand;
                     break;
                 }
-                // nothing appended to this chunk yet: finished, failed, or wait
+                // nothing appended to this chunk yet: publish the states this
+                // workgroup holds back first (others may be waiting for them)
+                if (s_nnew) {
+                    act = kPublish;
+                    break;
+                }
                 if (ld_coherent(&ctl->work) == 0 || ld_coherent(&lc->abort) ||
                     ld_coherent(&t.status->error) || ld_coherent(&ctl->error))
                     break;
@@ -106,40 +118,31 @@ __global__ __launch_bounds__(kExpandBlock) void k_explore_async(TableView t, Mod
             // entries below the cursor are below the capacity (< 2^32)
             s_from = (uint32_t)(base + used);
             s_take = take;
-            s_fail = 0;
+            s_act = act;
             used += take;
         }
         __syncthreads();
-        const uint32_t from = s_from, n = s_take;
-        if (n == 0)
+        const uint32_t act = s_act, from = s_from, n = s_take;
+        if (act == kStop)
             break;
-        // the entries are reserved; their writers store them right after
-        if (tid < n) {
-            uint32_t spins = 0;
-            while (ld_coherent(queue + from + tid) == kNoEntry) {
-                if (++spins > kStallPolls) {
-                    atomicCAS(&ctl->error, 0u, (uint32_t)LHS_ESTALL);
-                    s_fail = 1;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
+        if (act == kPublish) {
+            flush_new_slots<true>(nbuf, queue, lc, limit);
+            continue;
         }
-        __syncthreads();
-        if (s_fail)
-            break;
-        const bool aborted = expand_tile<G, LS, true, false, true>(smem, t, m, queue, from, n, queue, lc,
-                                                                   limit, tcap);
+        // new states stay buffered across tiles while this chunk has work
+        const bool aborted =
+            expand_tile<G, LS, true, true, true, true>(smem, t, m, queue, from, n, queue, lc, limit, tcap);
         if (tid == 0) {
-            // appended - expanded, after the appends themselves
-            atomicAdd(&ctl->work, (unsigned long long)s_pushed - (unsigned long long)n);
-            s_pushed = 0;
+            // discovered - expanded, after the discoveries are counted
+            const uint32_t now = s_pushed + s_nnew;
+            atomicAdd(&ctl->work, (unsigned long long)(now - found) - (unsigned long long)n);
+            found = now;
         }
         if (aborted)
             break;
     }
-    // edge / deadlock counts kept in LDS over the launch
-    expand_end<G>(smem, m.W, tcap, queue, lc, limit);
+    // counts kept in LDS over the launch (and, after an abort, the buffer)
+    expand_end<G, true>(smem, m.W, tcap, queue, lc, limit);
 }
 
 }  // namespace

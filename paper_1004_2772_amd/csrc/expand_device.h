@@ -79,6 +79,8 @@ static __shared__ unsigned long long s_acc_edges, s_acc_dead;
 static __shared__ uint32_t s_nnew, s_nbase, s_abort, s_eager;
 // New states appended to next[] since the caller last reset it.
 static __shared__ uint32_t s_pushed;
+// Set when a wait for a frontier entry ran out (AWAIT): the launch stops.
+static __shared__ uint32_t s_stall;
 
 // Call once at kernel start, before the first expand_tile.
 __device__ __forceinline__ void expand_begin() {
@@ -90,6 +92,7 @@ __device__ __forceinline__ void expand_begin() {
         s_abort = 0;
         s_eager = 0;
         s_pushed = 0;
+        s_stall = 0;
     }
 }
 
@@ -144,10 +147,10 @@ __device__ __forceinline__ void flush_new_slots(const uint32_t *nbuf, uint32_t *
 // accumulated edge/deadlock counts to lc.  Call by all threads after the
 // last expand_tile of the launch (also after an aborted tile: every claimed
 // slot must be listed in next[] for the rollback).
-template <int G>
+template <int G, bool COHERENT = false>
 __device__ __forceinline__ void expand_end(uint32_t *smem, uint32_t W, uint32_t tcap, uint32_t *next,
                                            LevelCounters *lc, uint32_t limit) {
-    flush_new_slots<false>(expand_nbuf<G>(smem, W, tcap), next, lc, limit);
+    flush_new_slots<COHERENT>(expand_nbuf<G>(smem, W, tcap), next, lc, limit);
     if (threadIdx.x == 0) {
         if (s_acc_edges)
             atomicAdd(&lc->edges, s_acc_edges);
@@ -199,9 +202,12 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
 // nears full) and edge/deadlock counts stay in LDS until expand_end
 // (single-model launches, whose workgroups run many tiles of one level);
 // otherwise both go out at the end of every tile.  DEFER_COUNTS alone keeps
-// only the counts in LDS (the exploration without levels, which must
-// publish every tile's new states at once).
-template <int G, uint32_t LS, bool COHERENT = false, bool DEFER = false, bool DEFER_COUNTS = DEFER>
+// only the counts in LDS.
+// AWAIT (with COHERENT): a frontier entry may still be in flight; 0xFFFFFFFF
+// marks one not yet written, which the staging lane waits for (bounded:
+// LHS_ESTALL and an aborted tile).
+template <int G, uint32_t LS, bool COHERENT = false, bool DEFER = false, bool DEFER_COUNTS = DEFER,
+          bool AWAIT = false>
 __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, const ModelView &m,
                                             const uint32_t *__restrict__ front, uint64_t base,
                                             uint32_t rows, uint32_t *__restrict__ next,
@@ -243,9 +249,31 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
         for (uint32_t i = tid; i < PLK; i += kBlock)
             tr_lds[i] = m.trans[i];
     succ_cnt[tid] = 0;
-    if (tid < rows) {
+    bool staged = tid < rows;
+    uint64_t slot = 0;
+    if (staged) {
         // rows of earlier levels were published before this level started
-        const uint64_t slot = COHERENT ? ld_coherent(front + base + tid) : front[base + tid];
+        slot = COHERENT ? ld_coherent(front + base + tid) : front[base + tid];
+        if constexpr (AWAIT) {
+            for (uint32_t spins = 0; slot == 0xFFFFFFFFu; ++spins) {
+                // give up on an aborted launch (the writer may have stopped)
+                // or after the bound (then also an error)
+                const bool out = spins >= kSpinLimit;
+                if (out || ((spins & 63u) == 63u &&
+                            __hip_atomic_load(&lc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                    if (out)
+                        set_error(t.status, 4u /* LHS_ESTALL */);
+                    __hip_atomic_store(&lc->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s_stall = 1;
+                    staged = false;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                slot = ld_coherent(front + base + tid);
+            }
+        }
+    }
+    if (staged) {
         const uint32_t *src = t.data + slot * W;
         uint32_t *dst = tile + tid * stride;
         if (COHERENT && (W & 1u) == 0) {
@@ -275,7 +303,7 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
     __syncthreads();
     if (restage && tid == 0)
         s_trans_staged = m.trans;
-    if (s_abort)
+    if (s_abort || s_stall)
         return true;
     const uint2 *tr = tr_in_lds ? tr_lds : m.trans;
 

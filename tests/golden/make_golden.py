@@ -6,8 +6,11 @@ oracle only (no GPU code is imported).
                      counts, edges, deadlocks, and the oracle's set digest.
 * batch_models.json — full (uncapped) results of each of the 64 models of the
                      batch mix.
+* wide_model.json  — the uncapped 8-process x 6-local model (gen.wide_model),
+                     explored to exhaustion: per-level counts, edges,
+                     deadlocks and the set digest.
 
-Run:  python tests/golden/make_golden.py [big|batch|all]
+Run:  python tests/golden/make_golden.py [big|batch|wide|all]
 (the 2^27 run needs about 16 GB of host memory and a few minutes).
 """
 import json
@@ -51,8 +54,20 @@ def batch():
     print("batch", len(out), sum(e["total"] for e in out), flush=True)
 
 
+def wide():
+    m = gen.wide_model()
+    t = time.time()
+    r = oracle.reach(m)
+    e = _entry(m, r, time.time() - t)
+    with open(os.path.join(HERE, "wide_model.json"), "w") as f:
+        json.dump(e, f, indent=1)
+    print("wide", e["total"], e["n_levels"], e["edges"], e["capped"], e["oracle_seconds"], flush=True)
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "all"
+    if what in ("wide", "all"):
+        wide()
     if what in ("batch", "all"):
         batch()
     if what in ("big", "all"):

@@ -5,6 +5,9 @@
   run (tests/golden/big_model.json, written by tests/golden/make_golden.py
   with the oracle only), and the stored set against the oracle's set digest;
   slot invariants on a sample of stored rows.
+* the uncapped 8-process x 6-local model (32.5M states): BFS per-level
+  counts and the exploration without levels (REACH_F_ASYNC) against the
+  oracle's recorded run (tests/golden/wide_model.json) and set digest.
 * the raw stream: 2^26 rows of 16 words (2^25 distinct, each twice) into a
   2^28-slot table, as one call and as 2^22-row calls, against the sequential
   oracle run on the same stream.
@@ -93,3 +96,28 @@ def test_stream_2p26(lhs, full_stream, shape, batch):
         t.check()
         assert t.count() == distinct
     check_stream_batches(o_id, distinct, seen.cpu().numpy(), idx.cpu().numpy().view(np.uint32), bounds)
+
+
+@pytest.mark.parametrize("shape", ["tuned", "default"])
+def test_wide_model_levels_and_no_levels(lhs, shape):
+    # the uncapped 32.5M-state model: BFS against every recorded level count,
+    # the exploration without levels against the order-free fields; both
+    # against the oracle's set digest
+    print(f"\n[full] wide model, {shape} shape", flush=True)
+    with open(os.path.join(GOLDEN, "wide_model.json")) as f:
+        g = json.load(f)
+    m = gen.wide_model()
+    assert (m.seed, m.P, m.L, m.S, m.D, m.K) == (int(g["seed"], 0), g["P"], g["L"], g["S"], g["D"], g["K"])
+    want_digest = [g["total"], g["digest"][1], g["digest"][2]]
+    with _table(lhs, shape, gen.WIDE_TABLE_SLOTS, m.W) as t:
+        r = lhs.reach_explore(m, table=t)
+        print(f"bfs {r.gpu_ms:.1f} ms", flush=True)
+        assert (r.total, r.n_levels, r.level_counts, r.edges, r.deadlocks, r.capped) == \
+            (g["total"], g["n_levels"], g["level_counts"], g["edges"], g["deadlocks"], False)
+        a = lhs.reach_explore(m, table=t, flags=lhs.REACH_F_ASYNC)
+        print(f"no levels {a.gpu_ms:.1f} ms", flush=True)
+        assert (a.total, a.n_levels, a.edges, a.deadlocks, a.capped) == \
+            (g["total"], 0, g["edges"], g["deadlocks"], False)
+        rows, _ = check_table_invariants(t, sample=200_000)
+    d = oracle.digest(rows)
+    assert [d[0], hex(d[1]), hex(d[2])] == want_digest
