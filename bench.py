@@ -282,6 +282,13 @@ def main():
         ceiling = probes[f"random_{lb}B_lines_{lb // 16}lane_GBs"]
         probes["fop_frac_of_random_line"] = round(achieved / ceiling, 4)
         probes["fop_frac_of_random_line_ceiling"] = f"random_{lb}B_lines_{lb // 16}lane_GBs"
+        # slot CAS issued by the find-or-put launch (one per insert plus the
+        # retries) against the random 64-bit CAS rate of the same GPU
+        cas = n_distinct + info["cas_failures"]
+        cas_per_s = cas / (launch_ms / 1e3) if n_launch == 1 else None
+        probes["fop_cas_per_s"] = round(cas_per_s, 1) if cas_per_s else None
+        probes["fop_cas_frac_of_random_cas"] = (round(cas_per_s / 1e9 / probes["random_cas64_Gops"], 4)
+                                                if cas_per_s else None)
         out["probes"] = probes
         log(f"probes: {probes}")
 

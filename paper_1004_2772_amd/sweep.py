@@ -10,9 +10,11 @@ band up to 99.9 % of its slots.  A band inserts its share of seeded distinct
 vectors and, mixed in at random positions, looks up n times as many vectors
 drawn uniformly from those stored before the band (capped at 2^24 reads per
 band); each band is one find-or-put call, timed with HIP events, into a
-table of the tuned shape, counting the lines every operation probes.  Every band
-is checked: inserted rows must report new, looked-up rows seen, and the
-table count must equal the rows inserted so far.
+table of the tuned shape.  A second, identical fill of a fresh table counts
+the lines each band's operations probe (and the waits and CAS retries): the
+count is one atomic per wavefront on one address, which would slow the timed
+pass.  Every band of both passes is checked: inserted rows must report new,
+looked-up rows seen, and the table count must equal the rows inserted so far.
 """
 from __future__ import annotations
 
@@ -33,7 +35,7 @@ def log(msg):
     print(f"[sweep {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def run_one(W: int, log2cap: int, n_reads: int, seed: int) -> list:
+def run_one(W: int, log2cap: int, n_reads: int, seed: int, count: bool = False) -> list:
     import torch
 
     import gen
@@ -43,8 +45,9 @@ def run_one(W: int, log2cap: int, n_reads: int, seed: int) -> list:
     out = []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with Table(cap, W) as t:
-        t.set_counters(1)          # lines probed per operation
-        lines_before = 0
+        if count:
+            t.set_counters(1)      # lines probed per operation
+        lines_before = waits_before = cas_before = 0
         lo = 0
         for b, frac in enumerate(BANDS):
             hi = int(cap * frac)
@@ -74,11 +77,15 @@ def run_one(W: int, log2cap: int, n_reads: int, seed: int) -> list:
             ok = bool(np.all(seen_h[is_write] == 0) and np.all(seen_h[~is_write] == 1))
             count = t.count()
             ok = ok and count == hi
-            lines = t.info()["lines_probed"]
-            out.append({"fill_from": round(lo / cap, 4), "fill_to": frac, "writes": nw, "reads": nr,
-                        "ms": round(ms, 4), "Gops": round(ops / ms / 1e6, 3),
-                        "lines_per_op": round((lines - lines_before) / ops, 3), "ok": ok})
-            lines_before = lines
+            info = t.info()
+            lines, waits, cas = info["lines_probed"], info["wait_hits"], info["cas_failures"]
+            band = {"fill_from": round(lo / cap, 4), "fill_to": frac, "writes": nw, "reads": nr,
+                    "ms": round(ms, 4), "Gops": round(ops / ms / 1e6, 3),
+                    "wait_hits": waits - waits_before, "cas_failures": cas - cas_before, "ok": ok}
+            if count:
+                band["lines_per_op"] = round((lines - lines_before) / ops, 3)
+            out.append(band)
+            lines_before, waits_before, cas_before = lines, waits, cas
             if not ok:
                 raise RuntimeError(f"sweep W={W} 2^{log2cap} n={n_reads} band {frac}: wrong seen flags "
                                    f"or count {count} != {hi}")
@@ -105,6 +112,9 @@ def main(argv=None):
     t0 = time.time()
     for i, (W, c, n) in enumerate(points):
         bands = run_one(W, c, n, 1000 + i)
+        counted = run_one(W, c, n, 1000 + i, count=True)
+        for b, cb in zip(bands, counted):
+            b["lines_per_op"] = cb["lines_per_op"]
         res["points"].append({"W": W, "log2_capacity": c, "reads_per_write": n, "bands": bands})
         log(f"W={W} 2^{c} n={n}: " + " ".join(f"{b['fill_to']:.3f}:{b['Gops']:.2f}" for b in bands))
     res["seconds"] = round(time.time() - t0, 1)

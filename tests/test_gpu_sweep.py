@@ -17,3 +17,9 @@ def test_sweep_quick():
         assert [b["fill_to"] for b in p["bands"]] == sweep.BANDS
         assert all(b["ok"] for b in p["bands"])
         assert p["bands"][-1]["writes"] > 0
+        lines = [b["lines_per_op"] for b in p["bands"]]
+        # probe lengths grow with the fill: about one line per operation
+        # while the table is at most half full, many near 99.9 %
+        assert 1.0 <= lines[0] <= 1.1
+        assert all(a <= b * 1.05 for a, b in zip(lines, lines[1:]))
+        assert lines[-1] > 5 * lines[0]
