@@ -230,8 +230,12 @@ __global__ __launch_bounds__(kExpandBlock) void k_batch_persistent(const ModelSt
         wait_vm_complete();
         __syncthreads();
         if (tid == 0) {
+            // the level's tile count, read while this tile still holds the
+            // level open: once the count below reaches it, the finaliser
+            // may already be writing the next level's count
+            const uint32_t total = ld_coherent(&L.tiles_total);
             const uint32_t done = atomicAdd(&L.tiles_done, 1u) + 1u;
-            s_fin = done == ld_coherent(&L.tiles_total);
+            s_fin = done == total;
         }
         __syncthreads();
         if (s_fin)
