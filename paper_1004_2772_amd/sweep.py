@@ -3,7 +3,7 @@ vector size: the paper's synthetic table experiment (section "Shared
 Storage Parameters", figure "Effect of fill-rate and size/rw-write on
 average throughput"), on one GPU.
 
-    python -m paper_1004_2772_amd.sweep [--out PATH] [--quick]
+    python -m paper_1004_2772_amd.sweep [--out JSON] [--txt TABLE] [--quick]
 
 For each (W, table size 2^c, reads per write n) a table is filled band by
 band up to 99.9 % of its slots.  A band inserts its share of seeded distinct
@@ -99,6 +99,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default="")
     ap.add_argument("--quick", action="store_true", help="small sizes only")
+    ap.add_argument("--txt", default="", help="also write the G ops/s and lines-per-op tables")
     a = ap.parse_args(argv)
     import torch
     assert torch.cuda.is_available(), "the sweep times kernels on a GPU"
@@ -121,7 +122,28 @@ def main(argv=None):
     if a.out:
         with open(a.out, "w") as f:
             json.dump(res, f, indent=1)
+    if a.txt:
+        with open(a.txt, "w") as f:
+            f.write(tables_text(res, " ".join(["python -m paper_1004_2772_amd.sweep"] + (argv or sys.argv[1:]))))
     return res
+
+
+def tables_text(res: dict, command: str) -> str:
+    """Throughput (G ops/s) and lines probed per operation by fill band."""
+    head = "".join(f"{b:>8}" for b in res["bands"])
+    out = [f"# find-or-put by fill band: table of the tuned shape, one call per band (MI355X, one GPU)",
+           f"# command: {command}",
+           f"# bands end at fill {res['bands']}; reads per band capped at {res['max_reads_per_band']}; "
+           f"every band checked (new/seen flags, count); {res['seconds']} s",
+           "# lines per op from a second, identical fill with the line counter on", ""]
+    for key, title, fmt in (("Gops", "G ops/s", "{:8.2f}"), ("lines_per_op", "lines probed per operation", "{:8.2f}")):
+        out.append(f"{title}:")
+        out.append(f"  W log2cap reads/write{head}")
+        for p in res["points"]:
+            out.append(f"{p['W']:>3} {p['log2_capacity']:>6} {p['reads_per_write']:>11}" +
+                       "".join(fmt.format(b[key]) for b in p["bands"]))
+        out.append("")
+    return "\n".join(out)
 
 
 if __name__ == "__main__":
