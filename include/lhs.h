@@ -182,6 +182,15 @@ lhs_status lhs_get_info(lhs_table *t, lhs_info *out);
 #define LHS_COUNT_LINES 1u
 lhs_status lhs_set_counters(lhs_table *t, uint32_t flags);
 
+/* Number of workers of the explorations on t (reach_explore, with or
+ * without REACH_F_GRAPH / REACH_F_ASYNC): at most max_workgroups workgroups
+ * of 256 lanes expand states, each one a worker in the sense of the paper's
+ * speedup S = T_1 / T_N and efficiency E = S / N over N workers (section
+ * "Preliminaries").  0 (the default) = every workgroup that fits on the GPU
+ * at once.  Results do not depend on it.  Find-or-put calls and the batch
+ * are not affected.  LHS_EINVAL for a null table. */
+lhs_status lhs_set_workers(lhs_table *t, uint32_t max_workgroups);
+
 /* ------------------------------------------------------------------------
  * Tuning table: table shapes chosen by the autotuner
  * (paper_1004_2772_amd/autotune.py), which times every lhs_config on

@@ -34,7 +34,7 @@ TUNE_TABLE, TUNE_BATCH = 0, 1
 #: every symbol include/lhs.h declares
 EXPORTS = ["lhs_strerror", "lhs_create", "lhs_create_ex", "lhs_get_config", "lhs_destroy",
            "lhs_clear", "lhs_find_or_put", "lhs_set_threads_per_state", "lhs_set_counters",
-           "lhs_tune_load", "lhs_tune_clear", "lhs_tune_lookup",
+           "lhs_set_workers", "lhs_tune_load", "lhs_tune_clear", "lhs_tune_lookup",
            "lhs_check", "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info",
            "reach_explore", "reach_result_free", "reach_explore_batch", "reach_trace",
            "reach_deadlock_slots",
@@ -142,6 +142,7 @@ def lib() -> ctypes.CDLL:
         L.lhs_check.argtypes = [p]
         L.lhs_set_threads_per_state.argtypes = [p, u32]
         L.lhs_set_counters.argtypes = [p, u32]
+        L.lhs_set_workers.argtypes = [p, u32]
         L.lhs_count.argtypes = [p, ctypes.POINTER(u64)]
         L.lhs_dump.argtypes = [p, p, p, u64, ctypes.POINTER(u64)]
         L.lhs_dump_slots.argtypes = [p, p]
@@ -168,7 +169,8 @@ def lib() -> ctypes.CDLL:
         L.lhs_probe_copy.argtypes = [p, p, u64, p]
         for name in ("lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_copy",
                      "lhs_create", "lhs_destroy", "lhs_clear", "lhs_find_or_put", "lhs_check",
-                     "lhs_set_threads_per_state", "lhs_set_counters", "lhs_create_ex", "lhs_get_config",
+                     "lhs_set_threads_per_state", "lhs_set_counters", "lhs_set_workers", "lhs_create_ex",
+                     "lhs_get_config",
                      "lhs_tune_load", "lhs_tune_clear", "lhs_tune_lookup",
                      "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info", "reach_explore",
                      "reach_explore_batch", "reach_trace", "reach_deadlock_slots",
@@ -290,6 +292,11 @@ class Table:
     def set_counters(self, flags: int):
         """LHS_COUNT_LINES (1): count lines probed (lhs_info.lines_probed)."""
         _check(lib().lhs_set_counters(self.handle, flags), "lhs_set_counters")
+
+    def set_workers(self, max_workgroups: int):
+        """At most this many workgroups expand states in explorations on this
+        table (0 = all that fit on the GPU at once)."""
+        _check(lib().lhs_set_workers(self.handle, max_workgroups), "lhs_set_workers")
 
     def count(self) -> int:
         c = ctypes.c_uint64()

@@ -184,7 +184,8 @@ lhs_status explore_async(lhs_table *t, const reach_model *m, const uint2 *d_tran
             return LHS_EDEVICE;
         // the resident workgroups; waits are bounded, so the protocol needs
         // no co-residency guarantee
-        hipLaunchKernelGGL((k_explore_async<decltype(G)::value, decltype(L)::value>), dim3(ncu * per_cu),
+        hipLaunchKernelGGL((k_explore_async<decltype(G)::value, decltype(L)::value>),
+                           dim3(exploration_grid(t, (uint64_t)ncu * per_cu)),
                            dim3(kExpandBlock), lds, s, tv, mv, queue, t->level, d_ctl, limit, tc);
         return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
     });

@@ -390,6 +390,13 @@ lhs_status lhs_set_counters(lhs_table *t, uint32_t flags) {
     return LHS_OK;
 }
 
+lhs_status lhs_set_workers(lhs_table *t, uint32_t max_workgroups) {
+    if (!t)
+        return LHS_EINVAL;
+    t->workers = max_workgroups;
+    return LHS_OK;
+}
+
 lhs_status lhs_get_config(lhs_table *t, lhs_config *out) {
     if (!t || !out)
         return LHS_EINVAL;

@@ -219,7 +219,7 @@ lhs_status launch_expand(lhs_table *t, const TableView &tv, const ModelView &mv,
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kExpandBlock, lds) != hipSuccess ||
             per_cu < 1)
             return LHS_EDEVICE;
-        const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, (uint64_t)ncu * per_cu));
+        const uint32_t blocks = exploration_grid(t, std::min<uint64_t>(tiles, (uint64_t)ncu * per_cu));
         hipLaunchKernelGGL((k_expand<decltype(G)::value, decltype(L)::value>), dim3(blocks), dim3(kExpandBlock),
                            lds, s, tv, mv, front, n_front, next, lc, limit, tc);
         return LHS_OK;
@@ -371,9 +371,10 @@ lhs_status explore_graph(lhs_table *t, const reach_model *m, const uint2 *d_tran
     h.ctl.max_levels = max_levels;
     LHS_HIP(hipMemcpyAsync(d_ctx, &h, sizeof(h), hipMemcpyHostToDevice, s));
 
-    // the captured graph depends on the table, its lanes per state and the
-    // LDS layout (W is the table's)
-    const uint32_t tps = tps_expand(t), key = tcap * 32u + tps;
+    // the captured graph depends on the table, its lanes per state, the LDS
+    // layout (W is the table's) and the worker cap
+    const uint32_t tps = tps_expand(t);
+    const uint64_t key = ((uint64_t)t->workers << 32) | (tcap * 32u + tps);
     if (!t->gexec || t->gexec_tcap != key) {
         if (t->gexec) {
             (void)hipGraphExecDestroy(t->gexec);
@@ -393,7 +394,8 @@ lhs_status explore_graph(lhs_table *t, const reach_model *m, const uint2 *d_tran
                 return LHS_EDEVICE;
             for (uint32_t k = 0; k < kGraphLevels; ++k) {
                 hipLaunchKernelGGL((k_expand_graph<decltype(G)::value, decltype(L)::value>),
-                                   dim3((uint32_t)(ncu * per_cu)), dim3(kExpandBlock), lds, t->gstream,
+                                   dim3(exploration_grid(t, (uint64_t)ncu * per_cu)), dim3(kExpandBlock), lds,
+                                   t->gstream,
                                    (const GraphCtx *)d_ctx, tcap);
                 hipLaunchKernelGGL(k_finalize_graph, dim3(1), dim3(1), 0, t->gstream, d_ctx);
                 hipLaunchKernelGGL(k_rollback_graph, dim3((uint32_t)ncu * 4), dim3(256), 0, t->gstream,

@@ -129,3 +129,7 @@ def test_async_flag_conflicts_rejected():
     res = (lhs.ReachResultC * 1)()
     o = lhs.ReachOpts(0, 0, lhs.REACH_F_ASYNC, None, None)
     assert L.reach_explore_batch(arr, 1, ctypes.byref(o), None, res) == 1
+
+
+def test_set_workers_rejects_null():
+    assert lhs.lib().lhs_set_workers(None, 4) == 1

@@ -183,3 +183,29 @@ def test_repeat_same_table(lhs):
         for flags in (lhs.REACH_F_ASYNC, 0, lhs.REACH_F_ASYNC, lhs.REACH_F_ASYNC):
             got = lhs.reach_explore(m, cap=0, table=t, flags=flags)
             assert _set_fields(got) == _set_fields(want)
+
+
+def _wide_enumeration_model(P=22, moving=10):
+    """P * K = 66 > 64 candidate transitions per state (the expansion's LDS
+    ring path): `moving` processes step through two local states, the rest
+    only self-loop, every process also carries a guard that never holds, and
+    process 0 copies its local state into the one shared variable."""
+    NONE = 0xFFFFFFFF
+    L, S, K = 2, 1, 3
+    t = np.zeros((P, L, K, 5), dtype=np.uint32)
+    for p in range(P):
+        for l in range(L):
+            t[p, l, 0] = [(l + 1) % L if p < moving else l, NONE, 0, NONE, 0]
+            t[p, l, 1] = [l, 0, 7, NONE, 0]
+            t[p, l, 2] = [l, NONE, 0, 0, l] if p == 0 else [l, 0, 9, NONE, 0]
+    return gen.Model(P, L, S, 2, K, t, np.zeros(P + S, dtype=np.uint32), 0, f"wide-enum({P},{moving})", 0)
+
+
+@pytest.mark.parametrize("tps", [1, 8])
+def test_wide_enumeration(lhs, tps):
+    m = _wide_enumeration_model()
+    assert m.P * m.K > 64
+    want = _oracle_full(m)
+    print(f"\n[async] P*K = {m.P * m.K}, {want.total} states, tps={tps}", flush=True)
+    assert want.total == 2 ** 10 * 2
+    _compare(lhs, m, cfg=lhs.config(8, "double", tps, tps))
