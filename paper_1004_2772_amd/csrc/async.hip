@@ -22,8 +22,10 @@
 // level boundary.  The expansion itself is the BFS tile (expand_tile):
 // LDS-staged rows, guarded successors, find-or-put, compaction of the new
 // states into an LDS buffer.  The buffer is appended to the queue with one
-// atomic when it nears full, and whenever the workgroup's own chunk has no
-// entry left to expand, so held-back states never starve an idle GPU.
+// atomic when it nears full, when some workgroup owns a chunk that nothing
+// has been appended to (it is waiting), and whenever its own chunk has no
+// entry left to expand: held-back states never starve an idle GPU, and while
+// every workgroup is busy they go out in bulk.
 //
 // Termination: after every tile a workgroup adds (states it discovered,
 // appended or buffered - states it expanded) to ctl->work in one atomic, so
@@ -92,6 +94,15 @@ __global__ __launch_bounds__(kExpandBlock) void k_explore_async(TableView t, Mod
                 }
                 const uint32_t tl = ld_coherent(&lc->n_next);
                 const uint64_t end = min<uint64_t>(tl, base + kChunk);
+                // some workgroup owns a chunk that nothing has been appended
+                // to yet, i.e. is waiting: publish held-back states before
+                // expanding more (only asked while the cursor is within a
+                // quarter of the grid's chunks of this one, as it then can be)
+                if (s_nnew && (uint64_t)tl < base + (uint64_t)(gridDim.x / 4 + 1) * kChunk &&
+                    (uint64_t)tl < (uint64_t)ld_coherent(&ctl->chunk) * kChunk) {
+                    act = kPublish;
+                    break;
+                }
                 if (end > base + used) {
                     take = (uint32_t)(end - base - used);
                     act = kExpand;
