@@ -333,6 +333,22 @@ def main():
         bfs["graph_levels"] = {"median_ms": round(gg, 2), "states_per_s": round(rg.total / (gg / 1e3), 1),
                                "same_result": (rg.total, rg.level_counts, rg.edges) ==
                                               (res.total, res.level_counts, res.edges)}
+        # the paper's speedup S = T_1 / T_N and efficiency E = S / N over N
+        # workers (one workgroup of 256 lanes each), on a 2^22-state prefix
+        # of the same model
+        mw = gen.big_model(cap=1 << 22)
+        with lhs.Table(1 << 24, mw.W) as tw:
+            ws = {}
+            for nw in (1, 1024):
+                tw.set_workers(nw)
+                rw = [lhs.reach_explore(mw, table=tw) for _ in range(3)]
+                ws[nw] = (sorted(r.gpu_ms for r in rw[1:])[0], rw[-1])
+        s_w = ws[1][0] / ws[1024][0]
+        bfs["workers_speedup"] = {"workload": f"BFS of the same model capped at 2^22 states ({ws[1][1].total} states)",
+                                  "ms_1_workgroup": round(ws[1][0], 2), "ms_1024_workgroups": round(ws[1024][0], 2),
+                                  "speedup_S": round(s_w, 1), "efficiency_E": round(s_w / 1024, 3),
+                                  "same_result": ws[1][1].level_counts == ws[1024][1].level_counts}
+        log(f"bfs workers: 1 workgroup {ws[1][0]:.1f} ms, 1024 workgroups {ws[1024][0]:.2f} ms, S = {s_w:.1f}")
         if args.sweep_tps:
             for tps in (1, 4, 8, 16):
                 table.set_threads_per_state(tps)
