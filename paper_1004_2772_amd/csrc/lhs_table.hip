@@ -107,10 +107,15 @@ __global__ __launch_bounds__(kBlock) void k_find_or_put(TableView t, const uint3
     flush_counters(t, cnt);
 }
 
+// Zero n 64-bit words (p 16-byte aligned): 16-byte stores, so one
+// wavefront store instruction writes 1 KiB of whole lines.
 __global__ void k_zero_u64(uint64_t *p, uint64_t n) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
+    uint4 *q = reinterpret_cast<uint4 *>(p);
+    const uint64_t n2 = n / 2, stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride)
+        q[i] = make_uint4(0, 0, 0, 0);
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0)
+        p[n - 1] = 0;
 }
 
 __global__ void k_zero_status(DevStatus *st) {
@@ -248,7 +253,7 @@ lhs_status launch_find_or_put(lhs_table *t, const uint32_t *d_states, uint64_t n
 }
 
 lhs_status launch_zero_u64(uint64_t *p, uint64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(n, kBlock * 8)), dim3(kBlock), 0, s, p, n);
+    hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(n / 2 + 1, kBlock * 4)), dim3(kBlock), 0, s, p, n);
     return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
 }
 
