@@ -81,6 +81,19 @@ def load_traffic(kernel, workload, n_launch_ops):
     return int(t["fetch_bytes"] + t["write_bytes"]), t
 
 
+def load_atomics(kernel, workload, n_launch_ops):
+    """Atomic requests per launch (rocprofv3 TCC counters) of the kernel and
+    of the random-CAS probe, or None if missing or taken on other sources."""
+    path = os.path.join(PROFILES, f"{kernel}_{workload}_atomics.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha") != source_sha(FOP_SOURCES) or t.get("ops_per_launch") != n_launch_ops:
+        return None
+    return t
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,6 +302,18 @@ def main():
         probes["fop_cas_per_s"] = round(cas_per_s, 1) if cas_per_s else None
         probes["fop_cas_frac_of_random_cas"] = (round(cas_per_s / 1e9 / probes["random_cas64_Gops"], 4)
                                                 if cas_per_s else None)
+        # the same from rocprofv3: L2 atomic requests per launch (committed
+        # counter summary) over this run's launch times
+        at = load_atomics("k_find_or_put", "stream2p26", launch_ops)
+        if at is not None and n_launch == 1:
+            probe_s = (1 << 26) / (probes["random_cas64_Gops"] * 1e9)
+            fop_rate = at["l2_atomics_per_launch"] / (launch_ms / 1e3)
+            probe_rate = at["probe_l2_atomics_per_launch"] / probe_s
+            out["atomics"] = {"source": "k_find_or_put_stream2p26_atomics.json (rocprofv3 TCC_ATOMIC_sum)",
+                              "fop_l2_atomics_per_op": round(at["l2_atomics_per_op"], 4),
+                              "fop_l2_atomics_per_s": round(fop_rate, 1),
+                              "probe_l2_atomics_per_s": round(probe_rate, 1),
+                              "frac_of_random_cas": round(fop_rate / probe_rate, 4)}
         out["probes"] = probes
         log(f"probes: {probes}")
 

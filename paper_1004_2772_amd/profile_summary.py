@@ -7,6 +7,11 @@
         FETCH_SIZE / WRITE_SIZE of a kernel per dispatch, scaled by what the
         same counters read for the plain copy probe of B bytes (which reads B
         and writes B bytes), written as JSON for bench.py.
+    python -m paper_1004_2772_amd.profile_summary atomics ATOMIC_DB --kernel NAME --ops N \
+        --probe NAME --probe-ops M --sources F1,F2 --out JSON [--cmd "..."]
+        TCC_ATOMIC_sum (atomic requests at the L2) and TCC_EA0_ATOMIC_sum (atomics
+        sent on to memory) of a kernel's largest dispatch and of the random-CAS
+        probe's, written as JSON for bench.py (which divides by the launch times).
 """
 from __future__ import annotations
 
@@ -84,6 +89,15 @@ def main(argv=None):
     t.add_argument("--out", required=True)
     t.add_argument("--cmd", default="")
     t.add_argument("--summary", default="")
+    at = sub.add_parser("atomics")
+    at.add_argument("db")
+    at.add_argument("--kernel", required=True)
+    at.add_argument("--ops", type=int, required=True)
+    at.add_argument("--probe", required=True)
+    at.add_argument("--probe-ops", type=int, required=True)
+    at.add_argument("--sources", required=True)
+    at.add_argument("--out", required=True)
+    at.add_argument("--cmd", default="")
     a = ap.parse_args(argv)
 
     if a.mode == "stats":
@@ -95,6 +109,22 @@ def main(argv=None):
             print(f"{r['kernel'][:44]:44s} {r['calls']:6d} {r['total_ms']:10.3f} {r['avg_ms']:9.4f} "
                   f"{r['min_ms']:9.4f} {r['max_ms']:9.4f} {r['pct']:6.2f}  {r['big_calls']:18d} "
                   f"{r['big_avg_ms']:9.4f}")
+        return
+
+    if a.mode == "atomics":
+        res = dict(kernel=a.kernel, ops_per_launch=a.ops, probe=a.probe, probe_ops_per_launch=a.probe_ops,
+                   source_sha=sources_sha(a.sources.split(",")), command=a.cmd)
+        for counter, key in (("TCC_ATOMIC_sum", "l2_atomics"), ("TCC_EA0_ATOMIC_sum", "ea_atomics")):
+            per = counter_per_dispatch(a.db, counter)
+            if a.kernel not in per or a.probe not in per:
+                sys.exit(f"{counter}: kernel or probe missing from {a.db}")
+            res[f"{key}_per_launch"] = largest_dispatch(per[a.kernel])
+            res[f"probe_{key}_per_launch"] = largest_dispatch(per[a.probe])
+            res[f"{key}_per_op"] = res[f"{key}_per_launch"] / a.ops
+            res[f"probe_{key}_per_op"] = res[f"probe_{key}_per_launch"] / a.probe_ops
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res, indent=1))
         return
 
     fetch = counter_per_dispatch(a.fetch_db, "FETCH_SIZE")
