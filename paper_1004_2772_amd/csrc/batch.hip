@@ -65,6 +65,8 @@ struct LevelState {
     uint32_t limit;
     uint32_t tiles_total;
     uint32_t tiles_done;
+    uint32_t tile_rows;         // frontier states per tile of this level
+    uint32_t pad;
 };
 
 // Per-model constants (written by the host before the launch, read-only in
@@ -90,9 +92,35 @@ __device__ __forceinline__ bool queue_failed(QueueState *qs) {
     return ld_coherent(&qs->error) != 0u;
 }
 
+// Tile size of a level.  Once at most kFewModels models remain and at least
+// half the workgroups wait on the queue with nothing to take, a level of at
+// most kSmallLevel states is cut into tiles of down to kMinTileRows states,
+// about one per waiting workgroup: the deepest models' narrow levels, run
+// after the rest of the batch has finished, then spread over the idle GPU
+// instead of one full tile's latency chain per workgroup.  Otherwise tiles
+// stay full (less per-tile work while the GPU is busy).
+constexpr uint32_t kSmallLevel = 32768;
+constexpr uint32_t kMinTileRows = 32;
+constexpr uint32_t kFewModels = 8;
+__device__ __forceinline__ uint32_t level_tile_rows(QueueState *qs, uint32_t n_states) {
+    if (n_states > kSmallLevel || ld_coherent(&qs->remaining) > kFewModels)
+        return kExpandBlock;
+    const unsigned long long h = ld_coherent(&qs->head), t = ld_coherent(&qs->tail);
+    const uint32_t idle = h > t ? (uint32_t)min<unsigned long long>(h - t, 1u << 16) : 0u;
+    if (idle < gridDim.x / 2)
+        return kExpandBlock;
+    uint32_t rows = kMinTileRows;
+    while (rows < kExpandBlock && (uint64_t)rows * (idle + 1) < n_states)
+        rows <<= 1;
+    return rows;
+}
+
 // Finalise model i's level; block-wide.  Called by the workgroup that
-// completed its last tile.
-__device__ void finalize_level(const ModelState *ms, ModelProgress *mp, LevelState *lv, uint32_t i,
+// completed its last tile.  Returns (uniformly) true when the model has a
+// next level: its tile 0 is then left to the caller, which expands it at
+// once instead of queueing it (a model's narrow levels do not wait behind
+// the queue); tiles 1.. go to the queue.
+__device__ bool finalize_level(const ModelState *ms, ModelProgress *mp, LevelState *lv, uint32_t i,
                                QueueState *qs, QCell *ring) {
     __shared__ uint32_t s_nt;
     __shared__ unsigned long long s_pos0;
@@ -133,7 +161,8 @@ __device__ void finalize_level(const ModelState *ms, ModelProgress *mp, LevelSta
                 st_coherent(&P.total, total);
                 const uint32_t cur = ld_coherent(&P.cur) ^ 1u;
                 st_coherent(&P.cur, cur);
-                nt = (n_next + kExpandBlock - 1) / kExpandBlock;
+                const uint32_t rows_per = level_tile_rows(qs, n_next);
+                nt = (n_next + rows_per - 1) / rows_per;
                 const uint64_t room = M.cap ? M.cap - total : 0xFFFFFFFFull;
                 st_coherent(&L.front, (unsigned long long)M.fr[cur]);
                 st_coherent(&L.next, (unsigned long long)M.fr[cur ^ 1u]);
@@ -141,6 +170,7 @@ __device__ void finalize_level(const ModelState *ms, ModelProgress *mp, LevelSta
                 st_coherent(&L.limit, (uint32_t)min<uint64_t>(room, 0xFFFFFFFFull));
                 st_coherent(&L.tiles_total, nt);
                 st_coherent(&L.tiles_done, 0u);
+                st_coherent(&L.tile_rows, rows_per);
             }
         }
         if (done)
@@ -152,16 +182,16 @@ __device__ void finalize_level(const ModelState *ms, ModelProgress *mp, LevelSta
         wait_vm_complete();
         if (done)
             atomicSub(&qs->remaining, 1u);
-        else
-            s_pos0 = atomicAdd(&qs->tail, (unsigned long long)nt);
+        else if (nt > 1)
+            s_pos0 = atomicAdd(&qs->tail, (unsigned long long)(nt - 1));
         s_nt = nt;
     }
     __syncthreads();
     const uint32_t nt = s_nt;
-    // enqueue the next level's tiles: wait for each cell to be free, fill it,
-    // then publish it
-    for (uint32_t k = tid; k < nt; k += kExpandBlock) {
-        const unsigned long long pos = s_pos0 + k;
+    // enqueue tiles 1.. of the next level: wait for each cell to be free,
+    // fill it, then publish it
+    for (uint32_t k = 1 + tid; k < nt; k += kExpandBlock) {
+        const unsigned long long pos = s_pos0 + (k - 1);
         QCell *c = ring + (pos & qs->mask);
         uint32_t spins = 0;
         while (ld_coherent(&c->seq) != pos) {
@@ -176,6 +206,7 @@ __device__ void finalize_level(const ModelState *ms, ModelProgress *mp, LevelSta
         wait_vm_complete();
         st_coherent(&c->seq, pos + 1ull);
     }
+    return nt != 0;
 }
 
 template <int G, uint32_t LS>
@@ -187,8 +218,12 @@ __global__ __launch_bounds__(kExpandBlock) void k_batch_persistent(const ModelSt
     expand_begin();
     __shared__ uint32_t s_model, s_tile, s_exit, s_fin;
     const uint32_t tid = threadIdx.x;
+    bool kept = false;   // tile 0 of s_model's new level is this workgroup's
     while (true) {
-        if (tid == 0) {
+        if (tid == 0 && kept) {
+            s_tile = 0;
+            s_exit = queue_failed(qs) ? 1u : 0u;
+        } else if (tid == 0) {
             uint32_t ex = 0;
             const unsigned long long pos = atomicAdd(&qs->head, 1ull);
             QCell *c = ring + (pos & qs->mask);
@@ -222,8 +257,9 @@ __global__ __launch_bounds__(kExpandBlock) void k_batch_persistent(const ModelSt
         uint32_t *next = reinterpret_cast<uint32_t *>(ld_coherent(&L.next));
         const uint32_t n_front = ld_coherent(&L.n_front);
         const uint32_t limit = ld_coherent(&L.limit);
-        const uint64_t base = (uint64_t)j * kExpandBlock;
-        const uint32_t rows = (uint32_t)min<uint64_t>(kExpandBlock, n_front - base);
+        const uint32_t rows_per = ld_coherent(&L.tile_rows);
+        const uint64_t base = (uint64_t)j * rows_per;
+        const uint32_t rows = (uint32_t)min<uint64_t>(rows_per, n_front - base);
         expand_tile<G, LS, true>(smem, M.t, M.m, front, base, rows, next, M.lc, limit, tcap);
         // this workgroup's stores of the tile are complete before it counts
         // the tile as done
@@ -238,8 +274,7 @@ __global__ __launch_bounds__(kExpandBlock) void k_batch_persistent(const ModelSt
             s_fin = done == total;
         }
         __syncthreads();
-        if (s_fin)
-            finalize_level(ms, mp, lv, i, qs, ring);
+        kept = s_fin && finalize_level(ms, mp, lv, i, qs, ring);
     }
 }
 
@@ -387,7 +422,8 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
         b.limit = b.m->state_cap ? (uint32_t)std::min<uint64_t>(b.m->state_cap - 1, 0xFFFFFFFFull)
                                  : 0xFFFFFFFFu;
         b.levels.push_back(1);
-        pending += b.t->capacity / kExpandBlock + 1;
+        // tiles of one level: full tiles, or small ones for small levels
+        pending += std::max<uint64_t>(b.t->capacity / kExpandBlock, kSmallLevel / kMinTileRows) + 1;
     }
     uint64_t cells = 1024;
     while (cells < 2 * pending)
@@ -492,6 +528,8 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
             L.limit = bm[i].limit;
             L.tiles_total = 1;
             L.tiles_done = 0;
+            L.tile_rows = kExpandBlock;
+            L.pad = 0;
         }
     }
 
