@@ -26,3 +26,28 @@ def test_scaling_quick():
     assert pts[1]["bfs_speedup"] > 8.0
     assert pts[1]["no_levels_speedup"] > 4.0
 
+
+
+@pytest.fixture(scope="module")
+def mid_model():
+    import gen
+    import oracle
+    m = gen.guarded_model(4242, 6, 6, 3, 4, 3)
+    return m, oracle.reach(m, cap=0)
+
+
+@pytest.mark.parametrize("workers", [1, 3, 64, 0])
+def test_worker_caps_do_not_change_results(mid_model, workers):
+    # every exploration mode, with a captured graph keyed by the worker cap
+    import paper_1004_2772_amd as lhs
+    m, want = mid_model
+    print(f"\n[scaling] workers={workers}: {want.total} states", flush=True)
+    with lhs.Table(1 << 22, m.W) as t:
+        t.set_workers(workers)
+        for flags in (0, lhs.REACH_F_GRAPH, lhs.REACH_F_ASYNC):
+            r = lhs.reach_explore(m, cap=0, table=t, flags=flags)
+            assert (r.total, r.edges, r.deadlocks) == (want.total, want.edges, want.deadlocks), flags
+            if flags != lhs.REACH_F_ASYNC:
+                assert r.level_counts == want.level_counts
+        capped = lhs.reach_explore(m, cap=want.total // 2, table=t, flags=lhs.REACH_F_GRAPH)
+        assert capped.capped and capped.total <= want.total // 2
