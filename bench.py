@@ -15,8 +15,10 @@ Extra legs in the same JSON line:
                  counter summaries when they match the current kernel source.
   probes       : measured ceilings: random line reads of 64/128/256 bytes
                  (cooperative lanes, and 128 B by one lane) and random 64-bit
-                 CAS throughput; the find-or-put's algorithmic GB/s over the
-                 ceiling at its table's line width.
+                 CAS throughput, random slot stores, row stores and row loads;
+                 the find-or-put's algorithmic GB/s over the line ceiling at
+                 its table's line width, and its launch time over the sum of
+                 its accesses priced at the probes' rates.
   bfs          : level-synchronous BFS of the 12-process x 16-local synthetic
                  model capped at 2^27 states (states/s, edges/s).
   batch        : the 64-model mix (2-16 processes, widths 4-32, 10^3-10^6
@@ -279,6 +281,15 @@ def main():
             b.record(stream)
             torch.cuda.synchronize()
             probes[f"random_{lb}B_lines_{lanes}lane_GBs"] = round(reads * lb / (a.elapsed_time(b) / 1e3) / 1e9, 1)
+        for form in ("slot_store", "row_store", "row_load"):
+            ops = 1 << 27
+            lhs.probe_random_access(buf, form, ops, 5, sink)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            lhs.probe_random_access(buf, form, ops, 6, sink)
+            b.record(stream)
+            torch.cuda.synchronize()
+            probes[f"random_{form}_Gops"] = round(ops / (a.elapsed_time(b) / 1e3) / 1e9, 3)
         del buf
         slots = torch.zeros(1 << 28, dtype=torch.int64, device=dev)
         ops = 1 << 26
@@ -298,6 +309,20 @@ def main():
         # slot CAS issued by the find-or-put launch (one per insert plus the
         # retries) against the random 64-bit CAS rate of the same GPU
         cas = n_distinct + info["cas_failures"]
+        # the whole access mix of the launch priced at the probes' rates, as
+        # if served one after another: per operation one slot line read (at
+        # 1/8 fill an operation examines 1.00 lines), per lookup one row
+        # load, per insert one row store and one DONE store, and every CAS
+        line_rate = probes[f"random_{lb}B_lines_{lb // 16}lane_GBs"] * 1e9 / lb
+        mix = {"line_reads": n / line_rate,
+               "row_loads": (n - n_distinct) / (probes["random_row_load_Gops"] * 1e9),
+               "cas": cas / (probes["random_cas64_Gops"] * 1e9),
+               "row_stores": n_distinct / (probes["random_row_store_Gops"] * 1e9),
+               "slot_stores": n_distinct / (probes["random_slot_store_Gops"] * 1e9)}
+        mix_s = sum(mix.values())
+        probes["fop_access_mix_ms"] = {k: round(v * 1e3, 3) for k, v in mix.items()}
+        probes["fop_access_mix_sum_ms"] = round(mix_s * 1e3, 3)
+        probes["fop_launch_over_access_mix_sum"] = round(launch_ms / 1e3 / mix_s, 4) if n_launch == 1 else None
         cas_per_s = cas / (launch_ms / 1e3) if n_launch == 1 else None
         probes["fop_cas_per_s"] = round(cas_per_s, 1) if cas_per_s else None
         probes["fop_cas_frac_of_random_cas"] = (round(cas_per_s / 1e9 / probes["random_cas64_Gops"], 4)

@@ -463,6 +463,24 @@ lhs_status lhs_probe_random_lines(const void *d_buf, uint64_t buf_bytes, uint32_
 lhs_status lhs_probe_random_cas(uint64_t *d_slots, uint64_t n_slots, uint64_t n_ops,
                                 uint64_t seed, uint64_t *d_sink, void *hip_stream);
 
+/* n_ops accesses in the remaining forms of a find-or-put, at uniformly random
+ * positions of d_buf (buf_bytes / 64 a power of two, d_buf 64-byte aligned):
+ *   LHS_PROBE_SLOT_STORE  8-byte agent-scope store to a random slot, one lane
+ *                         per store (the DONE publish of an insert);
+ *   LHS_PROBE_ROW_STORE   64-byte row written by eight lanes with 8-byte
+ *                         agent-scope stores (the row write of an insert);
+ *   LHS_PROBE_ROW_LOAD    the same row read by eight lanes with 8-byte
+ *                         agent-scope loads (the row compare of a lookup).
+ * d_buf's contents are overwritten by the store forms.  LHS_EINVAL for an
+ * unknown form, a null pointer, a size or an alignment outside the above. */
+typedef enum lhs_probe_form {
+    LHS_PROBE_SLOT_STORE = 0,
+    LHS_PROBE_ROW_STORE = 1,
+    LHS_PROBE_ROW_LOAD = 2
+} lhs_probe_form;
+lhs_status lhs_probe_random_access(void *d_buf, uint64_t buf_bytes, uint32_t form, uint64_t n_ops,
+                                   uint64_t seed, uint64_t *d_sink, void *hip_stream);
+
 /* Streaming copy of `bytes` (multiple of 16, 16-byte aligned pointers): the
  * reference kernel for calibrating hardware traffic counters. */
 lhs_status lhs_probe_copy(void *d_dst, const void *d_src, uint64_t bytes, void *hip_stream);

@@ -40,7 +40,7 @@ EXPORTS = ["lhs_strerror", "lhs_create", "lhs_create_ex", "lhs_get_config", "lhs
            "reach_deadlock_slots",
            "reach_server_clock", "reach_server_create", "reach_server_submit", "reach_server_poll",
            "reach_server_wait", "reach_server_get_stats", "reach_server_destroy",
-           "lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_copy"]
+           "lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_random_access", "lhs_probe_copy"]
 
 
 class LhsError(RuntimeError):
@@ -166,8 +166,9 @@ def lib() -> ctypes.CDLL:
         L.reach_server_destroy.argtypes = [p]
         L.lhs_probe_random_lines.argtypes = [p, u64, u32, u32, u64, u64, p, p]
         L.lhs_probe_random_cas.argtypes = [p, u64, u64, u64, p, p]
+        L.lhs_probe_random_access.argtypes = [p, u64, u32, u64, u64, p, p]
         L.lhs_probe_copy.argtypes = [p, p, u64, p]
-        for name in ("lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_copy",
+        for name in ("lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_random_access", "lhs_probe_copy",
                      "lhs_create", "lhs_destroy", "lhs_clear", "lhs_find_or_put", "lhs_check",
                      "lhs_set_threads_per_state", "lhs_set_counters", "lhs_set_workers", "lhs_create_ex",
                      "lhs_get_config",
@@ -507,6 +508,16 @@ def probe_random_lines(buf, line_bytes: int, lanes_per_line: int, n_reads: int, 
 def probe_random_cas(slots, n_ops: int, seed: int, sink, stream=None):
     _check(lib().lhs_probe_random_cas(_ptr(slots), slots.numel(), n_ops, seed, _ptr(sink),
                                       _stream_handle(stream)), "lhs_probe_random_cas")
+
+
+PROBE_FORMS = {"slot_store": 0, "row_store": 1, "row_load": 2}
+
+
+def probe_random_access(buf, form, n_ops: int, seed: int, sink, stream=None):
+    """form: "slot_store", "row_store", "row_load" (or its number)."""
+    f = PROBE_FORMS[form] if isinstance(form, str) else form
+    _check(lib().lhs_probe_random_access(_ptr(buf), buf.numel() * buf.element_size(), f, n_ops, seed,
+                                         _ptr(sink), _stream_handle(stream)), "lhs_probe_random_access")
 
 
 def probe_copy(dst, src, stream=None):

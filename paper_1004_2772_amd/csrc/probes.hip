@@ -5,6 +5,9 @@
 //                  one after another) or by line/16 cooperating lanes (16 B
 //                  each, one coalesced access: the find-or-put pattern).
 //   random CAS   : 64-bit compare-and-swap at uniformly random slots.
+//   random slot store, row store, row load: the other accesses of an insert
+//                  or lookup (DONE publish, row write, row compare) in the
+//                  form find-or-put issues them.
 //   copy         : a plain streaming copy, the reference for hardware
 //                  traffic counters.
 // Indices come from the SplitMix64 output function applied to a counter
@@ -72,6 +75,35 @@ __global__ __launch_bounds__(256) void k_probe_cas(uint64_t *slots, uint64_t n_s
         sink[0] = won;
 }
 
+// FORM 0: 8-byte agent-scope store to a random slot, one lane each.
+// FORM 1 / 2: 64-byte row at a random row position, stored / loaded by eight
+// lanes with 8-byte agent-scope accesses.  n_rows = 64-byte rows in buf.
+template <uint32_t FORM>
+__global__ __launch_bounds__(256) void k_probe_access(uint64_t *buf, uint64_t n_rows, uint64_t n_ops,
+                                                      uint64_t seed, uint64_t *sink) {
+    uint64_t acc = 0;
+    if constexpr (FORM == 0) {
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_ops;
+             i += (uint64_t)gridDim.x * blockDim.x) {
+            const uint64_t r = splitmix(seed ^ i);
+            __hip_atomic_store(buf + (r & (n_rows * 8 - 1)), r | 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else {
+        const uint32_t sub = threadIdx.x & 7u;
+        for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3; i < n_ops;
+             i += ((uint64_t)gridDim.x * blockDim.x) >> 3) {
+            const uint64_t r = splitmix(seed ^ i);
+            uint64_t *p = buf + (r & (n_rows - 1)) * 8 + sub;
+            if constexpr (FORM == 1)
+                __hip_atomic_store(p, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                acc ^= __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    if (acc == 0x9E3779B97F4A7C15ull)
+        sink[0] = acc;
+}
+
 __global__ __launch_bounds__(256) void k_probe_copy(uint4 *dst, const uint4 *src, uint64_t n) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
@@ -117,6 +149,27 @@ lhs_status lhs_probe_random_cas(uint64_t *d_slots, uint64_t n_slots, uint64_t n_
         return LHS_EINVAL;
     hipLaunchKernelGGL(k_probe_cas, dim3(probe_grid(n_ops)), dim3(256), 0, (hipStream_t)hip_stream,
                        d_slots, n_slots, n_ops, seed, d_sink);
+    return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
+}
+
+lhs_status lhs_probe_random_access(void *d_buf, uint64_t buf_bytes, uint32_t form, uint64_t n_ops,
+                                   uint64_t seed, uint64_t *d_sink, void *hip_stream) {
+    const uint64_t n_rows = buf_bytes / 64;
+    if (!d_buf || !d_sink || form > LHS_PROBE_ROW_LOAD || !lhs::is_pow2(n_rows) || ((uintptr_t)d_buf & 63))
+        return LHS_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    uint64_t *b = (uint64_t *)d_buf;
+    switch (form) {
+    case LHS_PROBE_SLOT_STORE:
+        hipLaunchKernelGGL(k_probe_access<0>, dim3(probe_grid(n_ops)), dim3(256), 0, s, b, n_rows, n_ops, seed, d_sink);
+        break;
+    case LHS_PROBE_ROW_STORE:
+        hipLaunchKernelGGL(k_probe_access<1>, dim3(probe_grid(n_ops * 8)), dim3(256), 0, s, b, n_rows, n_ops, seed, d_sink);
+        break;
+    default:
+        hipLaunchKernelGGL(k_probe_access<2>, dim3(probe_grid(n_ops * 8)), dim3(256), 0, s, b, n_rows, n_ops, seed, d_sink);
+        break;
+    }
     return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
 }
 

@@ -133,3 +133,16 @@ def test_async_flag_conflicts_rejected():
 
 def test_set_workers_rejects_null():
     assert lhs.lib().lhs_set_workers(None, 4) == 1
+
+
+def test_probes_reject_bad_arguments():
+    L = lhs.lib()
+    fake, sink = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21)   # never dereferenced: rejected first
+    assert L.lhs_probe_random_access(None, 1 << 20, 0, 1, 0, sink, None) == 1
+    assert L.lhs_probe_random_access(fake, 1 << 20, 0, 1, 0, None, None) == 1
+    assert L.lhs_probe_random_access(fake, 1 << 20, 3, 1, 0, sink, None) == 1          # unknown form
+    assert L.lhs_probe_random_access(fake, 3 << 20, 1, 1, 0, sink, None) == 1          # rows not 2^n
+    assert L.lhs_probe_random_access(ctypes.c_void_p((1 << 20) + 32), 1 << 20, 2, 1, 0, sink, None) == 1
+    assert L.lhs_probe_random_lines(fake, 1 << 20, 96, 1, 1, 0, sink, None) == 1       # line width
+    assert L.lhs_probe_random_cas(None, 1 << 10, 1, 0, sink, None) == 1
+    assert L.lhs_probe_copy(fake, fake, 24, None) == 1                                 # not 16-byte sized
