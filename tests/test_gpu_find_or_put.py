@@ -160,3 +160,58 @@ def test_lines_probed_counter(lhs, tps):
         assert 1.3 * len(rows) < t.info()["lines_probed"] < 2.0 * len(rows)
         with pytest.raises(lhs.LhsError):
             t.set_counters(2)
+
+
+@pytest.mark.parametrize("tps", [0, 1])
+@pytest.mark.parametrize("overlap", ["same", "windows"])
+def test_concurrent_streams_one_table(lhs, tps, overlap):
+    """Several calls on one table at once, each on its own stream (the table
+    is lockless): every vector ends up stored once, exactly one operation
+    over all calls reports it new, and every operation on it returns the
+    same index."""
+    import torch
+    W, k_streams, n = 8, 4, 1 << 20
+    rows, _ = gen.dup_stream(0xC0FFEE, n, W, 1)             # n distinct rows
+    ids = []
+    for k in range(k_streams):
+        if overlap == "same":
+            sub = np.arange(n, dtype=np.int64)               # all calls insert the same set
+        else:
+            sub = np.arange(k * n // 8, k * n // 8 + n // 2, dtype=np.int64)   # sliding windows
+        ids.append(sub[gen.permutation(0xABC + k, len(sub)).astype(np.int64)])
+    union = np.unique(np.concatenate(ids))
+    print(f"\n[concurrent] {k_streams} streams, {overlap}, tps={tps}, {len(union)} distinct", flush=True)
+    table = lhs.Table(1 << 22, W)
+    table.set_threads_per_state(tps)
+    states = [dev_u32(rows[i]) for i in ids]
+    seen = [torch.empty(len(i), dtype=torch.uint8, device="cuda") for i in ids]
+    idx = [torch.empty(len(i), dtype=torch.int32, device="cuda") for i in ids]
+    streams = [torch.cuda.Stream() for _ in ids]
+    cur = torch.cuda.current_stream()
+    for s in streams:
+        s.wait_stream(cur)                                   # inputs are ready
+    for k, s in enumerate(streams):
+        table.find_or_put(states[k], seen[k], idx[k], stream=s)
+    torch.cuda.synchronize()
+    table.check()
+    all_ids = np.concatenate(ids)
+    all_seen = np.concatenate([x.cpu().numpy() for x in seen])
+    all_idx = np.concatenate([x.cpu().numpy().view(np.uint32) for x in idx])
+    assert set(np.unique(all_seen).tolist()) <= {0, 1}
+    info = table.info()
+    # how the inserts split over the calls shows whether they overlapped
+    # (run one after another, the first call would insert everything it holds)
+    print(f"[concurrent] new per call {[int((x == 0).sum().item()) for x in seen]}, "
+          f"waits {info['wait_hits']}, cas failures {info['cas_failures']}", flush=True)
+    new_per_id = np.bincount(all_ids[all_seen == 0], minlength=n)
+    assert np.all(new_per_id[union] == 1) and int(new_per_id.sum()) == len(union)
+    order = np.argsort(all_ids, kind="stable")
+    sid, sidx = all_ids[order], all_idx[order]
+    first = np.r_[True, sid[1:] != sid[:-1]]
+    ref = np.repeat(sidx[first], np.diff(np.r_[np.flatnonzero(first), len(sid)]))
+    assert np.array_equal(sidx, ref), "one vector, two indices"
+    assert table.count() == len(union)
+    check_table_invariants(table)
+    stored, sidx2 = table.dump()
+    assert np.array_equal(np.sort(sidx2), np.sort(sidx[first]))
+    table.close()
