@@ -379,7 +379,7 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
  * Serving: reachability queries with continuous batching.
  *
  * A server owns a worker thread and a HIP stream on the device that was
- * current at reach_server_create.  It works in rounds of four BFS level
+ * current at reach_server_create.  It works in rounds of eight BFS level
  * steps run by the device alone; every step expands the current level of
  * every active query in one launch.  Between rounds it retires finished
  * queries and admits queued ones (first come, first served) while their
@@ -434,7 +434,9 @@ lhs_status reach_server_submit(reach_server *s, const reach_model *m, uint64_t *
  * an unknown or already collected ticket. */
 lhs_status reach_server_poll(reach_server *s, uint64_t ticket, reach_result *r, reach_query_times *t);
 
-/* Blocking version of reach_server_poll. */
+/* Blocking version of reach_server_poll.  Any thread may submit, poll and
+ * wait; when several threads wait on one ticket, one of them collects the
+ * result and the others return LHS_ENOTFOUND. */
 lhs_status reach_server_wait(reach_server *s, uint64_t ticket, reach_result *r, reach_query_times *t);
 
 lhs_status reach_server_get_stats(reach_server *s, reach_server_stats *out);

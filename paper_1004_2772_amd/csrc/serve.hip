@@ -613,6 +613,8 @@ lhs_status collect(reach_server *s, Query *q, reach_result *r, reach_query_times
     }
     s->tickets.erase(q->ticket);
     delete q;
+    // other threads waiting on this ticket see it gone
+    s->cv_done.notify_all();
     return rc;
 }
 
@@ -720,12 +722,16 @@ lhs_status reach_server_wait(reach_server *s, uint64_t ticket, reach_result *r, 
     if (!s)
         return LHS_EINVAL;
     std::unique_lock<std::mutex> lk(s->mu);
+    // the ticket is looked up again on every wake-up: another thread waiting
+    // on the same ticket may have collected (and freed) the query meanwhile
     auto it = s->tickets.find(ticket);
+    s->cv_done.wait(lk, [&] {
+        it = s->tickets.find(ticket);
+        return it == s->tickets.end() || it->second->done;
+    });
     if (it == s->tickets.end())
         return LHS_ENOTFOUND;
-    Query *q = it->second;
-    s->cv_done.wait(lk, [&] { return q->done; });
-    return collect(s, q, r, t);
+    return collect(s, it->second, r, t);
 }
 
 lhs_status reach_server_get_stats(reach_server *s, reach_server_stats *out) {

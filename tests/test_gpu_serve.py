@@ -95,7 +95,7 @@ def test_serve_errors(lhs):
         assert e.value.name == "LHS_EINVAL"
         # a query that overflows its table fails alone; the next one is fine
         bad = srv.submit(gen.cyclic_model(3, 20))         # 8000 states in 4096 slots
-        good = srv.submit(gen.tiny_cyclic() if False else gen.cyclic_model(2, 8))
+        good = srv.submit(gen.cyclic_model(2, 8))
         with pytest.raises(lhs.LhsError) as e:
             srv.wait(bad)
         assert e.value.name == "LHS_EFULL"
@@ -109,3 +109,57 @@ def test_serve_errors(lhs):
         with pytest.raises(lhs.LhsError) as e:
             srv.submit(gen.tiny_cyclic())                 # a 2^16-slot table never fits 1 MiB
         assert e.value.name == "LHS_EBUDGET"
+
+
+def test_serve_client_threads(lhs):
+    """Queries submitted and awaited from several host threads at once; two
+    threads waiting on one ticket: one gets the result, the other
+    LHS_ENOTFOUND (the ticket is collected once)."""
+    import threading
+    models = gen.batch_models()
+    golden = _golden_mix()
+    rng = np.random.default_rng(12)
+    picks = [rng.integers(0, len(models), size=6) for _ in range(4)]
+    print("\n[serve] 4 client threads x 6 queries", flush=True)
+    errors = []
+
+    def fields(r):
+        return (r.total, r.n_levels, r.level_counts, r.edges, r.deadlocks, r.capped)
+
+    def gfields(g):
+        return (g["total"], g["n_levels"], g["level_counts"], g["edges"], g["deadlocks"], g["capped"])
+
+    with lhs.Server(capacity=1 << 21) as srv:
+        def client(ks):
+            try:
+                ts = [(int(k), srv.submit(models[int(k)])) for k in ks]
+                for k, t in ts:
+                    if fields(srv.wait(t)[0]) != gfields(golden[k]):
+                        errors.append(k)
+            except Exception as e:          # reported below, on the main thread
+                errors.append(repr(e))
+
+        th = [threading.Thread(target=client, args=(ks,)) for ks in picks]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join(timeout=120)
+        assert not any(t.is_alive() for t in th)
+        assert not errors, errors
+        ticket = srv.submit(models[3])
+        out = []
+
+        def waiter():
+            try:
+                out.append(fields(srv.wait(ticket)[0]) == gfields(golden[3]))
+            except lhs.LhsError as e:
+                out.append(e.name)
+
+        ws = [threading.Thread(target=waiter) for _ in range(2)]
+        for t in ws:
+            t.start()
+        for t in ws:
+            t.join(timeout=60)
+        assert not any(t.is_alive() for t in ws)
+        assert sorted(map(str, out)) == ["LHS_ENOTFOUND", "True"]
+        assert srv.stats()["completed"] == 4 * 6 + 1
