@@ -8,11 +8,12 @@
 //     is needed), inserts their initial states, and
 //   * retires the queries whose exploration ended, returning their tables to
 //     the pool.
-// A step expands the current level of every active query in one launch
-// (tiles mapped to queries by a prefix), then one workgroup does every
-// query's level bookkeeping on the device (level count, cap test, frontier
-// swap, the next step's tile prefix) and a third kernel undoes a capped
-// level, so a round runs without the host.  A query that arrives while
+// A step is one launch: its workgroups expand the current level of every
+// active query (tiles mapped to queries by a prefix), and the workgroup that
+// finishes last does every query's level bookkeeping (level count, cap test,
+// frontier swap, the next step's tile prefix), so a round runs without the
+// host and a step costs one kernel boundary.  A capped level is not undone:
+// the query ends there and its table is emptied when it is next handed out.  A query that arrives while
 // others are on the GPU joins at the next round and its work overlaps
 // theirs; its result is exactly the one reach_explore computes for it alone
 // (same kernels, its own table).
@@ -47,16 +48,100 @@ struct StepCtl {
     uint32_t *fr[2];
     unsigned long long cap, total, edges, deadlocks, wait_hits;
     unsigned long long lv[kRoundSteps];   // level counts found in this round
-    uint32_t lv_n, cur, done, capped, error, rollback_n;
+    uint32_t lv_n, cur, done, capped, error, pad;
 };
 
-// Expand the current level of every active query; the tile prefix and its
-// total come from device memory (written by k_step_finalize).
+// Every query's level bookkeeping after a step, then the next step's tile
+// prefix; run by the one workgroup that finished the step last (all other
+// workgroups' counter updates are complete by then).  `scan` is LDS for
+// kDefaultMaxActive words.
+static_assert(expand_lds_words(1, 0, 1) >= kDefaultMaxActive, "the scan reuses the expansion's LDS");
+
+__device__ void step_finalize(BatchSlot *slots, StepCtl *ctl, LevelCounters *lc, DevStatus *st,
+                              uint32_t *begin, uint32_t n, uint32_t *scan) {
+    constexpr uint32_t kPer = kDefaultMaxActive / kExpandBlock;   // queries per thread in the scan
+    __shared__ uint32_t s_wtot[kExpandBlock / 64];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t a = tid; a < kDefaultMaxActive; a += kExpandBlock) {
+        uint32_t tiles = 0;
+        if (a < n) {
+            StepCtl &C = ctl[a];
+            BatchSlot &S = slots[a];
+            if (!C.done) {
+                // updated by other workgroups' atomics: read at the coherence point
+                const uint32_t n_next = ld_coherent(&lc[a].n_next);
+                const uint32_t err = ld_coherent(&st[a].error);
+                C.wait_hits += ld_coherent(&st[a].wait_hits);
+                if (err) {
+                    C.error = err;
+                    C.done = 1;
+                } else if (C.cap && n_next > S.limit) {
+                    C.capped = 1;
+                    C.done = 1;
+                } else {
+                    C.edges += ld_coherent(&lc[a].edges);
+                    C.deadlocks += ld_coherent(&lc[a].deadlocks);
+                    if (n_next == 0) {
+                        C.done = 1;
+                    } else {
+                        C.lv[C.lv_n++] = n_next;
+                        C.total += n_next;
+                        C.cur ^= 1u;
+                        S.front = C.fr[C.cur];
+                        S.next = C.fr[C.cur ^ 1u];
+                        S.n_front = n_next;
+                        S.limit = C.cap ? (uint32_t)min<unsigned long long>(C.cap - C.total, 0xFFFFFFFFull)
+                                        : 0xFFFFFFFFu;
+                    }
+                }
+            }
+            if (C.done)
+                S.n_front = 0;
+            lc[a] = LevelCounters{0, 0, 0, 0};
+            st[a].error = 0;
+            st[a].wait_hits = 0;
+            st[a].cas_failures = 0;
+            st[a].lines = 0;
+            tiles = (S.n_front + kExpandBlock - 1) / kExpandBlock;
+        }
+        scan[a] = tiles;
+    }
+    __syncthreads();
+    // exclusive prefix of the tile counts: thread t owns kPer consecutive queries
+    uint32_t local = 0;
+    for (uint32_t k = 0; k < kPer; ++k)
+        local += scan[tid * kPer + k];
+    const uint32_t incl = wave_scan_incl(local);
+    if (__lane_id() == 63)
+        s_wtot[tid / 64] = incl;
+    __syncthreads();
+    uint32_t off = incl - local, total = 0;
+    for (uint32_t w = 0; w < kExpandBlock / 64; ++w) {
+        off += w < tid / 64 ? s_wtot[w] : 0u;
+        total += s_wtot[w];
+    }
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t a = tid * kPer + k, v = scan[a];
+        if (a < n) {
+            begin[a] = off;
+            slots[a].tile_begin = off;
+        }
+        off += v;
+    }
+    if (tid == 0)
+        begin[n] = total;
+}
+
+// One step: expand the current level of every active query (the tile
+// prefix and its total come from device memory), then the last workgroup to
+// finish does the level bookkeeping for the next step.  `arrived` counts the
+// workgroups done with the step (zero at launch; reset by the last one).
 template <int G, uint32_t LS>
-__global__ __launch_bounds__(kExpandBlock) void k_expand_step(const BatchSlot *__restrict__ slots,
-                                                              const uint32_t *__restrict__ begin, uint32_t n,
-                                                              uint32_t tcap) {
+__global__ __launch_bounds__(kExpandBlock) void k_step(BatchSlot *slots, uint32_t *begin, uint32_t n,
+                                                       uint32_t tcap, StepCtl *ctl, LevelCounters *lc,
+                                                       DevStatus *st, uint32_t *arrived) {
     extern __shared__ uint32_t smem[];
+    __shared__ uint32_t s_last;
     expand_begin();
     const uint32_t tiles = begin[n];
     for (uint32_t g = blockIdx.x; g < tiles; g += gridDim.x) {
@@ -65,89 +150,26 @@ __global__ __launch_bounds__(kExpandBlock) void k_expand_step(const BatchSlot *_
         const uint32_t rows = (uint32_t)min<uint64_t>(kExpandBlock, s.n_front - base);
         expand_tile<G, LS>(smem, s.t, s.m, s.front, base, rows, s.next, s.lc, s.limit, tcap);
     }
-}
-
-// Every query's level bookkeeping after a step (thread a = query a, one
-// workgroup of kDefaultMaxActive threads), then the next step's tile prefix.
-__global__ __launch_bounds__(kDefaultMaxActive) void k_step_finalize(BatchSlot *slots, StepCtl *ctl,
-                                                                     LevelCounters *lc, DevStatus *st,
-                                                                     uint32_t *begin, uint32_t n) {
-    __shared__ uint32_t scan[kDefaultMaxActive];
-    const uint32_t a = threadIdx.x;
-    uint32_t tiles = 0;
-    if (a < n) {
-        StepCtl &C = ctl[a];
-        BatchSlot &S = slots[a];
-        if (!C.done) {
-            const LevelCounters L = lc[a];
-            C.wait_hits += st[a].wait_hits;
-            if (st[a].error) {
-                C.error = st[a].error;
-                C.done = 1;
-            } else if (C.cap && L.n_next > S.limit) {
-                C.rollback_n = L.n_next;      // k_step_rollback discards the level
-                C.capped = 1;
-                C.done = 1;
-            } else {
-                C.edges += L.edges;
-                C.deadlocks += L.deadlocks;
-                if (L.n_next == 0) {
-                    C.done = 1;
-                } else {
-                    C.lv[C.lv_n++] = L.n_next;
-                    C.total += L.n_next;
-                    C.cur ^= 1u;
-                    S.front = C.fr[C.cur];
-                    S.next = C.fr[C.cur ^ 1u];
-                    S.n_front = L.n_next;
-                    S.limit = C.cap ? (uint32_t)min<unsigned long long>(C.cap - C.total, 0xFFFFFFFFull)
-                                    : 0xFFFFFFFFu;
-                }
-            }
-        } else {
-            C.rollback_n = 0;
-        }
-        if (C.done)
-            S.n_front = 0;
-        lc[a] = LevelCounters{0, 0, 0, 0};
-        st[a].error = 0;
-        st[a].wait_hits = 0;
-        st[a].cas_failures = 0;
-        st[a].lines = 0;
-        tiles = (S.n_front + kExpandBlock - 1) / kExpandBlock;
-    }
-    // inclusive scan of the tile counts (Hillis-Steele)
-    scan[a] = tiles;
+    // this workgroup's counter updates are complete before it checks in
+    wait_vm_complete();
     __syncthreads();
-    for (uint32_t d = 1; d < kDefaultMaxActive; d <<= 1) {
-        const uint32_t v = a >= d ? scan[a - d] : 0u;
-        __syncthreads();
-        scan[a] += v;
-        __syncthreads();
-    }
-    if (a < n) {
-        begin[a] = scan[a] - tiles;
-        slots[a].tile_begin = scan[a] - tiles;
-    }
-    if (a == kDefaultMaxActive - 1)
-        begin[n] = scan[a];
-}
-
-// Zero the slots a capped level claimed: blockIdx.y = query.
-__global__ void k_step_rollback(const BatchSlot *slots, const StepCtl *ctl) {
-    const uint32_t a = blockIdx.y;
-    const uint32_t n = ctl[a].rollback_n;
-    const uint32_t *next = slots[a].next;
-    uint64_t *bucket = slots[a].t.bucket;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        bucket[next[i]] = 0;
+    if (threadIdx.x == 0)
+        s_last = atomicAdd(arrived, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last)
+        return;
+    step_finalize(slots, ctl, lc, st, begin, n, smem);
+    if (threadIdx.x == 0)
+        *arrived = 0;
 }
 
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-__global__ void k_zero_step(LevelCounters *lc, DevStatus *st, uint32_t n) {
+__global__ void k_zero_step(LevelCounters *lc, DevStatus *st, uint32_t n, uint32_t *arrived) {
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *arrived = 0;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         lc[i] = LevelCounters{0, 0, 0, 0};
         st[i].error = 0;
@@ -253,7 +275,7 @@ lhs_status ensure_step_buffers(reach_server *s, uint32_t n) {
         c <<= 1;
     if (hipMalloc(&s->d_slots, c * sizeof(BatchSlot)) != hipSuccess ||
         hipHostMalloc(&s->h_slots, c * sizeof(BatchSlot), hipHostMallocDefault) != hipSuccess ||
-        hipMalloc(&s->d_begin, (c + 1) * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&s->d_begin, (c + 2) * sizeof(uint32_t)) != hipSuccess ||   // + step arrival count
         hipHostMalloc(&s->h_begin, (c + 1) * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
         hipMalloc(&s->d_lc, c * sizeof(LevelCounters)) != hipSuccess ||
         hipHostMalloc(&s->h_lc, c * sizeof(LevelCounters), hipHostMallocDefault) != hipSuccess ||
@@ -455,12 +477,14 @@ lhs_status step_queries(reach_server *s, std::vector<Query *> &finished) {
         hipMemcpyAsync(s->d_begin, s->h_begin, (na + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s->stream) !=
             hipSuccess)
         return LHS_EDEVICE;
-    hipLaunchKernelGGL(k_zero_step, dim3((na + 255) / 256), dim3(256), 0, s->stream, s->d_lc, s->d_st, na);
+    uint32_t *d_arrived = s->d_begin + s->cap_slots + 1;
+    hipLaunchKernelGGL(k_zero_step, dim3((na + 255) / 256), dim3(256), 0, s->stream, s->d_lc, s->d_st, na,
+                       d_arrived);
     // workgroups for the expansion: enough for the round's first level four
     // times over (later levels loop), at most as many as are resident
     const size_t lds = (size_t)expand_lds_words(maxW, tcap, tps) * sizeof(uint32_t);
     rc = with_shape(tps, s->cfg.line_slots, [&](auto G, auto L) {
-        const void *fn = (const void *)k_expand_step<decltype(G)::value, decltype(L)::value>;
+        const void *fn = (const void *)k_step<decltype(G)::value, decltype(L)::value>;
         int ncu = 0, per_cu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kExpandBlock, lds) != hipSuccess ||
@@ -468,13 +492,10 @@ lhs_status step_queries(reach_server *s, std::vector<Query *> &finished) {
             return LHS_EDEVICE;
         const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)ncu * per_cu,
                                                            std::max<uint64_t>(64, 4ull * tiles));
-        for (uint32_t k = 0; k < kRoundSteps; ++k) {
-            hipLaunchKernelGGL((k_expand_step<decltype(G)::value, decltype(L)::value>), dim3(grid),
-                               dim3(kExpandBlock), lds, s->stream, s->d_slots, s->d_begin, na, tcap);
-            hipLaunchKernelGGL(k_step_finalize, dim3(1), dim3(kDefaultMaxActive), 0, s->stream, s->d_slots,
-                               s->d_ctl, s->d_lc, s->d_st, s->d_begin, na);
-            hipLaunchKernelGGL(k_step_rollback, dim3(32, na), dim3(256), 0, s->stream, s->d_slots, s->d_ctl);
-        }
+        for (uint32_t k = 0; k < kRoundSteps; ++k)
+            hipLaunchKernelGGL((k_step<decltype(G)::value, decltype(L)::value>), dim3(grid), dim3(kExpandBlock),
+                               lds, s->stream, s->d_slots, s->d_begin, na, tcap, s->d_ctl, s->d_lc, s->d_st,
+                               d_arrived);
         return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
     });
     if (rc != LHS_OK)
