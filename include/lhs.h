@@ -379,7 +379,7 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
  * Serving: reachability queries with continuous batching.
  *
  * A server owns a worker thread and a HIP stream on the device that was
- * current at reach_server_create.  It works in rounds of eight BFS level
+ * current at reach_server_create.  It works in rounds of four BFS level
  * steps run by the device alone; every step expands the current level of
  * every active query in one launch.  Between rounds it retires finished
  * queries and admits queued ones (first come, first served) while their

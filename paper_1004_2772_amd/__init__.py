@@ -206,6 +206,18 @@ def _ptr(x) -> int | None:
     return x.data_ptr()
 
 
+def _dptr(x, what: str) -> int | None:
+    """Address of a contiguous GPU tensor (None passes through); anything else
+    is refused before it reaches a kernel as a device address."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray) or not getattr(x, "is_cuda", False):
+        raise ValueError(f"{what} must be a GPU tensor")
+    if not x.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return x.data_ptr()
+
+
 def tune_load(path: str, device: str | None = None) -> int:
     """Load a tuning file (lhs_tune_load); returns the entries kept."""
     n = ctypes.c_uint32()
@@ -281,7 +293,8 @@ class Table:
             raise ValueError("seen must hold n bytes")
         if index is not None and (index.numel() < n or index.element_size() != 4):
             raise ValueError("index must hold n 32-bit words")
-        _check(lib().lhs_find_or_put(self.handle, _ptr(states), n, _ptr(seen), _ptr(index),
+        _check(lib().lhs_find_or_put(self.handle, _dptr(states, "states"), n, _dptr(seen, "seen"),
+                                     _dptr(index, "index"),
                                      _stream_handle(stream)), "lhs_find_or_put")
 
     def check(self):
@@ -500,13 +513,13 @@ class Server:
 
 def probe_random_lines(buf, line_bytes: int, lanes_per_line: int, n_reads: int, seed: int, sink,
                        stream=None):
-    _check(lib().lhs_probe_random_lines(_ptr(buf), buf.numel() * buf.element_size(), line_bytes,
-                                        lanes_per_line, n_reads, seed, _ptr(sink),
+    _check(lib().lhs_probe_random_lines(_dptr(buf, "buf"), buf.numel() * buf.element_size(), line_bytes,
+                                        lanes_per_line, n_reads, seed, _dptr(sink, "sink"),
                                         _stream_handle(stream)), "lhs_probe_random_lines")
 
 
 def probe_random_cas(slots, n_ops: int, seed: int, sink, stream=None):
-    _check(lib().lhs_probe_random_cas(_ptr(slots), slots.numel(), n_ops, seed, _ptr(sink),
+    _check(lib().lhs_probe_random_cas(_dptr(slots, "slots"), slots.numel(), n_ops, seed, _dptr(sink, "sink"),
                                       _stream_handle(stream)), "lhs_probe_random_cas")
 
 
@@ -516,11 +529,11 @@ PROBE_FORMS = {"slot_store": 0, "row_store": 1, "row_load": 2}
 def probe_random_access(buf, form, n_ops: int, seed: int, sink, stream=None):
     """form: "slot_store", "row_store", "row_load" (or its number)."""
     f = PROBE_FORMS[form] if isinstance(form, str) else form
-    _check(lib().lhs_probe_random_access(_ptr(buf), buf.numel() * buf.element_size(), f, n_ops, seed,
-                                         _ptr(sink), _stream_handle(stream)), "lhs_probe_random_access")
+    _check(lib().lhs_probe_random_access(_dptr(buf, "buf"), buf.numel() * buf.element_size(), f, n_ops, seed,
+                                         _dptr(sink, "sink"), _stream_handle(stream)), "lhs_probe_random_access")
 
 
 def probe_copy(dst, src, stream=None):
     nbytes = src.numel() * src.element_size()
     assert dst.numel() * dst.element_size() >= nbytes
-    _check(lib().lhs_probe_copy(_ptr(dst), _ptr(src), nbytes, _stream_handle(stream)), "lhs_probe_copy")
+    _check(lib().lhs_probe_copy(_dptr(dst, "dst"), _dptr(src, "src"), nbytes, _stream_handle(stream)), "lhs_probe_copy")

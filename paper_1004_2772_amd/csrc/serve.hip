@@ -41,7 +41,7 @@ namespace {
 
 constexpr uint64_t kDefaultBudget = 200ull << 30;
 constexpr uint32_t kDefaultMaxActive = 1024;   // also the most a round can hold
-constexpr uint32_t kRoundSteps = 8;
+constexpr uint32_t kRoundSteps = 4;
 
 // Device-side bookkeeping of one active query during a round.
 struct StepCtl {

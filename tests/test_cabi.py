@@ -146,3 +146,14 @@ def test_probes_reject_bad_arguments():
     assert L.lhs_probe_random_lines(fake, 1 << 20, 96, 1, 1, 0, sink, None) == 1       # line width
     assert L.lhs_probe_random_cas(None, 1 << 10, 1, 0, sink, None) == 1
     assert L.lhs_probe_copy(fake, fake, 24, None) == 1                                 # not 16-byte sized
+
+
+def test_binding_refuses_host_buffers_for_device_arguments():
+    import torch
+    host = torch.zeros(1 << 10, dtype=torch.int64)
+    for call in (lambda: lhs.probe_random_access(host, "row_load", 1, 0, host),
+                 lambda: lhs.probe_random_lines(np.zeros(1 << 10, np.int64), 64, 4, 1, 0, host),
+                 lambda: lhs.probe_random_cas(host, 1, 0, host),
+                 lambda: lhs.probe_copy(host, host)):
+        with pytest.raises(ValueError):
+            call()

@@ -215,3 +215,21 @@ def test_concurrent_streams_one_table(lhs, tps, overlap):
     stored, sidx2 = table.dump()
     assert np.array_equal(np.sort(sidx2), np.sort(sidx[first]))
     table.close()
+
+
+def test_host_buffers_refused(lhs):
+    """Host memory passed for a device argument is refused by the binding
+    before any kernel sees it."""
+    import torch
+    with lhs.Table(1 << 12, 4) as t:
+        rows = torch.zeros((8, 4), dtype=torch.int32)
+        seen = torch.empty(8, dtype=torch.uint8, device="cuda")
+        with pytest.raises(ValueError):
+            t.find_or_put(rows, seen)
+        with pytest.raises(ValueError):
+            t.find_or_put(rows.cuda(), torch.empty(8, dtype=torch.uint8))
+        with pytest.raises(ValueError):
+            t.find_or_put(rows.cuda(), seen, torch.empty(8, dtype=torch.int32))
+        t.find_or_put(rows.cuda(), seen)
+        t.check()
+        assert sorted(seen.cpu().tolist()) == [0] + [1] * 7   # one of the equal rows inserts
