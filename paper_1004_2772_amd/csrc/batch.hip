@@ -348,8 +348,8 @@ struct BatchModel {
 
 extern "C" {
 
-lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, const reach_opts *o,
-                               lhs_table *const *tables, reach_result *results) {
+static lhs_status reach_explore_batch_impl(const reach_model *const *models, uint32_t n, const reach_opts *o,
+                                           lhs_table *const *tables, reach_result *results) {
     if (!models || !results || n == 0 || n > kMaxBatch)
         return LHS_EINVAL;
     for (uint32_t i = 0; i < n; ++i) {
@@ -731,6 +731,11 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
         for (uint32_t i = 0; i < n; ++i)
             reach_result_free(&results[i]);
     return rc;
+}
+
+lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, const reach_opts *o,
+                               lhs_table *const *tables, reach_result *results) {
+    return lhs::guard([&] { return reach_explore_batch_impl(models, n, o, tables, results); });
 }
 
 }  // extern "C"

@@ -422,15 +422,19 @@ lhs_status lhs_check(lhs_table *t) {
     return (lhs_status)st.error;
 }
 
-lhs_status lhs_count(lhs_table *t, uint64_t *out) {
+static lhs_status lhs_count_impl(lhs_table *t, uint64_t *out) {
     if (!t || !out)
         return LHS_EINVAL;
     std::vector<uint64_t> offsets;
     return done_offsets(t, offsets, nullptr, out);
 }
 
-lhs_status lhs_dump(lhs_table *t, uint32_t *h_states, uint32_t *h_index, uint64_t max_rows,
-                    uint64_t *n_rows) {
+lhs_status lhs_count(lhs_table *t, uint64_t *out) {
+    return lhs::guard([&] { return lhs_count_impl(t, out); });
+}
+
+static lhs_status lhs_dump_impl(lhs_table *t, uint32_t *h_states, uint32_t *h_index, uint64_t max_rows,
+                                uint64_t *n_rows) {
     if (!t || !n_rows)
         return LHS_EINVAL;
     std::vector<uint64_t> offsets;
@@ -474,6 +478,11 @@ lhs_status lhs_dump(lhs_table *t, uint32_t *h_states, uint32_t *h_index, uint64_
     (void)hipFree(d_rows);
     (void)hipFree(d_idx);
     return rc;
+}
+
+lhs_status lhs_dump(lhs_table *t, uint32_t *h_states, uint32_t *h_index, uint64_t max_rows,
+                    uint64_t *n_rows) {
+    return lhs::guard([&] { return lhs_dump_impl(t, h_states, h_index, max_rows, n_rows); });
 }
 
 lhs_status lhs_dump_slots(lhs_table *t, uint64_t *h_slots) {

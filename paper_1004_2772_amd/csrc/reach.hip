@@ -452,7 +452,7 @@ lhs_status explore_graph(lhs_table *t, const reach_model *m, const uint2 *d_tran
 
 extern "C" {
 
-lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result *r) {
+static lhs_status reach_explore_impl(const reach_model *m, const reach_opts *o, reach_result *r) {
     if (!r)
         return LHS_EINVAL;
     std::memset(r, 0, sizeof(*r));
@@ -558,8 +558,12 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
     return rc;
 }
 
-lhs_status reach_trace(lhs_table *t, uint32_t slot, uint32_t *h_path, uint32_t *h_rows, uint32_t max_len,
-                       uint32_t *len) {
+lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result *r) {
+    return lhs::guard([&] { return reach_explore_impl(m, o, r); });
+}
+
+static lhs_status reach_trace_impl(lhs_table *t, uint32_t slot, uint32_t *h_path, uint32_t *h_rows, uint32_t max_len,
+                                   uint32_t *len) {
     if (!t || !len || !t->has_parents || slot >= t->capacity)
         return LHS_EINVAL;
     if (hipStreamSynchronize(t->last_stream) != hipSuccess)
@@ -593,6 +597,11 @@ lhs_status reach_trace(lhs_table *t, uint32_t slot, uint32_t *h_path, uint32_t *
                               hipMemcpyDeviceToHost));
     }
     return LHS_OK;
+}
+
+lhs_status reach_trace(lhs_table *t, uint32_t slot, uint32_t *h_path, uint32_t *h_rows, uint32_t max_len,
+                       uint32_t *len) {
+    return lhs::guard([&] { return reach_trace_impl(t, slot, h_path, h_rows, max_len, len); });
 }
 
 lhs_status reach_deadlock_slots(lhs_table *t, uint32_t *h_slots, uint32_t max, uint32_t *n) {

@@ -24,6 +24,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -645,7 +646,7 @@ extern "C" {
 
 double reach_server_clock(void) { return now_s(); }
 
-lhs_status reach_server_create(const reach_server_opts *o, reach_server **out) {
+static lhs_status reach_server_create_impl(const reach_server_opts *o, reach_server **out) {
     if (!out)
         return LHS_EINVAL;
     *out = nullptr;
@@ -681,15 +682,26 @@ lhs_status reach_server_create(const reach_server_opts *o, reach_server **out) {
         delete s;
         return LHS_EDEVICE;
     }
-    s->worker = std::thread(worker_main, s);
+    try {
+        s->worker = std::thread(worker_main, s);
+    } catch (...) {
+        (void)hipStreamDestroy(s->stream);
+        delete s;
+        throw;
+    }
     *out = s;
     return LHS_OK;
 }
 
-lhs_status reach_server_submit(reach_server *s, const reach_model *m, uint64_t *ticket) {
+lhs_status reach_server_create(const reach_server_opts *o, reach_server **out) {
+    return lhs::guard([&] { return reach_server_create_impl(o, out); });
+}
+
+static lhs_status reach_server_submit_impl(reach_server *s, const reach_model *m, uint64_t *ticket) {
     if (!s || !ticket || validate_model(m) != LHS_OK)
         return LHS_EINVAL;
-    Query *q = new (std::nothrow) Query();
+    // owned here until queued (freed on every early return or exception)
+    std::unique_ptr<Query> q(new (std::nothrow) Query());
     if (!q)
         return LHS_ENOMEM;
     q->W = m->n_procs + m->n_shared;
@@ -701,30 +713,34 @@ lhs_status reach_server_submit(reach_server *s, const reach_model *m, uint64_t *
     q->m.init = q->init.data();
     q->capacity = s->opts.capacity ? s->opts.capacity
                                    : (m->state_cap ? auto_capacity(m) : (1ull << 21));
-    if (m->state_cap && m->state_cap >= q->capacity) {
-        delete q;
+    if (m->state_cap && m->state_cap >= q->capacity)
         return LHS_EINVAL;
-    }
     q->bytes = table_bytes(q->capacity, q->W);
-    if (q->bytes > s->opts.budget_bytes) {
-        delete q;
+    if (q->bytes > s->opts.budget_bytes)
         return LHS_EBUDGET;
-    }
     q->limit = m->state_cap ? (uint32_t)std::min<uint64_t>(m->state_cap - 1, 0xFFFFFFFFull) : 0xFFFFFFFFu;
     q->levels.push_back(1);
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) {
-        delete q;
+    if (s->stop)
         return LHS_EINVAL;
-    }
     q->ticket = s->next_ticket++;
     q->t_submit = now_s();
-    s->queue.push_back(q);
-    s->tickets[q->ticket] = q;
+    s->tickets[q->ticket] = q.get();
+    try {
+        s->queue.push_back(q.get());
+    } catch (...) {
+        s->tickets.erase(q->ticket);
+        throw;
+    }
     s->stats.submitted += 1;
     *ticket = q->ticket;
+    q.release();
     s->cv_work.notify_one();
     return LHS_OK;
+}
+
+lhs_status reach_server_submit(reach_server *s, const reach_model *m, uint64_t *ticket) {
+    return lhs::guard([&] { return reach_server_submit_impl(s, m, ticket); });
 }
 
 lhs_status reach_server_poll(reach_server *s, uint64_t ticket, reach_result *r, reach_query_times *t) {

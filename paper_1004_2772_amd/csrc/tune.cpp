@@ -381,7 +381,7 @@ lhs_config tuned_config(uint32_t kind, uint32_t W, uint64_t capacity) {
 
 extern "C" {
 
-lhs_status lhs_tune_load(const char *path, const char *device, uint32_t *n_loaded) {
+static lhs_status lhs_tune_load_impl(const char *path, const char *device, uint32_t *n_loaded) {
     if (!path)
         return LHS_EINVAL;
     std::string arch;
@@ -413,6 +413,10 @@ lhs_status lhs_tune_load(const char *path, const char *device, uint32_t *n_loade
     if (n_loaded)
         *n_loaded = (uint32_t)g_entries.size();
     return LHS_OK;
+}
+
+lhs_status lhs_tune_load(const char *path, const char *device, uint32_t *n_loaded) {
+    return lhs::guard([&] { return lhs_tune_load_impl(path, device, n_loaded); });
 }
 
 lhs_status lhs_tune_clear(void) {
