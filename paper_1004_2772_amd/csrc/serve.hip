@@ -568,10 +568,12 @@ void worker_main(reach_server *s) {
         }
         const double t0 = now_s();
         std::vector<Query *> finished;
-        lhs_status rc = start_queries(s, admitted);
+        // an exception (a failed host allocation) ends the queries like a
+        // device failure instead of the process
+        lhs_status rc = lhs::guard([&] { return start_queries(s, admitted); });
         if (rc == LHS_OK) {
             s->active.insert(s->active.end(), admitted.begin(), admitted.end());
-            rc = step_queries(s, finished);
+            rc = lhs::guard([&] { return step_queries(s, finished); });
         } else {
             for (Query *q : admitted) {
                 q->status = rc;
