@@ -200,9 +200,11 @@ def _ptr(x) -> int | None:
     if x is None:
         return None
     if isinstance(x, np.ndarray):
-        assert x.flags["C_CONTIGUOUS"]
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
         return x.ctypes.data
-    assert x.is_contiguous()
+    if not x.is_contiguous():
+        raise ValueError("tensor must be contiguous")
     return x.data_ptr()
 
 
@@ -535,5 +537,6 @@ def probe_random_access(buf, form, n_ops: int, seed: int, sink, stream=None):
 
 def probe_copy(dst, src, stream=None):
     nbytes = src.numel() * src.element_size()
-    assert dst.numel() * dst.element_size() >= nbytes
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst is smaller than src")
     _check(lib().lhs_probe_copy(_dptr(dst, "dst"), _dptr(src, "src"), nbytes, _stream_handle(stream)), "lhs_probe_copy")

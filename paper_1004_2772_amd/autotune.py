@@ -232,7 +232,8 @@ def main(argv=None):
         return reselect(a.reselect)
 
     import torch
-    assert torch.cuda.is_available(), "the autotuner times kernels on a GPU"
+    if not torch.cuda.is_available():
+        raise RuntimeError("the autotuner times kernels on a GPU")
     props = torch.cuda.get_device_properties(0)
     arch = props.gcnArchName.split(":")[0]
     entries = []

@@ -117,7 +117,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     a = ap.parse_args(argv)
     import torch
-    assert torch.cuda.is_available(), "the scaling runs time kernels on a GPU"
+    if not torch.cuda.is_available():
+        raise RuntimeError("the scaling runs time kernels on a GPU")
     tune_load_default()
     # 1024 = 4 workgroups on each of 256 compute units, what fits at once
     workers = [4, 256] if a.quick else [1, 4, 16, 64, 256, 1024]

@@ -102,7 +102,8 @@ def main(argv=None):
     ap.add_argument("--txt", default="", help="also write the G ops/s and lines-per-op tables")
     a = ap.parse_args(argv)
     import torch
-    assert torch.cuda.is_available(), "the sweep times kernels on a GPU"
+    if not torch.cuda.is_available():
+        raise RuntimeError("the sweep times kernels on a GPU")
     tune_load_default()     # tables take the tuned shapes, as the benchmark's do
     if a.quick:
         points = [(W, c, n) for W in (4, 16) for c in (16,) for n in (0, 2)]
