@@ -470,6 +470,9 @@ static lhs_status reach_explore_impl(const reach_model *m, const reach_opts *o, 
     if (async && (opts.flags & REACH_F_GRAPH))
         return LHS_EINVAL;   // no levels to capture
 
+    // host-side packing first: nothing to undo if it throws
+    std::vector<uint2> packed;
+    pack_model(m, packed);
     lhs_table *t = opts.table;
     bool own = false;
     if (parents && !t)
@@ -489,8 +492,6 @@ static lhs_status reach_explore_impl(const reach_model *m, const reach_opts *o, 
             lhs_destroy(t);
         return LHS_EINVAL;
     }
-    std::vector<uint2> packed;
-    pack_model(m, packed);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
         if (own)
