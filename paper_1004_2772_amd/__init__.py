@@ -125,6 +125,13 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1004_2772_amd.build`")
+        # torch's HIP runtime first: started by the library instead, it
+        # leaves torch without a GPU in this process
+        try:
+            import torch
+            torch.cuda.is_available()
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         u64, u32, p, st = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
         L.lhs_strerror.argtypes = [st]
