@@ -12,6 +12,12 @@
         TCC_ATOMIC_sum (atomic requests at the L2) and TCC_EA0_ATOMIC_sum (atomics
         sent on to memory) of a kernel's largest dispatch and of the random-CAS
         probe's, written as JSON for bench.py (which divides by the launch times).
+    python -m paper_1004_2772_amd.profile_summary traffic-sum FETCH_DB WRITE_DB --kernel K1 [--kernel K2] \
+        --runs R [--take D] --units N --unit-name NAME --copy-bytes B --out JSON [--cmd "..."]
+        FETCH_SIZE / WRITE_SIZE summed over the dispatches of the named kernels
+        (the first D in dispatch order, default all), divided by R (the program
+        ran the same work R times in them), scaled by the copy
+        probe as above; per run and per unit (e.g. per edge of an exploration).
 """
 from __future__ import annotations
 
@@ -98,6 +104,17 @@ def main(argv=None):
     at.add_argument("--sources", required=True)
     at.add_argument("--out", required=True)
     at.add_argument("--cmd", default="")
+    ts = sub.add_parser("traffic-sum")
+    ts.add_argument("fetch_db")
+    ts.add_argument("write_db")
+    ts.add_argument("--kernel", action="append", required=True)
+    ts.add_argument("--runs", type=int, required=True)
+    ts.add_argument("--take", type=int, default=0)
+    ts.add_argument("--units", type=int, required=True)
+    ts.add_argument("--unit-name", default="units")
+    ts.add_argument("--copy-bytes", type=int, required=True)
+    ts.add_argument("--out", required=True)
+    ts.add_argument("--cmd", default="")
     a = ap.parse_args(argv)
 
     if a.mode == "stats":
@@ -129,6 +146,29 @@ def main(argv=None):
 
     fetch = counter_per_dispatch(a.fetch_db, "FETCH_SIZE")
     write = counter_per_dispatch(a.write_db, "WRITE_SIZE")
+    if a.mode == "traffic-sum":
+        if not fetch.get("k_probe_copy") or not write.get("k_probe_copy"):
+            sys.exit("copy probe missing from the counter runs (run bench.py with --calib-copy)")
+        f_fetch = a.copy_bytes / (largest_dispatch(fetch["k_probe_copy"]) * 1024.0)
+        f_write = a.copy_bytes / (largest_dispatch(write["k_probe_copy"]) * 1024.0)
+        names = a.kernel
+        missing = [n for n in names if n not in fetch or n not in write]
+        if missing:
+            sys.exit(f"kernels missing from the counter runs: {missing}")
+        take = a.take or None
+        fl = [v for n in names for _, v in fetch[n]][:take]
+        wl = [v for n in names for _, v in write[n]][:take]
+        kf, kw = sum(fl) / a.runs, sum(wl) / a.runs
+        res = dict(kernels=names, runs=a.runs, dispatches_per_run=len(fl) / a.runs,
+                   fetch_scale=f_fetch, write_scale=f_write,
+                   fetch_bytes_per_run=kf * 1024.0 * f_fetch, write_bytes_per_run=kw * 1024.0 * f_write,
+                   units_per_run=a.units, unit=a.unit_name, command=a.cmd)
+        res[f"fetch_bytes_per_{a.unit_name}"] = res["fetch_bytes_per_run"] / a.units
+        res[f"write_bytes_per_{a.unit_name}"] = res["write_bytes_per_run"] / a.units
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res, indent=1))
+        return
     copy_f = fetch.get("k_probe_copy")
     copy_w = write.get("k_probe_copy")
     if not copy_f or not copy_w:
