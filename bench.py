@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--no-probes", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-async", action="store_true", help="skip the exploration-without-levels leg")
+    ap.add_argument("--no-chain", action="store_true",
+                    help="in that leg, skip the chain of one-state levels (tens of thousands of launches)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="query arrivals per second")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
@@ -438,15 +440,16 @@ def main():
                 g = json.load(f)
             nl["matches_oracle"] = (g["total"], g["edges"], g["deadlocks"]) == (ra.total, ra.edges, ra.deadlocks)
         log(f"wide model: level loop {b_ms:.2f} ms, graph levels {g_ms:.2f} ms, no levels {a_ms:.2f} ms")
-        cm = gen.chain_model()
-        with lhs.Table(1 << 16, cm.W) as ct:
-            cg_ms, rcg = median_ms(cm, ct, lhs.REACH_F_GRAPH, 1)
-            ca_ms, rca = median_ms(cm, ct, lhs.REACH_F_ASYNC, 1)
-        nl["chain"] = {"workload": f"chain of {cm.L} one-state levels", "states": rca.total,
-                       "no_levels_ms": round(ca_ms, 2), "graph_levels_ms": round(cg_ms, 2),
-                       "us_per_state_no_levels": round(ca_ms * 1e3 / rca.total, 2),
-                       "same_result": (rca.total, rca.edges) == (rcg.total, rcg.edges)}
-        log(f"chain: graph levels {cg_ms:.1f} ms, no levels {ca_ms:.1f} ms")
+        if not args.no_chain:
+            cm = gen.chain_model()
+            with lhs.Table(1 << 16, cm.W) as ct:
+                cg_ms, rcg = median_ms(cm, ct, lhs.REACH_F_GRAPH, 1)
+                ca_ms, rca = median_ms(cm, ct, lhs.REACH_F_ASYNC, 1)
+            nl["chain"] = {"workload": f"chain of {cm.L} one-state levels", "states": rca.total,
+                           "no_levels_ms": round(ca_ms, 2), "graph_levels_ms": round(cg_ms, 2),
+                           "us_per_state_no_levels": round(ca_ms * 1e3 / rca.total, 2),
+                           "same_result": (rca.total, rca.edges) == (rcg.total, rcg.edges)}
+            log(f"chain: graph levels {cg_ms:.1f} ms, no levels {ca_ms:.1f} ms")
         out["no_levels"] = nl
     if sweep:
         out["tps_sweep"] = sweep
