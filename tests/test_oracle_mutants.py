@@ -2,7 +2,7 @@
 
 Each mutant is a textual edit of oracle/oracle.cpp compiled into a temporary
 library; the pins (hand fixtures, closed forms, brute force, the O(n^2) stream
-definition) are re-run against it and at least one must fail.  The original
+definition, the digest's known answer and word coverage) are re-run against it and at least one must fail.  The original
 snippet must still be present, so the list follows the oracle as it changes.
 """
 import os
@@ -17,6 +17,7 @@ from oracle.brute import brute
 from oracle.closed_form import cyclic_capped, cyclic_summary
 
 from conftest import ROOT, load_golden, model_from_fixture, result_fields
+from test_oracle_pins import FNV_TO_SPLITMIX_SEED0, SPLITMIX64_SEED0_FIRST, _digest_sees_every_word
 
 MUTANTS = [
     ("guard reads a local instead of the shared var",
@@ -37,6 +38,13 @@ MUTANTS = [
      "level_counts[sum->n_levels++] = fresh + (fresh > 3);"),
     ("stream seen polarity", "seen[k] = 1;", "seen[k] = 0;"),
     ("stream id of repeat", "id[k] = it->second;", "id[k] = static_cast<uint32_t>(distinct - 1);"),
+    ("digest skips the last word", "for (uint32_t i = 0; i < W; ++i) {\n        h ^= r[i];",
+     "for (uint32_t i = 0; i < W - 1; ++i) {\n        h ^= r[i];"),
+    ("digest reads half the row", "for (uint32_t i = 0; i < W; ++i) {\n        h ^= r[i];",
+     "for (uint32_t i = 0; i < W / 2; ++i) {\n        h ^= r[i];"),
+    ("digest reads one word over and over", "h ^= r[i];", "h ^= r[0];"),
+    ("digest finaliser step dropped", "h ^= h >> 27;", "(void)0;"),
+    ("set digest keeps only the last row", "s += d;", "s = d;"),
 ]
 
 
@@ -63,6 +71,12 @@ def _pins_pass(lib) -> bool:
                                   int(rng.integers(1, 3)), int(rng.integers(2, 4)), int(rng.integers(1, 4)))
             b = brute(m, cap=0)
             if result_fields(oracle.reach(m, cap=0)) != b:
+                return False
+        if oracle.digest(np.array([FNV_TO_SPLITMIX_SEED0], dtype=np.uint32)) != \
+                (1, SPLITMIX64_SEED0_FIRST, SPLITMIX64_SEED0_FIRST):
+            return False
+        for W in (1, 2, 17, 32):
+            if not _digest_sees_every_word(W):
                 return False
         for fx in load_golden("stream_fixtures.json")["fixtures"]:
             seen, ids, d = oracle.stream(np.array(fx["rows"], dtype=np.uint32))

@@ -130,6 +130,57 @@ def test_digest_properties():
     assert oracle.digest(rows[:63].copy())[0] == 63
 
 
+# A two-word row whose word-wise FNV-1a state (offset basis 0xcbf29ce484222325,
+# prime 2^40 + 0x1b3) is 0x9e3779b97f4a7c15, the state SplitMix64 (Steele,
+# Lea, Flood 2014) finalises for its first output from seed 0.  The row is
+# the only solution: the second word must bring the state to that value by
+# xor, so the first word is fixed by the high 32 bits (solved by hand over
+# the carries of the multiplication by the prime).  Its digest is then
+# SplitMix64's published first output for seed 0.
+FNV_TO_SPLITMIX_SEED0 = (0x4388CBF7, 0x5D464BC1)
+SPLITMIX64_SEED0_FIRST = 0xE220A8397B1DCDAF
+
+
+def test_digest_known_answer():
+    row = np.array([FNV_TO_SPLITMIX_SEED0], dtype=np.uint32)
+    assert oracle.digest(row) == (1, SPLITMIX64_SEED0_FIRST, SPLITMIX64_SEED0_FIRST)
+
+
+def _digest_sees_every_word(W: int) -> bool:
+    """Every word position and bit of a row reaches the digest (sum and xor
+    both change), swapping two different words changes it, and the set digest
+    is the wrapping sum and xor of the single-row digests."""
+    rows = gen.words(100 + W, 6 * W).reshape(6, W)
+    base = oracle.digest(rows)
+    seen = {oracle.digest(rows[2:3].copy())}
+    for j in range(W):
+        for bit in (0, 17, 31):
+            f = rows.copy()
+            f[2, j] ^= np.uint32(1 << bit)
+            d = oracle.digest(f)
+            if d[1] == base[1] or d[2] == base[2]:
+                return False
+            seen.add(oracle.digest(f[2:3].copy()))
+    if len(seen) != 3 * W + 1:        # distinct single rows, distinct digests
+        return False
+    if W >= 2:
+        sw = rows.copy()
+        sw[4, 0], sw[4, W - 1] = rows[4, W - 1], rows[4, 0]
+        if rows[4, 0] != rows[4, W - 1] and oracle.digest(sw) == base:
+            return False
+    singles = [oracle.digest(rows[k:k + 1].copy()) for k in range(len(rows))]
+    s = sum(x[1] for x in singles) % (1 << 64)
+    x = 0
+    for d in singles:
+        x ^= d[2]
+    return base == (len(rows), s, x)
+
+
+@pytest.mark.parametrize("W", [1, 2, 3, 16, 17, 32])
+def test_digest_sees_every_word(W):
+    assert _digest_sees_every_word(W)
+
+
 def test_generators_deterministic_and_in_range():
     a = gen.guarded_model(42, 12, 16, 4, 10, 3)
     b = gen.guarded_model(42, 12, 16, 4, 10, 3)
