@@ -134,13 +134,24 @@ lhs_status lhs_find_or_put(lhs_table *t, const uint32_t *d_states, uint64_t n,
 lhs_status lhs_set_threads_per_state(lhs_table *t, uint32_t tps);
 
 /* Wait for the last stream used with the table, then return its sticky
- * device error (LHS_EFULL / LHS_ESTALL) or LHS_OK. */
+ * device error (LHS_EFULL / LHS_ESTALL) or LHS_OK.  The paper lets a probe
+ * continue indefinitely and a writer's slot stay busy for as long as the
+ * write takes (section "Algorithm", Algorithm 3's probe loop and wait loop);
+ * here both are bounded and their failures are reported by this call.
+ * LHS_EINVAL for a null table, LHS_EDEVICE if the synchronisation fails. */
 lhs_status lhs_check(lhs_table *t);
 
-/* Number of stored (completely written) vectors.  Synchronous. */
+/* Number of stored vectors: slots in the done state of the bucket state
+ * diagram (figure "State diagram of buckets": empty -> write -> done).
+ * Slots still being written are not counted.  Synchronous (waits for the
+ * table's last stream); uses temporary device memory.  LHS_EINVAL for a null
+ * argument. */
 lhs_status lhs_count(lhs_table *t, uint64_t *out);
 
-/* Copy every stored vector to host memory, in ascending slot order.
+/* Copy every stored vector to host memory, in ascending slot order: the
+ * vectors of the done slots of the bucket state diagram (figure "State
+ * diagram of buckets"), read from the separate data array that the slot
+ * index addresses (section "Hash Table Design").
  *   h_states : host, room for max_rows * state_words uint32 (may be NULL
  *              to only count).
  *   h_index  : host, room for max_rows uint32 (may be NULL): slot of each row.
@@ -427,6 +438,22 @@ lhs_status reach_server_create(const reach_server_opts *o, reach_server **out);
  * on return.  *ticket identifies the query.  LHS_EBUDGET if its table can
  * never fit the budget, LHS_EINVAL for an invalid model. */
 lhs_status reach_server_submit(reach_server *s, const reach_model *m, uint64_t *ticket);
+
+/* reach_server_submit on a table of the caller's (NULL = the pool, as
+ * reach_server_submit).  The query's result is its visited set V of
+ * Algorithm 1, which the table keeps: once the query is collected
+ * (reach_server_poll / reach_server_wait) the table holds exactly the states
+ * of the kept levels (a level discarded by state_cap is undone) and can be
+ * read with lhs_dump / lhs_count.  The table is cleared when the query is
+ * admitted.  It must have the query's width, the server's line_slots and the
+ * server's device, which must be current, and capacity > state_cap.  Its
+ * memory is the caller's: it is not counted against budget_bytes and never
+ * pooled.  Its BFS frontiers are allocated now if it has none.  Between
+ * submission and collection the caller must not use or destroy the table;
+ * a table serves one query at a time.  Errors: LHS_EINVAL (also for a table
+ * already serving a query), LHS_ENOMEM. */
+lhs_status reach_server_submit_ex(reach_server *s, const reach_model *m, lhs_table *table,
+                                  uint64_t *ticket);
 
 /* Non-blocking: LHS_EAGAIN while the query runs; otherwise fills r (free with
  * reach_result_free) and t (either may be NULL), forgets the ticket and

@@ -38,7 +38,8 @@ EXPORTS = ["lhs_strerror", "lhs_create", "lhs_create_ex", "lhs_get_config", "lhs
            "lhs_check", "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info",
            "reach_explore", "reach_result_free", "reach_explore_batch", "reach_trace",
            "reach_deadlock_slots",
-           "reach_server_clock", "reach_server_create", "reach_server_submit", "reach_server_poll",
+           "reach_server_clock", "reach_server_create", "reach_server_submit", "reach_server_submit_ex",
+           "reach_server_poll",
            "reach_server_wait", "reach_server_get_stats", "reach_server_destroy",
            "lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_random_access", "lhs_probe_copy"]
 
@@ -167,6 +168,7 @@ def lib() -> ctypes.CDLL:
         L.reach_server_clock.restype = ctypes.c_double
         L.reach_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(p)]
         L.reach_server_submit.argtypes = [p, ctypes.POINTER(ReachModel), ctypes.POINTER(u64)]
+        L.reach_server_submit_ex.argtypes = [p, ctypes.POINTER(ReachModel), p, ctypes.POINTER(u64)]
         L.reach_server_poll.argtypes = [p, u64, ctypes.POINTER(ReachResultC), ctypes.POINTER(QueryTimes)]
         L.reach_server_wait.argtypes = [p, u64, ctypes.POINTER(ReachResultC), ctypes.POINTER(QueryTimes)]
         L.reach_server_get_stats.argtypes = [p, ctypes.POINTER(ServerStats)]
@@ -182,7 +184,7 @@ def lib() -> ctypes.CDLL:
                      "lhs_tune_load", "lhs_tune_clear", "lhs_tune_lookup",
                      "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info", "reach_explore",
                      "reach_explore_batch", "reach_trace", "reach_deadlock_slots",
-                     "reach_server_create", "reach_server_submit",
+                     "reach_server_create", "reach_server_submit", "reach_server_submit_ex",
                      "reach_server_poll", "reach_server_wait", "reach_server_get_stats",
                      "reach_server_destroy"):
             getattr(L, name).restype = st
@@ -470,11 +472,17 @@ class Server:
     def clock() -> float:
         return lib().reach_server_clock()
 
-    def submit(self, model, cap: int | None = None) -> int:
+    def submit(self, model, cap: int | None = None, table: Table | None = None) -> int:
+        """Queue a query; with ``table`` it runs on that table, which keeps
+        the query's reachable set once collected (reach_server_submit_ex)."""
         m, keep = _model_struct(model, cap)
         t = ctypes.c_uint64()
-        _check(lib().reach_server_submit(self.handle, ctypes.byref(m), ctypes.byref(t)),
-               "reach_server_submit")
+        if table is None:
+            _check(lib().reach_server_submit(self.handle, ctypes.byref(m), ctypes.byref(t)),
+                   "reach_server_submit")
+        else:
+            _check(lib().reach_server_submit_ex(self.handle, ctypes.byref(m), table.handle, ctypes.byref(t)),
+                   "reach_server_submit_ex")
         del keep
         return t.value
 

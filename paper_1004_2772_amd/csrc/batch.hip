@@ -270,6 +270,9 @@ __global__ __launch_bounds__(kExpandBlock) void k_batch_persistent(const ModelSt
             // level open: once the count below reaches it, the finaliser
             // may already be writing the next level's count
             const uint32_t total = ld_coherent(&L.tiles_total);
+            // the load and the add go to different addresses, which the
+            // memory model does not order: the load completes first
+            wait_vm_complete();
             const uint32_t done = atomicAdd(&L.tiles_done, 1u) + 1u;
             s_fin = done == total;
         }

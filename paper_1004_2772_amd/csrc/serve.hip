@@ -49,7 +49,8 @@ struct StepCtl {
     uint32_t *fr[2];
     unsigned long long cap, total, edges, deadlocks, wait_hits;
     unsigned long long lv[kRoundSteps];   // level counts found in this round
-    uint32_t lv_n, cur, done, capped, error, pad;
+    uint32_t lv_n, cur, done, capped, error;
+    uint32_t rollback_n;   // capped: entries of the discarded level in fr[cur ^ 1]
 };
 
 // Every query's level bookkeeping after a step, then the next step's tile
@@ -79,6 +80,7 @@ __device__ void step_finalize(BatchSlot *slots, StepCtl *ctl, LevelCounters *lc,
                 } else if (C.cap && n_next > S.limit) {
                     C.capped = 1;
                     C.done = 1;
+                    C.rollback_n = n_next;
                 } else {
                     C.edges += ld_coherent(&lc[a].edges);
                     C.deadlocks += ld_coherent(&lc[a].deadlocks);
@@ -189,6 +191,7 @@ struct Query {
     uint64_t capacity = 0, bytes = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
     lhs_table *t = nullptr;
+    lhs_table *caller = nullptr;   // the caller's table (reach_server_submit_ex)
     uint2 *d_trans = nullptr;
     uint32_t n_cur = 1, cur = 0, limit = 0;
     std::vector<uint64_t> levels;
@@ -296,6 +299,10 @@ lhs_status ensure_step_buffers(reach_server *s, uint32_t n) {
 // now.  Pooled tables of q's shape are reused; otherwise pooled tables are
 // freed until a new one fits the budget.
 bool acquire_table(reach_server *s, Query *q) {
+    if (q->caller) {
+        q->t = q->caller;
+        return true;
+    }
     auto key = std::make_pair(q->capacity, q->W);
     auto it = s->pool.find(key);
     if (it != s->pool.end()) {
@@ -329,7 +336,7 @@ size_t trans_class(size_t bytes) {
 }
 
 void release_table(reach_server *s, Query *q) {
-    if (q->t)
+    if (q->t && !q->caller)
         s->pool.emplace(std::make_pair(q->t->capacity, q->t->W), q->t);
     q->t = nullptr;
     if (q->d_trans) {
@@ -442,7 +449,7 @@ lhs_status step_queries(reach_server *s, std::vector<Query *> &finished) {
     lhs_status rc = ensure_step_buffers(s, na);
     if (rc != LHS_OK)
         return rc;
-    uint32_t tiles = 0, maxW = 1, tps = 1, tcap = 0;
+    uint32_t tiles = 0, maxW = 1, tps = 0, tcap = 0;
     for (uint32_t a = 0; a < na; ++a) {
         Query *q = s->active[a];
         BatchSlot &sl = s->h_slots[a];
@@ -469,8 +476,8 @@ lhs_status step_queries(reach_server *s, std::vector<Query *> &finished) {
         tiles += (q->n_cur + kExpandBlock - 1) / kExpandBlock;
         maxW = std::max(maxW, q->W);
         tcap = std::max(tcap, trans_lds_entries(q->m.n_procs, q->m.n_locals, q->m.trans_per_local));
-        tps = tps_expand(q->t);
     }
+    tps = s->cfg.tps_expand ? s->cfg.tps_expand : kDefaultTpsExpand;
     s->h_begin[na] = tiles;
     if (hipMemcpyAsync(s->d_slots, s->h_slots, na * sizeof(BatchSlot), hipMemcpyHostToDevice, s->stream) !=
             hipSuccess ||
@@ -508,10 +515,18 @@ lhs_status step_queries(reach_server *s, std::vector<Query *> &finished) {
         return LHS_EDEVICE;
     std::vector<Query *> keep;
     keep.reserve(na);
+    bool rolled_back = false;
     for (uint32_t a = 0; a < na; ++a) {
         Query *q = s->active[a];
         const StepCtl &c = s->h_ctl[a];
         const BatchSlot &sl = s->h_slots[a];
+        if (c.capped && q->caller && c.rollback_n) {
+            // a caller's table keeps the result: undo the discarded level
+            // (pooled tables are emptied when next handed out instead)
+            hipLaunchKernelGGL(k_rollback_one, dim3(std::min<uint32_t>((c.rollback_n + 255) / 256, 4096)),
+                               dim3(256), 0, s->stream, q->t->bucket, c.fr[c.cur ^ 1u], c.rollback_n);
+            rolled_back = true;
+        }
         q->wait_hits += c.wait_hits;
         q->levels.insert(q->levels.end(), c.lv, c.lv + c.lv_n);
         q->total = c.total;
@@ -526,6 +541,8 @@ lhs_status step_queries(reach_server *s, std::vector<Query *> &finished) {
         (c.done ? finished : keep).push_back(q);
     }
     s->active.swap(keep);
+    if (rolled_back && (hipGetLastError() != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess))
+        return LHS_EDEVICE;
     return LHS_OK;
 }
 
@@ -635,6 +652,13 @@ lhs_status collect(reach_server *s, Query *q, reach_result *r, reach_query_times
                 std::memcpy(r->level_counts, q->levels.data(), q->levels.size() * sizeof(uint64_t));
         }
     }
+    if (q->caller) {
+        // its work is complete (the round that ended the query was waited
+        // for); hand it back on the null stream: the server's stream dies
+        // with the server
+        q->caller->last_stream = nullptr;
+        q->caller->served_by = nullptr;
+    }
     s->tickets.erase(q->ticket);
     delete q;
     // other threads waiting on this ticket see it gone
@@ -699,9 +723,19 @@ lhs_status reach_server_create(const reach_server_opts *o, reach_server **out) {
     return lhs::guard([&] { return reach_server_create_impl(o, out); });
 }
 
-static lhs_status reach_server_submit_impl(reach_server *s, const reach_model *m, uint64_t *ticket) {
+static lhs_status reach_server_submit_impl(reach_server *s, const reach_model *m, lhs_table *table,
+                                           uint64_t *ticket) {
     if (!s || !ticket || validate_model(m) != LHS_OK)
         return LHS_EINVAL;
+    if (table) {
+        // one launch serves every query: the table must have the server's
+        // line width and live on the server's device, which is current
+        int dev = -1;
+        if (table->W != m->n_procs + m->n_shared || table->line_slots != s->cfg.line_slots ||
+            table->device != s->device || hipGetDevice(&dev) != hipSuccess || dev != s->device ||
+            (m->state_cap && m->state_cap >= table->capacity))
+            return LHS_EINVAL;
+    }
     // owned here until queued (freed on every early return or exception)
     std::unique_ptr<Query> q(new (std::nothrow) Query());
     if (!q)
@@ -713,18 +747,36 @@ static lhs_status reach_server_submit_impl(reach_server *s, const reach_model *m
     q->m = *m;
     q->m.trans = q->trans.data();
     q->m.init = q->init.data();
-    q->capacity = s->opts.capacity ? s->opts.capacity
-                                   : (m->state_cap ? auto_capacity(m) : (1ull << 21));
-    if (m->state_cap && m->state_cap >= q->capacity)
-        return LHS_EINVAL;
-    q->bytes = table_bytes(q->capacity, q->W);
-    if (q->bytes > s->opts.budget_bytes)
-        return LHS_EBUDGET;
+    if (table) {
+        // the caller's memory: not pooled and not counted against the budget
+        q->caller = table;
+        q->capacity = table->capacity;
+        q->bytes = 0;
+    } else {
+        q->capacity = s->opts.capacity ? s->opts.capacity
+                                       : (m->state_cap ? auto_capacity(m) : (1ull << 21));
+        if (m->state_cap && m->state_cap >= q->capacity)
+            return LHS_EINVAL;
+        q->bytes = table_bytes(q->capacity, q->W);
+        if (q->bytes > s->opts.budget_bytes)
+            return LHS_EBUDGET;
+    }
     q->limit = m->state_cap ? (uint32_t)std::min<uint64_t>(m->state_cap - 1, 0xFFFFFFFFull) : 0xFFFFFFFFu;
     q->levels.push_back(1);
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop)
         return LHS_EINVAL;
+    if (table) {
+        // a table serves one query at a time; its frontiers are allocated
+        // here, on the caller's thread, before the worker sees the query
+        const void *idle = nullptr;
+        if (!table->served_by.compare_exchange_strong(idle, s))
+            return LHS_EINVAL;
+        if (ensure_bfs_buffers(table) != LHS_OK) {
+            table->served_by = nullptr;
+            return LHS_ENOMEM;
+        }
+    }
     q->ticket = s->next_ticket++;
     q->t_submit = now_s();
     s->tickets[q->ticket] = q.get();
@@ -732,6 +784,8 @@ static lhs_status reach_server_submit_impl(reach_server *s, const reach_model *m
         s->queue.push_back(q.get());
     } catch (...) {
         s->tickets.erase(q->ticket);
+        if (table)
+            table->served_by = nullptr;
         throw;
     }
     s->stats.submitted += 1;
@@ -742,7 +796,11 @@ static lhs_status reach_server_submit_impl(reach_server *s, const reach_model *m
 }
 
 lhs_status reach_server_submit(reach_server *s, const reach_model *m, uint64_t *ticket) {
-    return lhs::guard([&] { return reach_server_submit_impl(s, m, ticket); });
+    return lhs::guard([&] { return reach_server_submit_impl(s, m, nullptr, ticket); });
+}
+
+lhs_status reach_server_submit_ex(reach_server *s, const reach_model *m, lhs_table *table, uint64_t *ticket) {
+    return lhs::guard([&] { return reach_server_submit_impl(s, m, table, ticket); });
 }
 
 lhs_status reach_server_poll(reach_server *s, uint64_t ticket, reach_result *r, reach_query_times *t) {
@@ -796,8 +854,13 @@ lhs_status reach_server_destroy(reach_server *s) {
     (void)hipStreamSynchronize(s->stream);
     for (auto &e : s->pool)
         lhs_destroy(e.second);
-    for (auto &e : s->tickets)
+    for (auto &e : s->tickets) {
+        if (e.second->caller) {
+            e.second->caller->last_stream = nullptr;
+            e.second->caller->served_by = nullptr;
+        }
         delete e.second;
+    }
     free_step_buffers(s);
     (void)hipFree(s->d_roots);
     (void)hipFree(s->d_root_off);

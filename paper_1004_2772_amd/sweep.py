@@ -35,7 +35,7 @@ def log(msg):
     print(f"[sweep {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def run_one(W: int, log2cap: int, n_reads: int, seed: int, count: bool = False) -> list:
+def run_one(W: int, log2cap: int, n_reads: int, seed: int, count_lines: bool = False) -> list:
     import torch
 
     import gen
@@ -45,7 +45,7 @@ def run_one(W: int, log2cap: int, n_reads: int, seed: int, count: bool = False) 
     out = []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with Table(cap, W) as t:
-        if count:
+        if count_lines:
             t.set_counters(1)      # lines probed per operation
         lines_before = waits_before = cas_before = 0
         lo = 0
@@ -75,20 +75,20 @@ def run_one(W: int, log2cap: int, n_reads: int, seed: int, count: bool = False) 
             t.check()
             seen_h = seen.cpu().numpy()
             ok = bool(np.all(seen_h[is_write] == 0) and np.all(seen_h[~is_write] == 1))
-            count = t.count()
-            ok = ok and count == hi
+            stored = t.count()
+            ok = ok and stored == hi
             info = t.info()
             lines, waits, cas = info["lines_probed"], info["wait_hits"], info["cas_failures"]
             band = {"fill_from": round(lo / cap, 4), "fill_to": frac, "writes": nw, "reads": nr,
                     "ms": round(ms, 4), "Gops": round(ops / ms / 1e6, 3),
                     "wait_hits": waits - waits_before, "cas_failures": cas - cas_before, "ok": ok}
-            if count:
+            if count_lines:
                 band["lines_per_op"] = round((lines - lines_before) / ops, 3)
             out.append(band)
             lines_before, waits_before, cas_before = lines, waits, cas
             if not ok:
                 raise RuntimeError(f"sweep W={W} 2^{log2cap} n={n_reads} band {frac}: wrong seen flags "
-                                   f"or count {count} != {hi}")
+                                   f"or count {stored} != {hi}")
             lo = hi
             del batch, seen
     torch.cuda.empty_cache()
@@ -114,7 +114,7 @@ def main(argv=None):
     t0 = time.time()
     for i, (W, c, n) in enumerate(points):
         bands = run_one(W, c, n, 1000 + i)
-        counted = run_one(W, c, n, 1000 + i, count=True)
+        counted = run_one(W, c, n, 1000 + i, count_lines=True)
         for b, cb in zip(bands, counted):
             b["lines_per_op"] = cb["lines_per_op"]
         res["points"].append({"W": W, "log2_capacity": c, "reads_per_write": n, "bands": bands})

@@ -7,6 +7,25 @@ DONE = np.uint64(1 << 62)
 MEMO = np.uint64((1 << 62) - 1)
 
 
+def sorted_rows(a: np.ndarray) -> np.ndarray:
+    """Rows of a [n, W] uint32 array in one fixed total order (bytewise, via
+    a void view): two arrays hold the same multiset of rows iff their sorted
+    forms are equal."""
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    if a.ndim != 2 or len(a) == 0:
+        return a
+    v = a.view(np.dtype((np.void, a.shape[1] * 4))).ravel()
+    return a[np.argsort(v, kind="stable")]
+
+
+def assert_same_set(got: np.ndarray, want: np.ndarray, what=""):
+    """The GPU's stored rows equal the oracle's states, row by row."""
+    got = np.asarray(got, dtype=np.uint32)
+    want = np.asarray(want, dtype=np.uint32)
+    assert got.shape == want.shape, (what, got.shape, want.shape)
+    assert np.array_equal(sorted_rows(got), sorted_rows(want)), f"stored set differs: {what}"
+
+
 def dev_u32(a):
     """numpy uint32 array -> contiguous int32 CUDA tensor with the same bits."""
     import torch

@@ -1,8 +1,8 @@
 """Batched exploration (many models in one launch) vs the CPU oracle.
 
 Each model's result must equal the oracle's (per-level counts, edges,
-deadlocks, capped flag, stored-set digest) and the result of exploring it
-alone, for the persistent driver and the host-loop driver."""
+deadlocks, capped flag, and the stored set row by row) and the result of
+exploring it alone, for the persistent driver and the host-loop driver."""
 import json
 import os
 
@@ -13,6 +13,7 @@ import gen
 import oracle
 
 from conftest import GOLDEN, result_fields
+from gpu_util import assert_same_set
 
 pytestmark = pytest.mark.gpu
 
@@ -49,7 +50,7 @@ def test_batch_small_vs_oracle(lhs, flags):
         full = oracle.reach(m, cap=50_001)
         cap = 50_000 if full.capped else (int(rng.integers(1, full.total + 1)) if rng.random() < 0.3 else 0)
         caps.append(cap)
-        wants.append(oracle.reach(m, cap=cap))
+        wants.append(oracle.reach(m, cap=cap, keep_states=True))
     print(f"\n[batch] 24 mixed models flags={flags}", flush=True)
     tables = [lhs.Table(1 << 17, m.W) for m in models]
     try:
@@ -57,6 +58,7 @@ def test_batch_small_vs_oracle(lhs, flags):
         for m, g, w, t in zip(models, got, wants, tables):
             assert result_fields(g) == result_fields(w), m.describe()
             rows, _ = t.dump()
+            assert_same_set(rows, w.states, m.describe())
             assert oracle.digest(rows) == w.digest, m.describe()
     finally:
         for t in tables:
@@ -101,6 +103,8 @@ def test_batch_mix_64_vs_oracle(lhs):
             rows, _ = t.dump()
             d = oracle.digest(rows)
             assert [d[0], hex(d[1]), hex(d[2])] == want["digest"], m.name
+            # every model has at most 10^6 states: compare the sets row by row
+            assert_same_set(rows, oracle.reach(m, keep_states=True).states, m.name)
     finally:
         for t in tables:
             t.close()

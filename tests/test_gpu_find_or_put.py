@@ -50,8 +50,10 @@ def test_stream_parity(lhs, W, batch, tps):
         check_stream_batches(o_id, distinct, seen, idx, bounds)
         assert t.count() == distinct
         got, _ = check_table_invariants(t)
-    assert oracle.digest(got) == oracle.digest(rows[np.unique(o_id)]) or \
-        oracle.digest(got) == oracle.digest(np.unique(stream, axis=0))
+    # the stored set is the stream's distinct rows: row by row, then by digest
+    want = np.unique(stream, axis=0)
+    assert np.array_equal(np.unique(got, axis=0), want)
+    assert oracle.digest(got) == oracle.digest(want)
 
 
 @pytest.mark.parametrize("tps", TPS)

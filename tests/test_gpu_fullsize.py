@@ -10,7 +10,8 @@
   oracle's recorded run (tests/golden/wide_model.json) and set digest.
 * the raw stream: 2^26 rows of 16 words (2^25 distinct, each twice) into a
   2^28-slot table, as one call and as 2^22-row calls, against the sequential
-  oracle run on the same stream.
+  oracle run on the same stream, and the stored rows against the stream row
+  by row.
 Both run with the package's tuning table loaded (the shapes the benchmark
 times) and with the default shape.
 """
@@ -95,7 +96,18 @@ def test_stream_2p26(lhs, full_stream, shape, batch):
             bounds.append((lo, hi))
         t.check()
         assert t.count() == distinct
-    check_stream_batches(o_id, distinct, seen.cpu().numpy(), idx.cpu().numpy().view(np.uint32), bounds)
+        idx_h = idx.cpu().numpy().view(np.uint32)
+        check_stream_batches(o_id, distinct, seen.cpu().numpy(), idx_h, bounds)
+        # the stored set, row by row: every operation's row is the one stored
+        # at its index; with the index classes checked above and the count,
+        # the table holds exactly the stream's distinct rows
+        rows, slots = t.dump()
+        assert np.all(np.diff(slots.astype(np.int64)) > 0)
+        for lo in range(0, n, 1 << 22):
+            hi = min(n, lo + (1 << 22))
+            pos = np.searchsorted(slots, idx_h[lo:hi])
+            assert np.array_equal(slots[pos], idx_h[lo:hi])
+            assert np.array_equal(rows[pos], stream[lo:hi]), f"stored row differs in [{lo}, {hi})"
 
 
 @pytest.mark.parametrize("shape", ["tuned", "default"])

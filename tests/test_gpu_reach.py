@@ -8,7 +8,7 @@ import oracle
 from oracle.closed_form import cyclic_summary
 
 from conftest import load_golden, model_from_fixture, result_fields
-from gpu_util import check_table_invariants
+from gpu_util import assert_same_set, check_table_invariants
 
 pytestmark = pytest.mark.gpu
 
@@ -38,11 +38,12 @@ def _gpu(lhs, m, cap=None, capacity=None, tps=0):
 
 
 def _compare(lhs, m, cap=None, capacity=None, tps=0):
-    want = oracle.reach(m, cap=cap)
+    want = oracle.reach(m, cap=cap, keep_states=True)
     if capacity is None:
         capacity = _capacity_for(max(want.total, cap or 0))
     got, rows = _gpu(lhs, m, cap, capacity, tps)
     assert result_fields(got) == result_fields(want), m.describe()
+    assert_same_set(rows, want.states, m.describe())
     assert oracle.digest(rows) == want.digest
     return got
 
@@ -61,8 +62,9 @@ def test_golden(lhs, fx):
         print(f"\n[reach] {fx['name']} cap={case['cap']}", flush=True)
         want = {k: case[k] for k in ("total", "level_counts", "edges", "deadlocks", "capped")}
         want["n_levels"] = len(case["level_counts"])
-        got, _ = _gpu(lhs, m, cap=case["cap"], capacity=1 << 12)
+        got, rows = _gpu(lhs, m, cap=case["cap"], capacity=1 << 12)
         assert result_fields(got) == want
+        assert_same_set(rows, oracle.reach(m, cap=case["cap"], keep_states=True).states, fx["name"])
 
 
 def _random_models(n, seed):
