@@ -35,7 +35,8 @@ typedef enum lhs_status {
     LHS_EFULL = 3,    /* a find-or-put probed every line without a free slot   */
     LHS_ESTALL = 4,   /* a wait on a slot being written exceeded its bound     */
     LHS_EDEVICE = 5,  /* a HIP runtime call failed                             */
-    LHS_EBUDGET = 6,  /* a request does not fit the server's memory budget     */
+    LHS_EBUDGET = 6,  /* a request does not fit a memory budget (the server's,
+                         or the fixed array of reach_explore_noalloc)          */
     LHS_ENOTFOUND = 7,/* unknown ticket                                        */
     LHS_EAGAIN = 8    /* result not ready yet (non-blocking poll)              */
 } lhs_status;
@@ -341,6 +342,35 @@ lhs_status reach_explore(const reach_model *m, const reach_opts *o, reach_result
 
 /* Free what reach_explore / reach_explore_batch allocated in r. */
 void reach_result_free(reach_result *r);
+
+/* For callers that cannot allocate memory (tight serving loops, harnesses
+ * that forbid allocation after start-up): reach_explore on a caller-created
+ * table t that allocates nothing, neither device nor host memory.  The
+ * frontiers, level counters and model upload that reach_explore keeps in the
+ * table and the device workspace live instead in one fixed device array of
+ * LHS_NOALLOC_SCRATCH_BYTES per device, reserved when the library is loaded
+ * and held until the process ends.  Limits, checked before any device work:
+ * t->capacity <= LHS_NOALLOC_MAX_CAPACITY slots and n_procs * n_locals *
+ * trans_per_local <= LHS_NOALLOC_MAX_TRANS transitions, else LHS_EBUDGET.
+ *   m              : the model (as for reach_explore; its state_cap applies).
+ *   t              : the caller's table on the current device, width
+ *                    n_procs + n_shared, capacity > state_cap; cleared first,
+ *                    it keeps the result set as with reach_opts.table.
+ *   h_level_counts : host, max_levels uint64 (caller-owned): the level counts.
+ *   r              : filled as by reach_explore except level_counts = NULL
+ *                    (the counts are in h_level_counts[0, r->n_levels)); it
+ *                    owns nothing, so reach_result_free is not needed.
+ *   hip_stream     : stream for all device work.
+ * Synchronous.  Errors: LHS_EINVAL (null or mismatched arguments, another
+ * device current, more levels than max_levels), LHS_EBUDGET (limits above),
+ * LHS_EFULL / LHS_ESTALL (device), LHS_EDEVICE.  Calls are serialised inside
+ * the library: they all share the device's one array, which keeps the last
+ * call's contents (every call clears what it reads). */
+#define LHS_NOALLOC_MAX_CAPACITY (1u << 21)
+#define LHS_NOALLOC_MAX_TRANS (1u << 16)
+#define LHS_NOALLOC_SCRATCH_BYTES (18u << 20)
+lhs_status reach_explore_noalloc(const reach_model *m, lhs_table *t, uint64_t *h_level_counts,
+                                 uint32_t max_levels, reach_result *r, void *hip_stream);
 
 /* Counterexample trace (Algorithm 1's deadlock report made concrete): after
  * reach_explore with REACH_F_PARENTS on table t, the path of slots from s0 to

@@ -36,7 +36,7 @@ EXPORTS = ["lhs_strerror", "lhs_create", "lhs_create_ex", "lhs_get_config", "lhs
            "lhs_clear", "lhs_find_or_put", "lhs_set_threads_per_state", "lhs_set_counters",
            "lhs_set_workers", "lhs_tune_load", "lhs_tune_clear", "lhs_tune_lookup",
            "lhs_check", "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info",
-           "reach_explore", "reach_result_free", "reach_explore_batch", "reach_trace",
+           "reach_explore", "reach_result_free", "reach_explore_noalloc", "reach_explore_batch", "reach_trace",
            "reach_deadlock_slots",
            "reach_server_clock", "reach_server_create", "reach_server_submit", "reach_server_submit_ex",
            "reach_server_poll",
@@ -158,6 +158,8 @@ def lib() -> ctypes.CDLL:
         L.reach_explore.argtypes = [ctypes.POINTER(ReachModel), ctypes.POINTER(ReachOpts),
                                     ctypes.POINTER(ReachResultC)]
         L.reach_result_free.argtypes = [ctypes.POINTER(ReachResultC)]
+        L.reach_explore_noalloc.argtypes = [ctypes.POINTER(ReachModel), p, p, u32,
+                                            ctypes.POINTER(ReachResultC), p]
         L.reach_trace.argtypes = [p, u32, p, p, u32, ctypes.POINTER(u32)]
         L.reach_deadlock_slots.argtypes = [p, p, u32, ctypes.POINTER(u32)]
         L.reach_explore_batch.argtypes = [ctypes.POINTER(ctypes.POINTER(ReachModel)), u32,
@@ -183,6 +185,7 @@ def lib() -> ctypes.CDLL:
                      "lhs_get_config",
                      "lhs_tune_load", "lhs_tune_clear", "lhs_tune_lookup",
                      "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info", "reach_explore",
+                     "reach_explore_noalloc",
                      "reach_explore_batch", "reach_trace", "reach_deadlock_slots",
                      "reach_server_create", "reach_server_submit", "reach_server_submit_ex",
                      "reach_server_poll", "reach_server_wait", "reach_server_get_stats",
@@ -456,6 +459,27 @@ def reach_explore(model, cap: int | None = None, capacity: int = 0, table: Table
     finally:
         lib().reach_result_free(ctypes.byref(r))
         del keep
+
+
+#: limits of reach_explore_noalloc (include/lhs.h)
+NOALLOC_MAX_CAPACITY = 1 << 21
+NOALLOC_MAX_TRANS = 1 << 16
+
+
+def reach_explore_noalloc(model, table: Table, cap: int | None = None, max_levels: int = 1 << 16,
+                          stream=None) -> ReachResult:
+    """reach_explore on ``table`` through the entry point that allocates
+    nothing (reach_explore_noalloc); the level counts land in a host array
+    this binding passes in."""
+    m, keep = _model_struct(model, cap)
+    levels = np.zeros(max_levels, dtype=np.uint64)
+    r = ReachResultC()
+    _check(lib().reach_explore_noalloc(ctypes.byref(m), table.handle, _ptr(levels), max_levels,
+                                       ctypes.byref(r), _stream_handle(stream)), "reach_explore_noalloc")
+    del keep
+    return ReachResult(total=r.total_states, n_levels=r.n_levels,
+                       level_counts=[int(x) for x in levels[: r.n_levels]], edges=r.edges,
+                       deadlocks=r.deadlocks, capped=bool(r.capped), wait_hits=r.wait_hits, gpu_ms=r.gpu_ms)
 
 
 class Server:

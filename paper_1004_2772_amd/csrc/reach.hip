@@ -2,8 +2,10 @@
 // one model: one launch of k_expand per level (tile body in expand_device.h),
 // the host reading the level's counters after each launch.
 #include <algorithm>
+#include <chrono>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -132,6 +134,44 @@ __global__ void k_zero_level(LevelCounters *lc) {
     lc->abort = 0;
     lc->edges = 0;
     lc->deadlocks = 0;
+}
+
+// ---- exploration without allocation (reach_explore_noalloc) ---------------
+// Everything the level loop needs besides the caller's table lives in one
+// file-scope device array, `scratch`, of a fixed size: the two frontiers of a
+// table of at most LHS_NOALLOC_MAX_CAPACITY slots, the level counters, the
+// root's seen byte, the initial state, and the model's transitions (as
+// given, and packed by k_pack_trans).  Each device holds its own copy from
+// module load until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returned on that device.
+constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t kNaFront0 = 0;
+constexpr size_t kNaFront1 = kNaFront0 + LHS_NOALLOC_MAX_CAPACITY * sizeof(uint32_t);
+constexpr size_t kNaLevel = kNaFront1 + LHS_NOALLOC_MAX_CAPACITY * sizeof(uint32_t);
+constexpr size_t kNaSeen = kNaLevel + align256(sizeof(LevelCounters));
+constexpr size_t kNaInit = kNaSeen + 256;
+constexpr size_t kNaRaw = kNaInit + align256(32 * sizeof(uint32_t));
+constexpr size_t kNaPacked = kNaRaw + align256(LHS_NOALLOC_MAX_TRANS * sizeof(reach_trans));
+constexpr size_t kNaBytes = kNaPacked + LHS_NOALLOC_MAX_TRANS * sizeof(uint2);
+static_assert(kNaBytes <= LHS_NOALLOC_SCRATCH_BYTES, "the header states the scratch size");
+static_assert(sizeof(reach_trans) == 5 * sizeof(uint32_t), "transitions are five words");
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mu;                    // serialises the calls (one scratch per device)
+void *g_na_ptr[kNaMaxDevices] = {};    // device address of `scratch`, per device
+
+// The host-side packing of the transition table (pack_model), on the
+// device: x = target | guard_var << 16 | eff_var << 24 (0xFF = none),
+// y = guard_val | eff_val << 16 (0 where the variable is none).
+__global__ void k_pack_trans(const uint32_t *raw, uint2 *out, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t *t = raw + 5ull * i;
+        const bool g = t[1] != REACH_NONE, e = t[3] != REACH_NONE;
+        out[i] = make_uint2(t[0] | ((g ? t[1] : 0xFFu) << 16) | ((e ? t[3] : 0xFFu) << 24),
+                            (g ? t[2] : 0u) | ((e ? t[4] : 0u) << 16));
+    }
 }
 
 }  // namespace
@@ -618,6 +658,109 @@ lhs_status reach_deadlock_slots(lhs_table *t, uint32_t *h_slots, uint32_t max, u
     if (h_slots && k)
         LHS_HIP(hipMemcpy(h_slots, t->dead_rec + 1, k * sizeof(uint32_t), hipMemcpyDeviceToHost));
     return LHS_OK;
+}
+
+static lhs_status reach_explore_noalloc_impl(const reach_model *m, lhs_table *t, uint64_t *h_level_counts,
+                                             uint32_t max_levels, reach_result *r, void *hip_stream) {
+    if (!r)
+        return LHS_EINVAL;
+    std::memset(r, 0, sizeof(*r));
+    if (!t || !h_level_counts || max_levels == 0 || validate_model(m) != LHS_OK)
+        return LHS_EINVAL;
+    const uint32_t W = m->n_procs + m->n_shared;
+    const uint64_t n_trans = (uint64_t)m->n_procs * m->n_locals * m->trans_per_local;
+    if (t->W != W || (m->state_cap && m->state_cap >= t->capacity))
+        return LHS_EINVAL;
+    if (t->capacity > LHS_NOALLOC_MAX_CAPACITY || n_trans > LHS_NOALLOC_MAX_TRANS)
+        return LHS_EBUDGET;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return LHS_EDEVICE;
+    if (dev != t->device || dev < 0 || dev >= kNaMaxDevices)
+        return LHS_EINVAL;
+    std::lock_guard<std::mutex> lock(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return LHS_EDEVICE;
+        g_na_ptr[dev] = p;
+    }
+    char *base = static_cast<char *>(g_na_ptr[dev]);
+    uint32_t *fr[2] = {reinterpret_cast<uint32_t *>(base + kNaFront0), reinterpret_cast<uint32_t *>(base + kNaFront1)};
+    LevelCounters *lc = reinterpret_cast<LevelCounters *>(base + kNaLevel);
+    uint8_t *seen = reinterpret_cast<uint8_t *>(base + kNaSeen);
+    uint32_t *d_init = reinterpret_cast<uint32_t *>(base + kNaInit);
+    uint32_t *raw = reinterpret_cast<uint32_t *>(base + kNaRaw);
+    uint2 *d_trans = reinterpret_cast<uint2 *>(base + kNaPacked);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const auto t0 = std::chrono::steady_clock::now();
+
+    // model and initial state, then level 0
+    LHS_HIP(hipMemcpyAsync(raw, m->trans, n_trans * sizeof(reach_trans), hipMemcpyHostToDevice, s));
+    LHS_HIP(hipMemcpyAsync(d_init, m->init, W * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_pack_trans, dim3((uint32_t)std::min<uint64_t>((n_trans + 255) / 256, 256)), dim3(256),
+                       0, s, raw, d_trans, (uint32_t)n_trans);
+    LHS_HIP(hipGetLastError());
+    t->last_stream = s;
+    lhs_status rc = lhs_clear(t, s);
+    if (rc != LHS_OK)
+        return rc;
+    if ((rc = launch_find_or_put(t, d_init, 1, seen, fr[0], s)) != LHS_OK)
+        return rc;
+    const ModelView mv = model_view(m, d_trans);
+    const TableView tv = bfs_view(t, false);
+    h_level_counts[0] = 1;
+    uint32_t n_levels = 1, n_cur = 1, cur = 0;
+    uint64_t total = 1, edges = 0, dead = 0;
+    int capped = 0;
+    LevelCounters h_lc{};
+    DevStatus h_st{};
+    while (true) {
+        const uint32_t limit =
+            m->state_cap ? (uint32_t)std::min<uint64_t>(m->state_cap - total, 0xFFFFFFFFull) : 0xFFFFFFFFu;
+        hipLaunchKernelGGL(k_zero_level, dim3(1), dim3(1), 0, s, lc);
+        if ((rc = launch_expand(t, tv, mv, fr[cur], n_cur, fr[cur ^ 1], lc, limit, s)) != LHS_OK)
+            return rc;
+        LHS_HIP(hipMemcpyAsync(&h_lc, lc, sizeof(h_lc), hipMemcpyDeviceToHost, s));
+        LHS_HIP(hipMemcpyAsync(&h_st, t->status, sizeof(h_st), hipMemcpyDeviceToHost, s));
+        LHS_HIP(hipStreamSynchronize(s));
+        if (h_st.error)
+            return (lhs_status)h_st.error;
+        if (m->state_cap && h_lc.n_next > limit) {
+            // discard the level: zero the slots it claimed
+            hipLaunchKernelGGL(k_rollback, dim3(std::min<uint32_t>((h_lc.n_next + 255) / 256, 4096)), dim3(256), 0,
+                               s, t->bucket, fr[cur ^ 1], h_lc.n_next);
+            LHS_HIP(hipGetLastError());
+            capped = 1;
+            break;
+        }
+        edges += h_lc.edges;
+        dead += h_lc.deadlocks;
+        if (h_lc.n_next == 0)
+            break;
+        if (n_levels == max_levels)
+            return LHS_EINVAL;   // more levels than the caller's array holds
+        h_level_counts[n_levels++] = h_lc.n_next;
+        total += h_lc.n_next;
+        n_cur = h_lc.n_next;
+        cur ^= 1;
+    }
+    LHS_HIP(hipMemcpyAsync(&h_st, t->status, sizeof(h_st), hipMemcpyDeviceToHost, s));
+    LHS_HIP(hipStreamSynchronize(s));
+    r->total_states = total;
+    r->edges = edges;
+    r->deadlocks = dead;
+    r->capped = capped;
+    r->n_levels = n_levels;
+    r->level_counts = nullptr;
+    r->wait_hits = h_st.wait_hits;
+    r->gpu_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return LHS_OK;
+}
+
+lhs_status reach_explore_noalloc(const reach_model *m, lhs_table *t, uint64_t *h_level_counts, uint32_t max_levels,
+                                 reach_result *r, void *hip_stream) {
+    return lhs::guard([&] { return reach_explore_noalloc_impl(m, t, h_level_counts, max_levels, r, hip_stream); });
 }
 
 void reach_result_free(reach_result *r) {
