@@ -5,9 +5,9 @@
 // step expands the tiles of every unfinished model in the same launch, so
 // small and large models, and models of different state widths, share the
 // GPU.  Two drivers:
-//   * persistent (default): one cooperative launch runs every level of every
-//     model from a device work queue of (model, tile) items; each model
-//     advances at its own pace, with no grid-wide barrier;
+//   * persistent (default): one launch of resident workgroups runs every
+//     level of every model from a device work queue of (model, tile) items;
+//     each model advances at its own pace, with no grid-wide barrier;
 //   * host loop (REACH_F_HOST_LOOP): all models advance together, one launch
 //     per level step covering the tiles of every unfinished model, the host
 //     reading the per-model counters after each.
@@ -42,6 +42,12 @@ constexpr uint32_t kBarrierSpinLimit = 1u << 24;   // bound on every queue wait
 // (coherent) accesses, completed (vmcnt(0)) before the item or counter that
 // announces it.  Every wait is bounded; on timeout the error flag is set and
 // all workgroups leave.
+//
+// The workgroups need not all be resident at once (the launch is a plain
+// one, sized to what fits): a workgroup only ever waits for a cell that a
+// running workgroup fills (a finaliser, which itself waits only for free
+// cells, and the ring holds one full level of every model), so one that
+// starts late takes its first item, or finds the batch finished, and leaves.
 
 struct QCell {
     unsigned long long seq;
@@ -569,7 +575,7 @@ static lhs_status reach_explore_batch_impl(const reach_model *const *models, uin
             void *args[] = {&d_ms, &d_mp, &d_lv, &d_qs, &d_ring, &tcap};
             (void)hipEventRecord(ws.ev[0], s);
             if (hipGetLastError() != hipSuccess ||
-                hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kExpandBlock), args, lds, s) != hipSuccess)
+                hipLaunchKernel(fn, dim3(grid), dim3(kExpandBlock), args, lds, s) != hipSuccess)
                 rc = LHS_EDEVICE;
             (void)hipEventRecord(ws.ev[1], s);
             if (rc == LHS_OK) {
