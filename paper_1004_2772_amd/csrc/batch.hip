@@ -249,6 +249,10 @@ __global__ __launch_bounds__(kExpandBlock) void k_batch_persistent(const ModelSt
             if (!ex) {
                 s_model = ld_coherent(&c->model);
                 s_tile = ld_coherent(&c->tile);
+                // the item is read before the cell is freed: the store must
+                // not be performed ahead of the loads (different addresses),
+                // or the next producer could overwrite the item first
+                wait_vm_complete();
                 st_coherent(&c->seq, pos + qs->mask + 1ull);   // free for position pos + R
             }
             s_exit = ex;

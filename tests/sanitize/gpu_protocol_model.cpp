@@ -1,0 +1,620 @@
+// CPU-thread model of the GPU kernels' synchronisation protocols, for
+// ThreadSanitizer.  It plays the part that a model checker plays for the
+// paper's Algorithm 3 (section "Algorithm": the authors checked the
+// find-or-put algorithm with a model of it): threads stand for lanes and
+// workgroups, and TSan checks that every access to shared payload is ordered
+// by the protocol's announcements.
+//
+// Mapping from the kernels (csrc/lhs_device.h, expand_device.h, batch.hip):
+//  * Payload -- vector rows, frontier entries, a level's state, the (model,
+//    tile) of a ring cell, per-model progress -- is plain memory here, so
+//    that TSan reports any access pair the protocol leaves unordered.
+//  * Slot words, counters, ring sequence numbers and the tile count are
+//    std::atomic.  A kernel access that is relaxed and unordered stays
+//    relaxed.  Where the kernel waits for its earlier accesses to complete
+//    (s_waitcnt vmcnt(0)) before an announcing store or atomic, the model
+//    uses release.  Where the kernel issues its next accesses only after an
+//    observed value returned (the value decides what it does next), the
+//    model uses acquire.
+//
+// Part 1, find-or-put: slot = 0 (empty) -> OCC|memo (claimed, CAS) ->
+// OCC|DONE|memo (published).  The CAS winner writes the row and only then
+// publishes; a reader compares a row only after observing DONE, from the
+// line snapshot, from a failed CAS, or by a bounded wait.  Lines are walked
+// from the home slot and left by double hashing, as in the kernels.
+//
+// Part 2, the persistent batch: workers take (model, tile) items from a
+// bounded ring of sequence-numbered cells; the worker that completes a
+// level's last tile finalises it (rollback of a capped level, level count,
+// frontier swap, next level's state), keeps tile 0 of the next level and
+// enqueues the others.  Models are N independent cyclic L-state processes;
+// results are checked against a sequential BFS.
+//
+// Planted mistakes (compile with -DPLANT=n) remove one ordering each; the
+// test expects TSan (or a result check) to catch every one:
+//   1 publish DONE before writing the row      2 publish DONE relaxed
+//   3 compare a matching row without DONE      4 free a ring cell relaxed
+//   5 count a finished tile relaxed
+#include <algorithm>
+#include <atomic>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <set>
+#include <thread>
+#include <vector>
+
+#ifndef PLANT
+#define PLANT 0
+#endif
+
+namespace {
+
+constexpr uint64_t kOcc = 1ull << 63, kDone = 1ull << 62, kMemo = kDone - 1;
+constexpr uint32_t kSpin = 1u << 26;
+enum Code { kNew, kSeen, kFull, kStall };
+
+uint64_t mix64(uint64_t z) {   // SplitMix64 finaliser (Steele, Lea, Flood 2014)
+    z ^= z >> 30;
+    z *= 0xbf58476d1ce4e5b9ull;
+    z ^= z >> 27;
+    z *= 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+uint64_t hash_row(const uint32_t *v, uint32_t W) {
+    uint64_t h = 0x243f6a8885a308d3ull;
+    for (uint32_t i = 0; i < W; ++i)
+        h = mix64(h ^ v[i]);
+    return h;
+}
+
+struct Table {
+    uint32_t W, LS, lines;
+    std::unique_ptr<std::atomic<uint64_t>[]> slot;
+    std::vector<uint32_t> data;   // payload: rows, plain memory
+    std::atomic<uint64_t> waits{0}, cas_fail{0};
+    Table(uint32_t W_, uint32_t LS_, uint32_t cap) : W(W_), LS(LS_), lines(cap / LS_),
+                                                     slot(new std::atomic<uint64_t>[cap]), data((size_t)cap * W_) {
+        for (uint32_t i = 0; i < cap; ++i)
+            slot[i].store(0, std::memory_order_relaxed);
+    }
+    uint32_t capacity() const { return lines * LS; }
+};
+
+bool row_equals(const Table &t, uint32_t s, const uint32_t *v) {
+    return std::memcmp(&t.data[(size_t)s * t.W], v, t.W * 4u) == 0;   // plain reads of the row
+}
+
+// Algorithm 3 with walking the line; returns kNew / kSeen / kFull / kStall.
+Code find_or_put(Table &t, const uint32_t *v, uint32_t &out) {
+    const uint64_t h = hash_row(v, t.W);
+    const uint64_t memo = kOcc | (h & kMemo);
+    const uint32_t start = (uint32_t)h & (t.LS - 1);
+    const uint32_t step = (uint32_t)(h >> 32) | 1u;
+    uint32_t line = (uint32_t)(h >> 8) & (t.lines - 1);
+    std::vector<uint64_t> snap(t.LS);
+    for (uint32_t round = 0; round < t.lines; ++round, line = (line + step) & (t.lines - 1)) {
+        // the line snapshot (the kernel compares rows of slots seen DONE
+        // here without reading their slot again)
+        for (uint32_t i = 0; i < t.LS; ++i)
+            snap[i] = t.slot[line * t.LS + i].load(std::memory_order_acquire);
+        for (uint32_t k = 0; k < t.LS; ++k) {
+            const uint32_t s = line * t.LS + ((start + k) & (t.LS - 1));
+            uint64_t cur = snap[(start + k) & (t.LS - 1)];
+            if (cur == 0) {
+                // claim: a CAS whose returned value the lane tests before
+                // its next access (acquire; a failure may return DONE, and
+                // the row is then compared at once).  C++ wants the success
+                // order at least as strong as the failure order.
+                uint64_t old = 0;
+                if (t.slot[s].compare_exchange_strong(old, memo, std::memory_order_acquire,
+                                                      std::memory_order_acquire)) {
+                    // (the yield widens the write-busy window, as the GPU's
+                    // row store and its completion wait do)
+#if PLANT == 1
+                    t.slot[s].store(memo | kDone, std::memory_order_release);
+                    std::this_thread::yield();
+                    std::memcpy(&t.data[(size_t)s * t.W], v, t.W * 4u);
+#elif PLANT == 2
+                    std::memcpy(&t.data[(size_t)s * t.W], v, t.W * 4u);
+                    std::this_thread::yield();
+                    t.slot[s].store(memo | kDone, std::memory_order_relaxed);
+#else
+                    // row stores, completed (vmcnt(0)) before the DONE store
+                    std::memcpy(&t.data[(size_t)s * t.W], v, t.W * 4u);
+                    std::this_thread::yield();
+                    t.slot[s].store(memo | kDone, std::memory_order_release);
+#endif
+                    out = s;
+                    return kNew;
+                }
+                t.cas_fail.fetch_add(1, std::memory_order_relaxed);
+                cur = old;
+            }
+            if ((cur & ~kDone) != memo)
+                continue;   // claimed with another memo: immutable, skip
+#if PLANT != 3
+            if (!(cur & kDone)) {
+                // the writer's bounded wait (write-busy "lock")
+                t.waits.fetch_add(1, std::memory_order_relaxed);
+                uint32_t spins = 0;
+                while (!((cur = t.slot[s].load(std::memory_order_acquire)) & kDone))
+                    if (++spins > kSpin)
+                        return kStall;
+                    else
+                        std::this_thread::yield();
+            }
+#endif
+            if (row_equals(t, s, v)) {
+                out = s;
+                return kSeen;
+            }
+        }
+    }
+    return kFull;
+}
+
+// ---------------------------------------------------------------- part 1 ---
+int part1() {
+    // W = 5 rows from a small alphabet: many equal vectors, a small table
+    // with 8-slot lines filled to 3/4 so that probes leave their home line
+    const uint32_t W = 5, cap = 1u << 12, pool = 3000, threads = 8, ops = 6000;
+    Table t(W, 8, cap);
+    std::vector<uint32_t> rows((size_t)pool * W);
+    uint64_t x = 0x9E3779B97F4A7C15ull;
+    for (uint32_t i = 0; i < pool; ++i) {
+        rows[(size_t)i * W] = i;
+        for (uint32_t j = 1; j < W; ++j)
+            rows[(size_t)i * W + j] = (uint32_t)((x = mix64(x + i * 31 + j)) % 3);
+    }
+    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> res(threads);   // (row, slot) of new/seen
+    std::vector<std::vector<uint8_t>> isnew(threads);
+    std::vector<std::thread> th;
+    std::atomic<int> bad{0};
+    // every thread walks the pool in the same order from a nearby start, so
+    // equal vectors are inserted by several threads at about the same time
+    for (uint32_t w = 0; w < threads; ++w)
+        th.emplace_back([&, w] {
+            for (uint32_t k = 0; k < ops; ++k) {
+                const uint32_t r = (k + 3 * w) % pool;
+                uint32_t s = ~0u;
+                const Code c = find_or_put(t, &rows[(size_t)r * W], s);
+                if (c != kNew && c != kSeen)
+                    bad.fetch_add(1);
+                res[w].push_back({r, s});
+                isnew[w].push_back(c == kNew);
+            }
+        });
+    for (auto &h : th)
+        h.join();
+    // every value stored once: one "new" per distinct row, one slot per row,
+    // distinct rows in distinct slots, and each slot holds its row
+    std::map<uint32_t, uint32_t> slot_of, news;
+    std::set<uint32_t> used;
+    for (uint32_t w = 0; w < threads; ++w)
+        for (size_t k = 0; k < res[w].size(); ++k) {
+            const auto [r, s] = res[w][k];
+            auto it = slot_of.find(r);
+            if (it == slot_of.end())
+                slot_of[r] = s;
+            else if (it->second != s)
+                bad.fetch_add(1);
+            news[r] += isnew[w][k];
+        }
+    for (auto &[r, s] : slot_of) {
+        if (news[r] != 1 || !used.insert(s).second || !row_equals(t, s, &rows[(size_t)r * W]))
+            bad.fetch_add(1);
+    }
+    uint32_t done = 0;
+    for (uint32_t i = 0; i < cap; ++i) {
+        const uint64_t v = t.slot[i].load();
+        if (v && !(v & kDone))
+            bad.fetch_add(1);   // claimed but never published
+        done += (v & kDone) != 0;
+    }
+    if (done != slot_of.size())
+        bad.fetch_add(1);
+    printf("part1: %zu distinct of %u ops, %u stored, %llu waits, %llu cas failures, errors %d\n",
+           slot_of.size(), threads * ops, done, (unsigned long long)t.waits.load(),
+           (unsigned long long)t.cas_fail.load(), bad.load());
+    return bad.load();
+}
+
+// ---------------------------------------------------------------- part 2 ---
+struct Cell {
+    std::atomic<uint64_t> seq;
+    uint32_t model, tile;   // payload
+};
+
+struct LevelState {     // payload, written by the finaliser of the level before
+    uint32_t cur;       // announcing the level's tiles
+    uint32_t n_front, limit, tiles_total, tile_rows;
+    std::atomic<uint32_t> tiles_done{0};
+};
+
+struct Model {
+    uint32_t N, L;      // N independent cyclic L-state processes, W = N
+    uint64_t cap;       // level-prefix state cap (0 = none)
+    std::unique_ptr<Table> t;
+    std::vector<uint32_t> fr[2];                  // payload
+    std::atomic<uint32_t> n_next{0}, abort{0};
+    std::atomic<uint64_t> edges{0}, dead{0};
+    LevelState lv;
+    // progress (payload; only finalisers touch it, one level after another)
+    uint64_t total = 1, p_edges = 0, p_dead = 0;
+    std::vector<uint64_t> levels{1};
+    bool capped = false;
+};
+
+struct Queue {
+    std::atomic<uint64_t> head{0}, tail{0};
+    std::atomic<uint32_t> remaining{0}, error{0};
+    uint64_t mask = 0;
+    std::unique_ptr<Cell[]> ring;
+};
+
+constexpr uint32_t kTileRows = 8;
+
+// Fill ring position pos (reserved on the tail): wait for its cell to be
+// free, write the item, publish it.  False if the wait ran out.
+bool ring_put(Queue &q, uint64_t pos, uint32_t model, uint32_t tile) {
+    Cell &c = q.ring[pos & q.mask];
+    uint32_t spins = 0;
+    while (c.seq.load(std::memory_order_acquire) != pos) {
+        if (++spins > kSpin)
+            return false;
+        std::this_thread::yield();
+    }
+    c.model = model;
+    c.tile = tile;
+    c.seq.store(pos + 1, std::memory_order_release);   // after vmcnt(0)
+    return true;
+}
+
+// Take ring position pos (reserved on the head): wait for its cell to be
+// filled, read the item, free the cell for position pos + ring size.  False
+// if give_up() said so, or the wait ran out (then *timed_out).
+template <class GiveUp>
+bool ring_take(Queue &q, uint64_t pos, uint32_t &model, uint32_t &tile, GiveUp give_up, bool &timed_out) {
+    Cell &c = q.ring[pos & q.mask];
+    uint32_t spins = 0;
+    timed_out = false;
+    while (c.seq.load(std::memory_order_acquire) != pos + 1) {
+        if (give_up())
+            return false;
+        if (++spins > kSpin) {
+            timed_out = true;
+            return false;
+        }
+        std::this_thread::yield();
+    }
+    model = c.model;
+    tile = c.tile;
+#if PLANT == 4
+    c.seq.store(pos + q.mask + 1, std::memory_order_relaxed);
+#else
+    // the item was read (vmcnt(0)) before the cell is freed
+    c.seq.store(pos + q.mask + 1, std::memory_order_release);
+#endif
+    return true;
+}
+
+// Expand tile `j` of model m's current level; new states to next[].
+void expand_tile(Model &m, uint32_t j, Queue &q) {
+    const LevelState &L = m.lv;
+    const uint32_t cur = L.cur, n_front = L.n_front, limit = L.limit, rows_per = L.tile_rows;
+    const uint32_t base = j * rows_per, rows = std::min(rows_per, n_front - base);
+    const uint32_t W = m.N;
+    std::vector<uint32_t> fresh, s(W);
+    uint64_t edges = 0, dead = 0;
+    for (uint32_t i = 0; i < rows; ++i) {
+        if (m.abort.load(std::memory_order_relaxed))
+            break;
+        const uint32_t slot = m.fr[cur][base + i];                    // frontier entry (payload)
+        std::memcpy(s.data(), &m.t->data[(size_t)slot * W], W * 4u);  // row of an earlier level
+        uint32_t n = 0;
+        for (uint32_t p = 0; p < m.N; ++p) {
+            std::vector<uint32_t> v = s;
+            v[p] = (v[p] + 1) % m.L;
+            uint32_t at = 0;
+            const Code c = find_or_put(*m.t, v.data(), at);
+            if (c == kNew)
+                fresh.push_back(at);
+            else if (c != kSeen)
+                q.error.store(1, std::memory_order_relaxed);
+            ++n;
+        }
+        edges += n;
+        dead += n == 0;
+    }
+    // append: one reservation on the level's cursor, then the entries; the
+    // level aborts once the cursor passes its limit
+    if (!fresh.empty()) {
+        const uint32_t b = m.n_next.fetch_add((uint32_t)fresh.size(), std::memory_order_relaxed);
+        if ((uint64_t)b + fresh.size() > limit)
+            m.abort.store(1, std::memory_order_relaxed);
+        std::copy(fresh.begin(), fresh.end(), m.fr[cur ^ 1u].begin() + b);
+    }
+    m.edges.fetch_add(edges, std::memory_order_relaxed);
+    m.dead.fetch_add(dead, std::memory_order_relaxed);
+}
+
+// Finalise model i's level (its last tile is done).  Returns true when the
+// model has a next level, whose tile 0 the caller then expands.
+bool finalize(std::vector<Model> &ms, uint32_t i, Queue &q) {
+    Model &m = ms[i];
+    LevelState &L = m.lv;
+    const uint32_t n_next = m.n_next.load(std::memory_order_relaxed);
+    bool done = false;
+    uint32_t nt = 0;
+    if (m.cap && n_next > L.limit) {
+        for (uint32_t k = 0; k < n_next; ++k)   // discard the level: free its claims
+            m.t->slot[m.fr[L.cur ^ 1u][k]].store(0, std::memory_order_relaxed);
+        m.capped = true;
+        done = true;
+    } else {
+        m.p_edges += m.edges.load(std::memory_order_relaxed);
+        m.p_dead += m.dead.load(std::memory_order_relaxed);
+        if (n_next == 0) {
+            done = true;
+        } else {
+            m.levels.push_back(n_next);
+            m.total += n_next;
+            nt = (n_next + kTileRows - 1) / kTileRows;
+            L.cur ^= 1u;
+            L.n_front = n_next;
+            L.limit = m.cap ? (uint32_t)std::min<uint64_t>(m.cap - m.total, 0xFFFFFFFFu) : 0xFFFFFFFFu;
+            L.tiles_total = nt;
+            L.tile_rows = kTileRows;
+            L.tiles_done.store(0, std::memory_order_relaxed);
+        }
+    }
+    m.n_next.store(0, std::memory_order_relaxed);
+    m.abort.store(0, std::memory_order_relaxed);
+    m.edges.store(0, std::memory_order_relaxed);
+    m.dead.store(0, std::memory_order_relaxed);
+    if (done) {
+        q.remaining.fetch_sub(1, std::memory_order_release);
+        return false;
+    }
+    if (nt > 1) {
+        // enqueue tiles 1..: wait for each cell to be free, fill, publish
+        const uint64_t pos0 = q.tail.fetch_add(nt - 1, std::memory_order_relaxed);
+        for (uint32_t k = 1; k < nt; ++k)
+            if (!ring_put(q, pos0 + k - 1, i, k)) {
+                q.error.store(2, std::memory_order_relaxed);
+                return false;
+            }
+    }
+    return true;
+}
+
+void worker(std::vector<Model> &ms, Queue &q) {
+    bool kept = false;
+    uint32_t mi = 0, tile = 0;
+    while (true) {
+        if (kept) {
+            tile = 0;
+        } else {
+            const uint64_t pos = q.head.fetch_add(1, std::memory_order_relaxed);
+            bool timed_out = false;
+            const bool got = ring_take(
+                q, pos, mi, tile,
+                [&] {
+                    return q.remaining.load(std::memory_order_relaxed) == 0 ||
+                           q.error.load(std::memory_order_relaxed) != 0;
+                },
+                timed_out);
+            if (timed_out)
+                q.error.store(3, std::memory_order_relaxed);
+            if (!got)
+                return;
+        }
+        Model &m = ms[mi];
+        expand_tile(m, tile, q);
+        // the tile's stores completed (vmcnt(0)), and the level's tile count
+        // read, before the tile is counted as done
+        const uint32_t total = m.lv.tiles_total;
+#if PLANT == 5
+        const uint32_t done = m.lv.tiles_done.fetch_add(1, std::memory_order_relaxed) + 1;
+#else
+        const uint32_t done = m.lv.tiles_done.fetch_add(1, std::memory_order_acq_rel) + 1;
+#endif
+        kept = done == total && finalize(ms, mi, q);
+    }
+}
+
+// Sequential BFS of a cyclic model with the same level-prefix cap.
+void bfs(uint32_t N, uint32_t L, uint64_t cap, std::vector<uint64_t> &levels, uint64_t &edges, bool &capped,
+         std::set<std::vector<uint32_t>> &seen) {
+    std::vector<std::vector<uint32_t>> cur{std::vector<uint32_t>(N, 0)};
+    seen = {cur[0]};
+    levels = {1};
+    edges = 0;
+    capped = false;
+    while (true) {
+        std::vector<std::vector<uint32_t>> next;
+        for (auto &s : cur)
+            for (uint32_t p = 0; p < N; ++p) {
+                auto v = s;
+                v[p] = (v[p] + 1) % L;
+                if (seen.insert(v).second)
+                    next.push_back(v);
+            }
+        if (cap && seen.size() > cap) {
+            for (auto &v : next)
+                seen.erase(v);
+            capped = true;
+            return;
+        }
+        edges += cur.size() * N;
+        if (next.empty())
+            return;
+        levels.push_back(next.size());
+        cur.swap(next);
+    }
+}
+
+int part2() {
+    // (N, L, cap): widths 2..6, some capped in the middle of a level
+    const uint32_t spec[][3] = {{2, 9, 0},  {3, 7, 0},   {4, 5, 0},  {5, 4, 0},    {6, 3, 0},   {3, 12, 500},
+                                {4, 6, 700}, {5, 5, 1000}, {2, 30, 0}, {6, 4, 2000}, {4, 7, 0}, {3, 3, 0}};
+    const uint32_t n_models = sizeof(spec) / sizeof(spec[0]);
+    std::vector<Model> ms(n_models);
+    // expected results first; the ring holds one full level of every model
+    // (as the kernel's does), so its cells are reused many times over
+    std::vector<std::vector<uint64_t>> w_levels(n_models);
+    std::vector<uint64_t> w_edges(n_models);
+    std::vector<bool> w_capped(n_models);
+    std::vector<std::set<std::vector<uint32_t>>> w_set(n_models);
+    uint64_t pending = n_models;
+    for (uint32_t i = 0; i < n_models; ++i) {
+        bool c = false;
+        bfs(spec[i][0], spec[i][1], spec[i][2], w_levels[i], w_edges[i], c, w_set[i]);
+        w_capped[i] = c;
+        // only kept levels are ever enqueued (a discarded one is not expanded)
+        const uint64_t widest = *std::max_element(w_levels[i].begin(), w_levels[i].end());
+        pending += (widest + kTileRows - 1) / kTileRows + 1;
+    }
+    for (uint32_t i = 0; i < n_models; ++i) {
+        Model &m = ms[i];
+        m.N = spec[i][0];
+        m.L = spec[i][1];
+        m.cap = spec[i][2];
+        uint64_t states = 1;
+        for (uint32_t p = 0; p < m.N; ++p)
+            states *= m.L;
+        uint32_t cap = 64;
+        while (cap < 2 * states + 64)
+            cap <<= 1;
+        m.t.reset(new Table(m.N, 8, cap));
+        m.fr[0].assign(cap, 0);
+        m.fr[1].assign(cap, 0);
+        // level 0: insert s0 (before the workers start)
+        std::vector<uint32_t> s0(m.N, 0);
+        uint32_t at = 0;
+        if (find_or_put(*m.t, s0.data(), at) != kNew)
+            return 1;
+        m.fr[0][0] = at;
+        m.lv.cur = 0;
+        m.lv.n_front = 1;
+        m.lv.limit = m.cap ? (uint32_t)(m.cap - 1) : 0xFFFFFFFFu;
+        m.lv.tiles_total = 1;
+        m.lv.tile_rows = kTileRows;
+    }
+    Queue q;
+    uint64_t cells = 16;
+    while (cells < pending)
+        cells <<= 1;
+    q.mask = cells - 1;
+    q.ring.reset(new Cell[cells]);
+    for (uint64_t p = 0; p < cells; ++p) {
+        // positions 0..n-1 hold tile 0 of every model's level 0
+        q.ring[p].seq.store(p < n_models ? p + 1 : p, std::memory_order_relaxed);
+        q.ring[p].model = p < n_models ? (uint32_t)p : 0u;
+        q.ring[p].tile = 0;
+    }
+    q.tail.store(n_models);
+    q.remaining.store(n_models);
+    std::vector<std::thread> th;
+    for (int w = 0; w < 8; ++w)
+        th.emplace_back(worker, std::ref(ms), std::ref(q));
+    for (auto &h : th)
+        h.join();
+    int bad = q.error.load() ? 1 : 0;
+    uint64_t items = 0;
+    for (uint32_t i = 0; i < n_models; ++i) {
+        Model &m = ms[i];
+        const std::vector<uint64_t> &levels = w_levels[i];
+        const uint64_t edges = w_edges[i];
+        const bool capped = w_capped[i];
+        const std::set<std::vector<uint32_t>> &want = w_set[i];
+        for (uint64_t n : m.levels)
+            items += (n + kTileRows - 1) / kTileRows;
+        std::set<std::vector<uint32_t>> got;
+        uint32_t claimed = 0;
+        for (uint32_t s = 0; s < m.t->capacity(); ++s) {
+            const uint64_t v = m.t->slot[s].load();
+            if (v & kDone)
+                got.insert(std::vector<uint32_t>(&m.t->data[(size_t)s * m.N], &m.t->data[(size_t)s * m.N] + m.N));
+            else if (v)
+                ++claimed;
+        }
+        const bool ok = levels == m.levels && edges == m.p_edges && capped == m.capped && got == want &&
+                        claimed == 0 && m.total == want.size();
+        bad += !ok;
+        printf("part2: model %u (%u x %u, cap %llu): %llu states in %zu levels, %llu edges, capped %d %s\n", i, m.N,
+               m.L, (unsigned long long)m.cap, (unsigned long long)m.total, m.levels.size(),
+               (unsigned long long)m.p_edges, (int)m.capped, ok ? "ok" : "WRONG");
+    }
+    printf("part2: %llu tiles through a ring of %llu cells\n", (unsigned long long)items,
+           (unsigned long long)cells);
+    if (items <= cells)
+        ++bad;   // the ring was never reused: the test would prove little
+    return bad;
+}
+
+// ---------------------------------------------------------------- part 3 ---
+// The ring alone, with no other synchronisation between its users: four
+// producers reserve positions on the tail and fill them, four consumers
+// reserve positions on the head and take them, through eight cells.  Every
+// item must come out exactly once and intact.
+int part3() {
+    Queue q;
+    q.mask = 7;
+    q.ring.reset(new Cell[8]);
+    for (uint64_t p = 0; p < 8; ++p) {
+        q.ring[p].seq.store(p, std::memory_order_relaxed);
+        q.ring[p].model = q.ring[p].tile = 0;
+    }
+    const uint32_t per = 4000, np = 4, nc = 4, total = per * np;
+    std::vector<std::vector<uint32_t>> got(nc);
+    std::atomic<int> bad{0};
+    std::vector<std::thread> th;
+    for (uint32_t w = 0; w < np; ++w)
+        th.emplace_back([&, w] {
+            for (uint32_t k = 0; k < per; ++k) {
+                const uint32_t id = w * per + k;
+                if (!ring_put(q, q.tail.fetch_add(1, std::memory_order_relaxed), id, id ^ 0x5A5A5A5Au))
+                    bad.fetch_add(1);
+            }
+        });
+    for (uint32_t w = 0; w < nc; ++w)
+        th.emplace_back([&, w] {
+            while (true) {
+                const uint64_t pos = q.head.fetch_add(1, std::memory_order_relaxed);
+                if (pos >= total)
+                    return;
+                uint32_t a = 0, b = 0;
+                bool timed_out = false;
+                if (!ring_take(q, pos, a, b, [] { return false; }, timed_out) || b != (a ^ 0x5A5A5A5Au))
+                    bad.fetch_add(1);
+                got[w].push_back(a);
+            }
+        });
+    for (auto &h : th)
+        h.join();
+    std::vector<uint32_t> all;
+    for (auto &g : got)
+        all.insert(all.end(), g.begin(), g.end());
+    std::sort(all.begin(), all.end());
+    for (uint32_t i = 0; i < all.size(); ++i)
+        if (all[i] != i)
+            bad.fetch_add(1);
+    if (all.size() != total)
+        bad.fetch_add(1);
+    printf("part3: %zu items through 8 cells, errors %d\n", all.size(), bad.load());
+    return bad.load();
+}
+
+}  // namespace
+
+int main() {
+    const int a = part1();
+    const int b = part2();
+    const int c = part3();
+    printf("errors %d\n", a + b + c);
+    return a + b + c ? 1 : 0;
+}

@@ -1,6 +1,8 @@
 """Host code under sanitizers (no GPU): the multi-core lockless CPU table
-under ThreadSanitizer, and the tuning-file reader under AddressSanitizer and
-UndefinedBehaviorSanitizer with mutated inputs."""
+under ThreadSanitizer, a CPU-thread model of the GPU kernels' protocols under
+ThreadSanitizer (with planted ordering mistakes it must catch), and the
+tuning-file reader under AddressSanitizer and UndefinedBehaviorSanitizer with
+mutated inputs."""
 import os
 import shutil
 import subprocess
@@ -22,6 +24,39 @@ def test_cpu_table_under_thread_sanitizer(tmp_path):
                        env=dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66"))
     assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
     assert r.returncode == 0, r.stdout + r.stderr[-2000:]
+
+
+def _protocol_model(tmp_path, plant):
+    exe = str(tmp_path / f"gpu_protocol_model_{plant}")
+    subprocess.check_call(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=thread", "-pthread", f"-DPLANT={plant}",
+                           os.path.join(HERE, "gpu_protocol_model.cpp"), "-o", exe])
+    return subprocess.run([exe], capture_output=True, text=True, timeout=600,
+                          env=dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66"))
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_gpu_protocol_model_under_thread_sanitizer(tmp_path):
+    """Find-or-put's claim / row write / publish / bounded wait, the batch
+    ring with last-tile level finalisation, and the ring alone, modelled with
+    threads and the kernels' orderings: no race, and every result equals a
+    sequential BFS (gpu_protocol_model.cpp)."""
+    r = _protocol_model(tmp_path, 0)
+    assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
+    assert r.returncode == 0 and "errors 0" in r.stdout, r.stdout + r.stderr[-2000:]
+    assert "WRONG" not in r.stdout
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+@pytest.mark.parametrize("plant,what", [
+    (1, "DONE published before the row is written"),
+    (2, "DONE published without release"),
+    (3, "matching row compared without waiting for DONE"),
+    (4, "ring cell freed before its item is read"),
+    (5, "finished tile counted without ordering"),
+])
+def test_gpu_protocol_model_catches_planted_mistakes(tmp_path, plant, what):
+    r = _protocol_model(tmp_path, plant)
+    assert "ThreadSanitizer: data race" in r.stderr or r.returncode != 0, f"not caught: {what}"
 
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
