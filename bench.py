@@ -9,10 +9,12 @@ the value is find-or-put operations per second over the timed steps, with the
 inputs already resident in HBM.
 
 Extra legs in the same JSON line:
-  roofline     : the find-or-put kernel's algorithmic bytes per launch over its
-                 average duration (HIP events on the launch stream), against
-                 the 8 TB/s HBM peak; hardware traffic from committed rocprofv3
-                 counter summaries when they match the current kernel source.
+  roofline     : the find-or-put kernel's algorithmic bytes per launch (one
+                 128-byte slot line and one 64-byte row per operation, 192 B)
+                 over its average duration (HIP events on the launch stream),
+                 against the 8 TB/s HBM peak and against the measured random
+                 128-byte line ceiling; hardware traffic from committed
+                 rocprofv3 counter summaries when they match the kernel source.
   probes       : measured ceilings: random line reads of 64/128/256 bytes
                  (cooperative lanes, and 128 B by one lane) and random 64-bit
                  CAS throughput, random slot stores, row stores and row loads;
@@ -24,11 +26,16 @@ Extra legs in the same JSON line:
   batch        : the 64-model mix (2-16 processes, widths 4-32, 10^3-10^6
                  states each) explored in one persistent launch, in one launch
                  per step, and one model at a time, on the same tables.
-  serve        : Poisson arrivals (200/s) of queries drawn uniformly from the
-                 mix, served with continuous batching and, for comparison, one
-                 query at a time; p50/p99 latency from scheduled arrival.
+  serve        : Poisson arrivals (200/s for 60 s, the first 5 s excluded) of
+                 queries drawn uniformly from the mix, served with continuous
+                 batching and, for comparison, one query at a time; p50/p99
+                 latency from scheduled arrival, states per second of server
+                 work; and a burst of queries submitted at once, where the
+                 GPU and not the arrivals bounds the states per second.
   cpu_baseline : the CPU oracle (sequential find-or-put) timed on a bounded
-                 prefix of the same stream, one host thread.
+                 prefix of the same stream, one host thread; bfs.cpu_baseline
+                 and batch.cpu_baseline time the oracle's BFS on the model
+                 capped at 2^22 states and over the 64-model mix.
   cpu_lockless : the paper's lockless table and level-synchronous BFS on all
                  host cores (cpu_table/), on the same stream and on the model
                  capped at 2^22 states.
@@ -64,10 +71,18 @@ def source_sha(paths):
 
 
 def fop_bytes_per_op(W, line_slots=16):
-    """Algorithmic bytes of one find-or-put: input row, one line of 8-byte
-    slots, one row of data (written if new, compared if seen), seen byte +
-    index."""
+    """The build's own count of one find-or-put's bytes at its table's line
+    width: input row, one line of 8-byte slots, one row of data (written if
+    new, compared if seen), seen byte + index."""
     return 4 * W + 8 * line_slots + 4 * W + 1 + 4
+
+
+def spec_bytes_per_op(W):
+    """Random bytes one find-or-put must move by the method: one 128-byte
+    line of slots (about one line per operation at low fill) and one row of
+    data written (new) or read (seen), in 64-byte pieces: 192 B at W = 16.
+    Sequential input and output are counted apart."""
+    return 128 + 64 * ((4 * W + 63) // 64)
 
 
 def load_traffic(kernel, workload, n_launch_ops):
@@ -115,8 +130,10 @@ def main():
                     help="in that leg, skip the chain of one-state levels (tens of thousands of launches)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="query arrivals per second")
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
-    ap.add_argument("--serve-warmup", type=float, default=1.0, help="seconds excluded from latency stats")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-warmup", type=float, default=5.0, help="seconds excluded from latency stats")
+    ap.add_argument("--serve-burst", type=int, default=1000,
+                    help="queries submitted at once for the saturated serving point (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true", help="also run the copy probe (counter calibration)")
     ap.add_argument("--bfs-cap", type=int, default=1 << 27)
     ap.add_argument("--cpu-sample", type=int, default=1 << 25)
@@ -228,18 +245,25 @@ def main():
         table.set_threads_per_state(0)
 
     ops_per_s = n / (ms_per_step / 1e3)
-    bpo = fop_bytes_per_op(W, info["line_slots"])
+    bpo = spec_bytes_per_op(W)
+    own_bpo = fop_bytes_per_op(W, info["line_slots"])
     launch_ops = min(batch, n)
     achieved = bpo * launch_ops / (launch_ms / 1e3) / 1e9
     traffic, tinfo = load_traffic("k_find_or_put", "stream2p26", launch_ops)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_find_or_put", "avg_launch_ms": round(launch_ms, 4),
-                "algorithmic_bytes_per_op": bpo, "ops_per_launch": launch_ops}
+                "algorithmic_bytes_per_op": bpo, "ops_per_launch": launch_ops,
+                "own_accounting": {"bytes_per_op": own_bpo,
+                                   "what": f"input row + one {8 * info['line_slots']}-byte line (the "
+                                           f"table's) + one row + seen byte and index",
+                                   "GBs": round(own_bpo * launch_ops / (launch_ms / 1e3) / 1e9, 1)}}
     if tinfo is not None:
         roofline["traffic_source"] = os.path.basename(tinfo.get("summary", ""))
         if traffic:
             roofline["traffic_over_algorithmic"] = round(traffic / (bpo * launch_ops), 3)
+            roofline["hbm_traffic_GBs"] = round(traffic / (launch_ms / 1e3) / 1e9, 1)
+            roofline["hbm_traffic_frac"] = round(traffic / (launch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
 
     props = torch.cuda.get_device_properties(0)
     cpu_name = ""
@@ -306,8 +330,14 @@ def main():
         del slots
         lb = 8 * info["line_slots"]
         ceiling = probes[f"random_{lb}B_lines_{lb // 16}lane_GBs"]
-        probes["fop_frac_of_random_line"] = round(achieved / ceiling, 4)
-        probes["fop_frac_of_random_line_ceiling"] = f"random_{lb}B_lines_{lb // 16}lane_GBs"
+        # the primary denominator: random 128-byte lines read by 8 lanes each
+        line128 = probes["random_128B_lines_8lane_GBs"]
+        roofline["random_128B_line_GBs"] = line128
+        roofline["frac_of_random_128B_line"] = round(achieved / line128, 4)
+        roofline["meets_40pct_of_random_128B_line"] = achieved / line128 >= 0.40
+        probes["fop_own_bytes_frac_of_table_line_ceiling"] = round(
+            roofline["own_accounting"]["GBs"] / ceiling, 4)
+        probes["fop_table_line_ceiling"] = f"random_{lb}B_lines_{lb // 16}lane_GBs"
         # slot CAS issued by the find-or-put launch (one per insert plus the
         # retries) against the random 64-bit CAS rate of the same GPU
         cas = n_distinct + info["cas_failures"]
@@ -506,11 +536,14 @@ def main():
                              f"({n_q} queries) drawn uniformly from the 64-model mix; tables of "
                              f"2^21 slots; latency = result time - scheduled arrival; first "
                              f"{args.serve_warmup:g} s excluded"}
+        n_burst = args.serve_burst
+        burst_picks = (gen.xs64(0x5E50, n_burst) % np.uint64(len(models))).astype(np.int64) if n_burst else None
         for label, max_active in (("continuous", 0), ("one_at_a_time", 1)):
             with lhs.Server(capacity=1 << 21, max_active=max_active) as srv:
                 # resident tables: one warm-up query per shape before the clock starts
                 for t in [srv.submit(m) for m in models]:
                     srv.wait(t)
+                st0 = srv.stats()
                 t0 = srv.clock() + 0.05
                 tickets = []
                 for i in range(n_q):
@@ -527,16 +560,38 @@ def main():
                         lat.append((done - (t0 + arrivals[i])) * 1e3)
                         svc.append((done - adm) * 1e3)
                 st = srv.stats()
+                busy = st["busy_s"] - st0["busy_s"]
+                burst = None
+                if n_burst:
+                    # every query submitted at once: the server, not the
+                    # arrival rate, bounds the states per second
+                    b0 = srv.clock()
+                    bt = [srv.submit(models[k]) for k in burst_picks]
+                    b_states, b_last = 0, b0
+                    for t in bt:
+                        r, (_, _, done) = srv.wait(t)
+                        b_states += r.total
+                        b_last = max(b_last, done)
+                    burst = {"queries": n_burst, "states": int(b_states),
+                             "makespan_s": round(b_last - b0, 4),
+                             "states_per_s": round(b_states / (b_last - b0), 1)}
             lat, svc = np.array(lat), np.array(svc)
             serve[label] = {"queries": n_q, "states": int(states),
                             "states_per_s": round(states / (done_last - t0), 1),
+                            "states_per_busy_s": round(states / busy, 1) if busy > 0 else None,
+                            "busy_s": round(busy, 3),
                             "p50_ms": round(float(np.percentile(lat, 50)), 3),
                             "p99_ms": round(float(np.percentile(lat, 99)), 3),
                             "service_p50_ms": round(float(np.percentile(svc, 50)), 3),
-                            "steps": st["steps"], "peak_table_bytes": st["peak_bytes"]}
-            log(f"serve {label}: p50 {serve[label]['p50_ms']} ms, p99 {serve[label]['p99_ms']} ms")
+                            "steps": st["steps"] - st0["steps"], "peak_table_bytes": st["peak_bytes"],
+                            "burst": burst}
+            log(f"serve {label}: p50 {serve[label]['p50_ms']} ms, p99 {serve[label]['p99_ms']} ms, "
+                f"busy {busy:.2f} s" + (f", burst {burst['states_per_s']:.3g} states/s" if burst else ""))
         serve["p99_speedup_vs_one_at_a_time"] = round(
             serve["one_at_a_time"]["p99_ms"] / serve["continuous"]["p99_ms"], 2)
+        if n_burst:
+            serve["burst_speedup_vs_one_at_a_time"] = round(
+                serve["continuous"]["burst"]["states_per_s"] / serve["one_at_a_time"]["burst"]["states_per_s"], 2)
         out["serve"] = serve
 
     if not args.no_cpu:
@@ -551,6 +606,27 @@ def main():
                                "sample": f"first {S} rows of the same stream ({d} distinct), "
                                          f"sequential std::unordered_map find-or-put, {cdt:.1f} s"}
         log(f"cpu baseline: {S / cdt:.0f} ops/s over {S} rows")
+        if "bfs" in out:
+            # the oracle's BFS of the same model to a lower cap (one core)
+            mc = gen.big_model(cap=1 << 22)
+            c0 = time.time()
+            ro = oracle.reach(mc)
+            cdt = time.time() - c0
+            out["bfs"]["cpu_baseline"] = {
+                "value": round(ro.total / cdt, 1), "unit": "states/s", "cores": 1, "kind": "oracle",
+                "sample": f"the same model capped at 2^22 states ({ro.total} states, {ro.n_levels} levels, "
+                          f"{ro.edges} edges), sequential BFS over std::unordered_set, {cdt:.1f} s"}
+            log(f"cpu baseline bfs: {ro.total / cdt:.0f} states/s")
+        if "batch" in out:
+            # the oracle over the whole 64-model mix, one model after another
+            c0 = time.time()
+            tot = sum(oracle.reach(m).total for m in gen.batch_models())
+            cdt = time.time() - c0
+            out["batch"]["cpu_baseline"] = {
+                "value": round(tot / cdt, 1), "unit": "states/s", "cores": 1, "kind": "oracle",
+                "seconds": round(cdt, 2),
+                "sample": f"every model of the 64-model mix ({tot} states), sequential BFS, {cdt:.1f} s"}
+            log(f"cpu baseline batch: {cdt:.1f} s for {tot} states")
     if not args.no_cpu_lockless:
         # the paper's method on every host core (multi-core lockless table)
         import cpu_table

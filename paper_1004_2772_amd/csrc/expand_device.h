@@ -41,10 +41,10 @@ struct SuccVec {
 // transition-table area of `tcap` entries:
 //   tile     [256][W|1]  frontier states of the current tile
 //   tr       [tcap] u64  the model's packed transitions (when they fit)
-//   masks    [256] u64   enabled transitions of each tile state (P*K <= 64)
-//   offs     [258]       exclusive prefix of successor counts (+ total)
+//   pick     [256]       the (state, enabled pair) of each successor of the
+//                        current pass (P*K <= 64), in the mask area
 //     (queue [kQueue]    enabled (state, process, transition) when P*K > 64,
-//                        in the same words as masks/offs)
+//                        in the same words)
 //   succ_cnt [256]       successors per tile state (edges, deadlocks)
 //   hq       [256] u64   hash of each successor of the current pass  } G > 1
 //   d0, d1   [256]       successor descriptors of the pass          } only
@@ -179,9 +179,9 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
 // Successor enumeration (P*K <= 64): every lane evaluates all guards of its
 // own state into a 64-bit mask of enabled (process, transition) pairs, read
 // from the LDS copy of the transition table; a block prefix sum over the mask
-// popcounts numbers the tile's successors, and lane q of a pass decodes
-// successor number q by binary search over the prefix and the rank of its
-// bit.  Wider models (P*K > 64) enumerate candidates 256 at a time into an
+// popcounts numbers the tile's successors.  Before each pass of 256, every
+// state lane writes its successors that fall in the pass, in bit order, to
+// their places in an LDS list, and lane q of the pass takes entry q.  Wider models (P*K > 64) enumerate candidates 256 at a time into an
 // LDS ring.
 //
 // New states are compacted into LDS and appended to next[] with one atomic
@@ -217,7 +217,6 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
     uint32_t *tile = smem;
     uint2 *tr_lds = reinterpret_cast<uint2 *>(tile + kBlock * stride);
     uint64_t *masks = reinterpret_cast<uint64_t *>(tr_lds + tcap);
-    uint32_t *offs = reinterpret_cast<uint32_t *>(masks + kBlock);
     uint32_t *queue = reinterpret_cast<uint32_t *>(masks);     // wide models only
     uint32_t *succ_cnt = reinterpret_cast<uint32_t *>(masks) + kMaskArea;
     uint64_t *hq = reinterpret_cast<uint64_t *>(succ_cnt + kBlock);   // 8-byte aligned (G > 1)
@@ -273,7 +272,28 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
             }
         }
     }
-    if (staged) {
+    // plain loads of rows of W = 4, 8, 16 or 32 words: the wavefront loads
+    // its 64 rows together, W/4 lanes per row with one 16-byte piece each,
+    // so one load instruction moves 64/(W/4) whole rows
+    const bool coop = !COHERENT && (W == 4 || W == 8 || W == 16 || W == 32);
+    if (coop) {
+        const uint32_t lane = __lane_id(), wrow = tid - lane;    // the wave's first row
+        const uint32_t cs = W == 4 ? 0u : (W == 8 ? 1u : (W == 16 ? 2u : 3u));   // log2(W/4)
+        const uint32_t c = lane & ((1u << cs) - 1u);
+        const uint32_t my_slot = (uint32_t)slot;
+        for (uint32_t r0 = 0; r0 < 64; r0 += 64u >> cs) {
+            const uint32_t r = r0 + (lane >> cs);
+            const uint32_t rs = (uint32_t)__shfl((int)my_slot, (int)r, 64);
+            if (wrow + r < rows) {
+                const uint4 x = reinterpret_cast<const uint4 *>(t.data + (uint64_t)rs * W)[c];
+                uint32_t *dst = tile + (wrow + r) * stride + 4 * c;
+                dst[0] = x.x;
+                dst[1] = x.y;
+                dst[2] = x.z;
+                dst[3] = x.w;
+            }
+        }
+    } else if (staged) {
         const uint32_t *src = t.data + slot * W;
         uint32_t *dst = tile + tid * stride;
         if (COHERENT && (W & 1u) == 0) {
@@ -385,7 +405,6 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
                 }
             }
         }
-        masks[tid] = mask;
         const uint32_t c = (uint32_t)__popcll(mask);
         succ_cnt[tid] = c;
         const uint32_t incl = wave_scan_incl(c);
@@ -397,29 +416,26 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
             woff += w < tid / 64 ? s_wtot[w] : 0u;
             total += s_wtot[w];
         }
-        offs[tid] = woff + incl - c;
-        if (tid == 0)
-            offs[kBlock] = total;
-        __syncthreads();
+        // this state's successors are numbered [nextq, nextq + c) in the tile
+        uint32_t nextq = woff + incl - c;
+        uint64_t rem = mask;
         // ---- passes of 256 successors -------------------------------------
+        // Every state lane writes the (state, enabled pair) of its successors
+        // that fall in the pass into `pick` (the mask area); lane q of the
+        // pass then stages successor s0 + q.
+        uint32_t *pick = reinterpret_cast<uint32_t *>(masks);
         for (uint32_t s0 = 0; s0 < total && !aborted; s0 += kBlock) {
             const uint32_t take = min(total - s0, kBlock);
+            while (rem && nextq < s0 + kBlock) {
+                pick[nextq - s0] = (tid << 8) | (uint32_t)__builtin_ctzll(rem);
+                rem &= rem - 1;
+                ++nextq;
+            }
+            __syncthreads();
             if (tid < take) {
-                const uint32_t q = s0 + tid;
-                uint32_t lo = 0, hi = kBlock;    // offs[lo] <= q < offs[hi]
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (offs[mid] <= q)
-                        lo = mid;
-                    else
-                        hi = mid;
-                }
-                uint64_t mk = masks[lo];
-                for (uint32_t r = q - offs[lo]; r; --r)
-                    mk &= mk - 1;
-                const uint32_t j = (uint32_t)__builtin_ctzll(mk);
+                const uint32_t e = pick[tid], j = e & 0xFFu;
                 const uint32_t p = m.K == 1 ? j : __umulhi(j, m.magic_K);
-                stage_successor(tid, lo, p, j - p * m.K);
+                stage_successor(tid, e >> 8, p, j - p * m.K);
             }
             __syncthreads();
             aborted = fop_pass(take);
