@@ -59,9 +59,25 @@ __global__ __launch_bounds__(kBlock) void k_find_or_put(TableView t, const uint3
         const uint32_t words = rows * W;
         const uint32_t *src = in + base * W;
         __syncthreads();
-        for (uint32_t f = tid; f < words; f += kBlock) {
-            const uint32_t r = W == 1 ? f : __umulhi(f, magicW);
-            tile[r * stride + (f - r * W)] = src[f];
+        if ((W & 3u) == 0 && (reinterpret_cast<uintptr_t>(in) & 15u) == 0) {
+            // rows of a multiple of four words, 16-byte aligned: 16-byte
+            // loads, each inside one row
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+            const u32x4 *src4 = reinterpret_cast<const u32x4 *>(src);
+            for (uint32_t f4 = tid; f4 < words / 4; f4 += kBlock) {
+                const uint32_t f = 4 * f4, r = __umulhi(f, magicW);
+                const u32x4 x = __builtin_nontemporal_load(src4 + f4);   // read once
+                uint32_t *dst = tile + r * stride + (f - r * W);
+                dst[0] = x.x;
+                dst[1] = x.y;
+                dst[2] = x.z;
+                dst[3] = x.w;
+            }
+        } else {
+            for (uint32_t f = tid; f < words; f += kBlock) {
+                const uint32_t r = W == 1 ? f : __umulhi(f, magicW);
+                tile[r * stride + (f - r * W)] = src[f];
+            }
         }
         __syncthreads();
         uint64_t h = 0;
@@ -79,9 +95,9 @@ __global__ __launch_bounds__(kBlock) void k_find_or_put(TableView t, const uint3
             find_or_put_wave<LS, LdsRow>(t, &ws[tid / 64], smem, make_uint2(tid * stride, 0u), h, active,
                                          slot, code, cnt);
             if (active) {
-                seen[base + tid] = code == kSeen ? 1 : (code == kNew ? 0 : 0xFF);
+                __builtin_nontemporal_store((uint8_t)(code == kSeen ? 1 : (code == kNew ? 0 : 0xFF)), seen + base + tid);
                 if (index)
-                    index[base + tid] = slot;
+                    __builtin_nontemporal_store(slot, index + base + tid);
             }
         } else {
             for (uint32_t r = 0; r < G; ++r) {
@@ -110,10 +126,12 @@ __global__ __launch_bounds__(kBlock) void k_find_or_put(TableView t, const uint3
 // Zero n 64-bit words (p 16-byte aligned): 16-byte stores, so one
 // wavefront store instruction writes 1 KiB of whole lines.
 __global__ void k_zero_u64(uint64_t *p, uint64_t n) {
-    uint4 *q = reinterpret_cast<uint4 *>(p);
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 *q = reinterpret_cast<u32x4 *>(p);
     const uint64_t n2 = n / 2, stride = (uint64_t)gridDim.x * blockDim.x;
+    const u32x4 z = {0u, 0u, 0u, 0u};
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride)
-        q[i] = make_uint4(0, 0, 0, 0);
+        __builtin_nontemporal_store(z, q + i);
     if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0)
         p[n - 1] = 0;
 }

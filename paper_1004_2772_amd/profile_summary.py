@@ -12,6 +12,12 @@
         TCC_ATOMIC_sum (atomic requests at the L2) and TCC_EA0_ATOMIC_sum (atomics
         sent on to memory) of a kernel's largest dispatch and of the random-CAS
         probe's, written as JSON for bench.py (which divides by the launch times).
+    python -m paper_1004_2772_amd.profile_summary probes FETCH_DB WRITE_DB --copy-bytes B --out JSON [--cmd "..."]
+        FETCH_SIZE / WRITE_SIZE per access of each measurement probe, from the
+        timed (second) dispatch of each probe as bench.py runs them: random
+        line reads of 64 / 128 / 256 bytes (cooperative lanes), 8-byte slot
+        stores, 64-byte row stores, 64-byte row loads and 64-bit CAS; copy-
+        calibrated as above.
     python -m paper_1004_2772_amd.profile_summary traffic-sum FETCH_DB WRITE_DB --kernel K1 [--kernel K2] \
         --runs R [--take D] --units N --unit-name NAME --copy-bytes B --out JSON [--cmd "..."]
         FETCH_SIZE / WRITE_SIZE summed over the dispatches of the named kernels
@@ -104,6 +110,12 @@ def main(argv=None):
     at.add_argument("--sources", required=True)
     at.add_argument("--out", required=True)
     at.add_argument("--cmd", default="")
+    pr = sub.add_parser("probes")
+    pr.add_argument("fetch_db")
+    pr.add_argument("write_db")
+    pr.add_argument("--copy-bytes", type=int, required=True)
+    pr.add_argument("--out", required=True)
+    pr.add_argument("--cmd", default="")
     ts = sub.add_parser("traffic-sum")
     ts.add_argument("fetch_db")
     ts.add_argument("write_db")
@@ -146,6 +158,32 @@ def main(argv=None):
 
     fetch = counter_per_dispatch(a.fetch_db, "FETCH_SIZE")
     write = counter_per_dispatch(a.write_db, "WRITE_SIZE")
+    if a.mode == "probes":
+        if not fetch.get("k_probe_copy") or not write.get("k_probe_copy"):
+            sys.exit("copy probe missing from the counter runs (run bench.py with --calib-copy)")
+        f_fetch = a.copy_bytes / (largest_dispatch(fetch["k_probe_copy"]) * 1024.0)
+        f_write = a.copy_bytes / (largest_dispatch(write["k_probe_copy"]) * 1024.0)
+        # bench.py's probe order: each probe runs twice (warm-up, timed)
+        plan = [("random_64B_line_read", "void k_probe_lines_coop<4u>", 1, 1 << 25),
+                ("random_128B_line_read", "void k_probe_lines_coop<8u>", 1, 1 << 24),
+                ("random_256B_line_read", "void k_probe_lines_coop<16u>", 1, 1 << 23),
+                ("slot_store_8B", "void k_probe_access<0u>", 1, 1 << 27),
+                ("row_store_64B", "void k_probe_access<1u>", 1, 1 << 27),
+                ("row_load_64B", "void k_probe_access<2u>", 1, 1 << 27),
+                ("cas_64bit", "k_probe_cas", 1, 1 << 26)]
+        res = dict(fetch_scale=f_fetch, write_scale=f_write, command=a.cmd, per_access={})
+        for name, kernel, k, ops in plan:
+            fl, wl = fetch.get(kernel, []), write.get(kernel, [])
+            if len(fl) <= k or len(wl) <= k:
+                sys.exit(f"{kernel}: dispatch {k} missing from the counter runs")
+            res["per_access"][name] = {
+                "accesses": ops,
+                "fetch_bytes": fl[k][1] * 1024.0 * f_fetch / ops,
+                "write_bytes": wl[k][1] * 1024.0 * f_write / ops}
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res, indent=1))
+        return
     if a.mode == "traffic-sum":
         if not fetch.get("k_probe_copy") or not write.get("k_probe_copy"):
             sys.exit("copy probe missing from the counter runs (run bench.py with --calib-copy)")

@@ -121,6 +121,34 @@ def test_high_fill(lhs, tps):
         check_table_invariants(t)
 
 
+@pytest.mark.parametrize("W", [4, 16, 32])
+@pytest.mark.parametrize("tps", [1, 4])
+def test_unaligned_input_rows(lhs, W, tps):
+    """Rows handed over one word past a 16-byte boundary (a view into a larger
+    buffer) take the kernel's 4-byte staging path: same results as the oracle
+    and as aligned rows."""
+    import torch
+    print(f"\n[fop] unaligned rows W={W} tps={tps}", flush=True)
+    rows, order = gen.dup_stream(300 + W, 4000, W, 2)
+    stream = gen.gather(rows, order)
+    o_seen, o_id, distinct = oracle.stream(stream)
+    flat = torch.zeros(stream.size + 1, dtype=torch.int32, device="cuda")
+    flat[1:] = dev_u32(stream).view(-1)
+    dev = flat[1:].view(len(stream), W)
+    assert dev.data_ptr() % 16 == 4
+    n = len(stream)
+    seen = torch.empty(n, dtype=torch.uint8, device="cuda")
+    idx = torch.empty(n, dtype=torch.int32, device="cuda")
+    with lhs.Table(1 << 14, W) as t:
+        t.set_threads_per_state(tps)
+        t.find_or_put(dev, seen, idx)
+        t.check()
+        assert t.count() == distinct
+        check_stream_batches(o_id, distinct, seen.cpu().numpy(), idx.cpu().numpy().view(np.uint32), [(0, n)])
+        got, _ = check_table_invariants(t)
+    assert np.array_equal(np.unique(got, axis=0), np.unique(stream, axis=0))
+
+
 def test_bad_threads_per_state(lhs):
     with lhs.Table(1 << 10, 4) as t:
         for bad in (2, 3, 32):

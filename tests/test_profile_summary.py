@@ -48,3 +48,28 @@ def test_traffic_sum_takes_the_first_dispatches_of_the_runs(tmp_path):
     assert r["dispatches_per_run"] == 3
     assert r["fetch_bytes_per_run"] == 6 * 1024 * 2.0 and r["write_bytes_per_run"] == 6 * 1024
     assert r["fetch_bytes_per_edge"] == 4096 and r["write_bytes_per_edge"] == 2048
+
+
+def test_probes_take_the_timed_dispatch_of_each_probe(tmp_path):
+    copy_bytes = 1 << 20
+    lines = {4: 1 << 25, 8: 1 << 24, 16: 1 << 23}
+    rows = [(COPY, 4096, copy_bytes / 2048)]
+    # each probe twice (warm-up, timed); the timed one is summarised
+    for c, n in lines.items():
+        name = f"void (anonymous namespace)::k_probe_lines_coop<{c}u>(uint4 const*, unsigned long)"
+        rows += [(name, 1, 1.0), (name, 1, n * 16 * c / 1024 / 2)]   # counter reads half: x2 scale
+    for form, n in ((0, 1 << 27), (1, 1 << 27), (2, 1 << 27)):
+        name = f"void (anonymous namespace)::k_probe_access<{form}u>(unsigned long*, unsigned long)"
+        rows += [(name, 1, 1.0), (name, 1, n * 8 / 1024)]
+    cas = "(anonymous namespace)::k_probe_cas(unsigned long*, unsigned long, unsigned long)"
+    rows += [(cas, 1, 1.0), (cas, 1, (1 << 26) * 64 / 1024)]
+    f = _db(tmp_path / "f.db", "FETCH_SIZE", rows)
+    w = _db(tmp_path / "w.db", "WRITE_SIZE", [(COPY, 4096, copy_bytes / 1024)] + rows[1:])
+    out = tmp_path / "p.json"
+    ps.main(["probes", f, w, "--copy-bytes", str(copy_bytes), "--out", str(out)])
+    r = json.loads(out.read_text())["per_access"]
+    assert r["random_64B_line_read"]["fetch_bytes"] == 64.0
+    assert r["random_128B_line_read"]["fetch_bytes"] == 128.0
+    assert r["random_256B_line_read"]["fetch_bytes"] == 256.0
+    assert r["slot_store_8B"]["fetch_bytes"] == 16.0 and r["slot_store_8B"]["write_bytes"] == 8.0
+    assert r["cas_64bit"]["write_bytes"] == 64.0 and r["cas_64bit"]["accesses"] == 1 << 26
