@@ -28,10 +28,12 @@ Extra legs in the same JSON line:
                  per step, and one model at a time, on the same tables.
   serve        : Poisson arrivals (200/s for 60 s, the first 5 s excluded) of
                  queries drawn uniformly from the mix, served with continuous
-                 batching and, for comparison, one query at a time; p50/p99
-                 latency from scheduled arrival, states per second of server
-                 work; and a burst of queries submitted at once, where the
-                 GPU and not the arrivals bounds the states per second.
+                 batching by the persistent launch and, for comparison, one
+                 query at a time (--serve-rounds adds host rounds of level
+                 steps); p50/p99 latency from scheduled arrival, states per
+                 second of server work; and a burst of queries submitted at
+                 once, where the GPU and not the arrivals bounds the states
+                 per second.
   cpu_baseline : the CPU oracle (sequential find-or-put) timed on a bounded
                  prefix of the same stream, one host thread; bfs.cpu_baseline
                  and batch.cpu_baseline time the oracle's BFS on the model
@@ -132,6 +134,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="query arrivals per second")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-warmup", type=float, default=5.0, help="seconds excluded from latency stats")
+    ap.add_argument("--serve-rounds", action="store_true",
+                    help="also serve the stream with host rounds of level steps instead of the persistent launch")
     ap.add_argument("--serve-burst", type=int, default=1000,
                     help="queries submitted at once for the saturated serving point (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true", help="also run the copy probe (counter calibration)")
@@ -538,8 +542,11 @@ def main():
                              f"{args.serve_warmup:g} s excluded"}
         n_burst = args.serve_burst
         burst_picks = (gen.xs64(0x5E50, n_burst) % np.uint64(len(models))).astype(np.int64) if n_burst else None
-        for label, max_active in (("continuous", 0), ("one_at_a_time", 1)):
-            with lhs.Server(capacity=1 << 21, max_active=max_active) as srv:
+        modes = [("continuous", 0, False), ("one_at_a_time", 1, False)]
+        if args.serve_rounds:
+            modes.append(("continuous_rounds", 0, True))
+        for label, max_active, rounds in modes:
+            with lhs.Server(capacity=1 << 21, max_active=max_active, rounds=rounds) as srv:
                 # resident tables: one warm-up query per shape before the clock starts
                 for t in [srv.submit(m) for m in models]:
                     srv.wait(t)
@@ -583,7 +590,8 @@ def main():
                             "p50_ms": round(float(np.percentile(lat, 50)), 3),
                             "p99_ms": round(float(np.percentile(lat, 99)), 3),
                             "service_p50_ms": round(float(np.percentile(svc, 50)), 3),
-                            "steps": st["steps"] - st0["steps"], "peak_table_bytes": st["peak_bytes"],
+                            ("round_steps" if rounds else "launches"): st["steps"] - st0["steps"],
+                            "peak_table_bytes": st["peak_bytes"],
                             "burst": burst}
             log(f"serve {label}: p50 {serve[label]['p50_ms']} ms, p99 {serve[label]['p99_ms']} ms, "
                 f"busy {busy:.2f} s" + (f", burst {burst['states_per_s']:.3g} states/s" if burst else ""))

@@ -420,13 +420,21 @@ lhs_status reach_explore_batch(const reach_model *const *models, uint32_t n, con
  * Serving: reachability queries with continuous batching.
  *
  * A server owns a worker thread and a HIP stream on the device that was
- * current at reach_server_create.  It works in rounds of four BFS level
- * steps run by the device alone; every step expands the current level of
- * every active query in one launch.  Between rounds it retires finished
- * queries and admits queued ones (first come, first served) while their
- * tables fit the device-memory budget.  Tables stay resident in a pool and
- * are reused by later queries of the same capacity and width.  A query's
- * result equals reach_explore on it alone.
+ * current at reach_server_create.  By default one persistent launch serves
+ * every query on the GPU: its workgroups take (query, tile) items from a
+ * device work queue, the workgroup that finishes a query's level advances
+ * that query alone, new queries are posted to the running launch (an idle
+ * workgroup inserts s0 and starts it at once) and finished ones are
+ * reported through completion records in host memory, so a query starts and
+ * ends without waiting for a kernel boundary.  The launch ends once idle
+ * and is started again when work arrives.  REACH_SERVER_F_ROUNDS instead
+ * works in rounds of four BFS level steps run by the device alone (every
+ * step expands the current level of every active query in one launch), and
+ * admits and retires queries between rounds.  Either way queries are
+ * admitted first come, first served, while their tables fit the
+ * device-memory budget; tables stay resident in a pool and are reused by
+ * later queries of the same capacity and width.  A query's result equals
+ * reach_explore on it alone.
  * ---------------------------------------------------------------------- */
 typedef struct reach_server reach_server;
 
@@ -436,10 +444,13 @@ typedef struct reach_server_opts {
                               2*state_cap + 2^16 if the model is capped, else
                               2^21                                               */
     uint32_t max_active;   /* queries on the GPU at once, at most 1024 (0 = 1024) */
-    uint32_t flags;        /* reserved, 0                                       */
+    uint32_t flags;        /* REACH_SERVER_F_*                                  */
     lhs_config table;      /* shape of every query table; all zero = the
                               tuning table's "batch" choice                   */
 } reach_server_opts;
+
+/* Rounds of host-launched level steps instead of the persistent launch. */
+#define REACH_SERVER_F_ROUNDS 1u
 
 typedef struct reach_query_times {
     double submit_s;       /* reach_server_clock() at submission                */
@@ -466,7 +477,9 @@ lhs_status reach_server_create(const reach_server_opts *o, reach_server **out);
 
 /* Queue a query; the model (host memory) is copied, the caller may free it
  * on return.  *ticket identifies the query.  LHS_EBUDGET if its table can
- * never fit the budget, LHS_EINVAL for an invalid model. */
+ * never fit the budget, LHS_EINVAL for an invalid model (or, on a
+ * persistent server, a table of more than 2^30 slots: the work queue holds a
+ * full level of every query on the GPU). */
 lhs_status reach_server_submit(reach_server *s, const reach_model *m, uint64_t *ticket);
 
 /* reach_server_submit on a table of the caller's (NULL = the pool, as

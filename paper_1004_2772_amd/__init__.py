@@ -28,6 +28,7 @@ REACH_F_HOST_LOOP = 1
 REACH_F_GRAPH = 2
 REACH_F_PARENTS = 4
 REACH_F_ASYNC = 8
+REACH_SERVER_F_ROUNDS = 1
 PROBES = {"double": 0, "linear": 1, "quadratic": 2}
 TUNE_TABLE, TUNE_BATCH = 0, 1
 
@@ -483,12 +484,15 @@ def reach_explore_noalloc(model, table: Table, cap: int | None = None, max_level
 
 
 class Server:
-    """Continuous-batching reachability server (one worker thread on the GPU)."""
+    """Continuous-batching reachability server (one worker thread on the GPU):
+    one persistent launch serves every query, or with ``rounds`` the host
+    launches rounds of level steps (REACH_SERVER_F_ROUNDS)."""
 
     def __init__(self, budget_bytes: int = 0, capacity: int = 0, max_active: int = 0,
-                 cfg: LhsConfig | None = None):
+                 cfg: LhsConfig | None = None, rounds: bool = False):
         h = ctypes.c_void_p()
-        o = ServerOpts(budget_bytes, capacity, max_active, 0, cfg if cfg is not None else LhsConfig())
+        o = ServerOpts(budget_bytes, capacity, max_active, REACH_SERVER_F_ROUNDS if rounds else 0,
+                       cfg if cfg is not None else LhsConfig())
         _check(lib().reach_server_create(ctypes.byref(o), ctypes.byref(h)), "reach_server_create")
         self.handle = h
 

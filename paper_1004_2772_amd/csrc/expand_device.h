@@ -70,8 +70,10 @@ __host__ __device__ inline uint32_t trans_lds_entries(uint32_t P, uint32_t L, ui
     return n <= kTransLdsMax ? (uint32_t)n : 0u;
 }
 
-// Which model's transitions are currently staged in this workgroup's LDS.
+// Which model's transitions are currently staged in this workgroup's LDS
+// (buffer and key).
 static __shared__ const uint2 *s_trans_staged;
+static __shared__ unsigned long long s_trans_key;
 // Edge / deadlock counts accumulated over tiles (deferred mode).
 static __shared__ unsigned long long s_acc_edges, s_acc_dead;
 // New-state buffer fill, its reserved base in next[], and the level's abort
@@ -86,6 +88,7 @@ static __shared__ uint32_t s_stall;
 __device__ __forceinline__ void expand_begin() {
     if (threadIdx.x == 0) {
         s_trans_staged = nullptr;
+        s_trans_key = 0;
         s_acc_edges = 0;
         s_acc_dead = 0;
         s_nnew = 0;
@@ -159,6 +162,19 @@ __device__ __forceinline__ void expand_end(uint32_t *smem, uint32_t W, uint32_t 
     }
 }
 
+// One packed transition: a plain load, or (CL) a coherent one for buffers
+// rewritten while the kernel runs.
+template <bool CL>
+__device__ __forceinline__ uint2 ld_trans(const uint2 *p) {
+    if constexpr (CL) {
+        const uint64_t x = __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_SYSTEM);
+        return make_uint2((uint32_t)x, (uint32_t)(x >> 32));
+    } else {
+        return *p;
+    }
+}
+
 __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
     const uint32_t lane = __lane_id();
 #pragma unroll
@@ -206,8 +222,10 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
 // AWAIT (with COHERENT): a frontier entry may still be in flight; 0xFFFFFFFF
 // marks one not yet written, which the staging lane waits for (bounded:
 // LHS_ESTALL and an aborted tile).
+// CL: slot lines are read with coherent loads (tables reused within one
+// launch, the persistent server).
 template <int G, uint32_t LS, bool COHERENT = false, bool DEFER = false, bool DEFER_COUNTS = DEFER,
-          bool AWAIT = false>
+          bool AWAIT = false, bool CL = false>
 __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, const ModelView &m,
                                             const uint32_t *__restrict__ front, uint64_t base,
                                             uint32_t rows, uint32_t *__restrict__ next,
@@ -237,7 +255,7 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
     const bool tr_in_lds = PLK <= tcap;
 
     __syncthreads();   // the previous tile is fully consumed
-    const bool restage = tr_in_lds && s_trans_staged != m.trans;
+    const bool restage = tr_in_lds && (s_trans_staged != m.trans || s_trans_key != m.key);
     if (tid == 0) {
         s_tail = 0;
         s_abort = __hip_atomic_load(&lc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -246,7 +264,7 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
     }
     if (restage)
         for (uint32_t i = tid; i < PLK; i += kBlock)
-            tr_lds[i] = m.trans[i];
+            tr_lds[i] = ld_trans<CL>(m.trans + i);
     succ_cnt[tid] = 0;
     bool staged = tid < rows;
     uint64_t slot = 0;
@@ -321,11 +339,24 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
         }
     }
     __syncthreads();
-    if (restage && tid == 0)
-        s_trans_staged = m.trans;
+    // the LDS copy lives behind this model's tile rows: a tile that does not
+    // stage its transitions may overwrite another model's copy with its rows
+    // and masks, so it forgets that copy
+    if ((restage || !tr_in_lds) && tid == 0) {
+        s_trans_staged = tr_in_lds ? m.trans : nullptr;
+        s_trans_key = m.key;
+    }
     if (s_abort || s_stall)
         return true;
     const uint2 *tr = tr_in_lds ? tr_lds : m.trans;
+    // transition idx (CL and not staged: read past the caches)
+    auto trans_at = [&](uint64_t idx) -> uint2 {
+        if constexpr (CL) {
+            if (!tr_in_lds)
+                return ld_trans<true>(m.trans + idx);
+        }
+        return tr[idx];
+    };
 
     auto flush_new = [&]() { flush_new_slots<COHERENT>(nbuf, next, lc, limit); };
     // ---- find-or-put of successors d0/d1/hq[0, take); new slots to nbuf ----
@@ -335,12 +366,12 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
             const bool active = q < take;
             uint32_t slot, code;
             if constexpr (G == 1) {
-                find_or_put_wave<LS, SuccVec>(t, &ws[tid / 64], smem, make_uint2(my_d0, my_d1), my_h, active,
-                                              slot, code, cnt);
+                find_or_put_wave<LS, SuccVec, CL>(t, &ws[tid / 64], smem, make_uint2(my_d0, my_d1), my_h,
+                                                  active, slot, code, cnt);
             } else {
                 const uint32_t o = active ? q : 0;
-                find_or_put<G, LS>(t, SuccVec::decode(smem, make_uint2(d0[o], d1[o])), hq[o], active, slot,
-                                   code, cnt);
+                find_or_put<G, LS, SuccVec, CL>(t, SuccVec::decode(smem, make_uint2(d0[o], d1[o])), hq[o], active,
+                                                slot, code, cnt);
             }
             const bool is_new = active && leader && code == kNew;
             if (t.parent && is_new) {
@@ -368,7 +399,7 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
     // registers (G == 1, i == tid)
     auto stage_successor = [&](uint32_t i, uint32_t st, uint32_t p, uint32_t k) {
         const uint32_t *row = tile + st * stride;
-        const uint2 x = tr[((uint64_t)p * m.L + row[p]) * m.K + k];
+        const uint2 x = trans_at(((uint64_t)p * m.L + row[p]) * m.K + k);
         const uint32_t evar = x.x >> 24;
         const uint32_t ew = evar == 0xFFu ? 0xFFu : m.P + evar;
         const SuccVec v{row, p, x.x & 0xFFFFu, ew == 0xFFu ? 0xFFFFFFFFu : ew, x.y >> 16};
@@ -396,9 +427,9 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
                 const uint32_t local = row[p];
                 if (local >= m.L)
                     continue;
-                const uint2 *tp = tr + ((uint64_t)p * m.L + local) * m.K;
+                const uint64_t tb = ((uint64_t)p * m.L + local) * m.K;
                 for (uint32_t k = 0; k < m.K; ++k) {
-                    const uint2 x = tp[k];
+                    const uint2 x = trans_at(tb + k);
                     const uint32_t gvar = (x.x >> 16) & 0xFFu;
                     const bool en = gvar == 0xFFu || row[m.P + gvar] == (x.y & 0xFFFFu);
                     mask |= (uint64_t)en << (p * m.K + k);
@@ -457,7 +488,7 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
                     const uint32_t *row = tile + st * stride;
                     const uint32_t local = row[p];
                     if (local < m.L) {
-                        const uint2 x = tr[((uint64_t)p * m.L + local) * m.K + k];
+                        const uint2 x = trans_at(((uint64_t)p * m.L + local) * m.K + k);
                         const uint32_t gvar = (x.x >> 16) & 0xFFu;
                         en = gvar == 0xFFu || row[m.P + gvar] == (x.y & 0xFFFFu);
                     }

@@ -127,6 +127,20 @@ __device__ __forceinline__ void wait_vm_complete() {
     __builtin_amdgcn_s_waitcnt(0x0F70);
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
+// 16 bytes of a slot line: a plain load, or (CL) two coherent 8-byte loads,
+// for callers whose tables may have been emptied while they run (another
+// XCD's cache can still hold the line as it was before).
+template <bool CL>
+__device__ __forceinline__ uint4 ld_line16(const uint4 *p) {
+    if constexpr (CL) {
+        const uint64_t *q = reinterpret_cast<const uint64_t *>(p);
+        const uint64_t a = ld_coherent(q), b = ld_coherent(q + 1);
+        return make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
+    } else {
+        return *p;
+    }
+}
+
 // Compiler-level acquire after observing DONE (the hardware already orders
 // the dependent loads after the observed load).
 __device__ __forceinline__ void after_done_observed() {
@@ -225,14 +239,14 @@ struct Group {
 // chunks sub, sub + G, ..., so every load instruction of the group covers one
 // contiguous 16*G-byte segment of the line.  With G >= LS every lane below
 // LS loads one slot and the others only take part in the ballots.
-template <int G, uint32_t LS>
+template <int G, uint32_t LS, bool CL = false>
 __device__ __forceinline__ void line_masks(const Group<G> &g, const uint64_t *line_ptr, uint64_t memo,
                                            uint32_t &empty, uint32_t &match) {
     constexpr uint32_t SPL = LS / G;
     uint32_t e = 0, m = 0;
     if constexpr (SPL <= 1) {
         const bool own = (uint32_t)G == LS || g.sub < LS;
-        const uint64_t s0 = own ? line_ptr[g.sub] : ~0ull;
+        const uint64_t s0 = own ? (CL ? ld_coherent(line_ptr + g.sub) : line_ptr[g.sub]) : ~0ull;
         constexpr uint32_t lm = LS == 32 ? 0xFFFFFFFFu : (1u << LS) - 1u;
         e = g.bits(__ballot(own && s0 == 0)) & lm;
         m = g.bits(__ballot(own && (s0 & ~kDone) == memo)) & lm;
@@ -242,7 +256,7 @@ __device__ __forceinline__ void line_masks(const Group<G> &g, const uint64_t *li
         uint4 x[Q];
 #pragma unroll
         for (uint32_t q = 0; q < Q; ++q)
-            x[q] = p[q * G + g.sub];
+            x[q] = ld_line16<CL>(p + q * G + g.sub);
 #pragma unroll
         for (uint32_t q = 0; q < Q; ++q) {
             const uint64_t s0 = ((uint64_t)x[q].y << 32) | x[q].x;
@@ -327,7 +341,7 @@ __device__ __forceinline__ bool row_equals(const Group<G> &g, const uint32_t *ro
 // slot claimed by a group of its own wavefront therefore finds it already
 // published; a claim made by another wavefront is published without that
 // wavefront waiting on anything first.
-template <int G, uint32_t LS, class Vec>
+template <int G, uint32_t LS, class Vec, bool CL = false>
 __device__ __forceinline__ void find_or_put(const TableView &t, const Vec &v, uint64_t h, bool active,
                                             uint32_t &out_slot, uint32_t &out_code,
                                             LaneCounters &cnt) {
@@ -353,7 +367,7 @@ __device__ __forceinline__ void find_or_put(const TableView &t, const Vec &v, ui
                 break;
             }
             uint32_t e, m;
-            line_masks<G, LS>(g, t.bucket + (uint64_t)line * LS, memo, e, m);
+            line_masks<G, LS, CL>(g, t.bucket + (uint64_t)line * LS, memo, e, m);
             empty = rotr_line<LS>(e, start);
             cand = rotr_line<LS>(e | m, start);
             have_line = true;
@@ -452,7 +466,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Masks (bit i = slot i of the line) of empty, memo-matching and done slots
 // for every lane with `need`; other lanes only help.  Wavefront-uniform call.
 // C = LS/2 helper lanes per line, 64/C lines per load instruction, C rounds.
-template <uint32_t LS>
+template <uint32_t LS, bool CL = false>
 __device__ __forceinline__ void coop_line_masks(WaveScratch<LS> *ws, const uint64_t *bucket, bool need,
                                                 uint32_t line, uint64_t memo, uint32_t &empty,
                                                 uint32_t &match, uint32_t &done) {
@@ -472,7 +486,7 @@ __device__ __forceinline__ void coop_line_masks(WaveScratch<LS> *ws, const uint6
     for (uint32_t q = 0; q < C; ++q) {
         const uint32_t i = q * LPQ + (lane >> CS);
         if (i < nn)
-            x[q] = reinterpret_cast<const uint4 *>(bucket + (uint64_t)ws->idx[i] * LS)[c];
+            x[q] = ld_line16<CL>(reinterpret_cast<const uint4 *>(bucket + (uint64_t)ws->idx[i] * LS) + c);
     }
 #pragma unroll
     for (uint32_t q = 0; q < C; ++q) {
@@ -596,7 +610,7 @@ __device__ __forceinline__ bool coop_rows_equal(WS *ws, const uint32_t *smem,
 //
 // All 64 lanes must call this together (inactive lanes only help).  `d` is
 // the lane's vector descriptor (Vec::decode(smem, d) rebuilds it in any lane).
-template <uint32_t LS, class Vec>
+template <uint32_t LS, class Vec, bool CL = false>
 __device__ __forceinline__ void find_or_put_wave(const TableView &t, WaveScratch<LS> *ws,
                                                  const uint32_t *smem, uint2 d, uint64_t h,
                                                  bool active, uint32_t &out_slot,
@@ -620,7 +634,7 @@ __device__ __forceinline__ void find_or_put_wave(const TableView &t, WaveScratch
         const bool need = !finished && !have_line;
         if (__ballot(need)) {
             uint32_t e = 0, m = 0, dn = 0;
-            coop_line_masks<LS>(ws, t.bucket, need, line, memo, e, m, dn);
+            coop_line_masks<LS, CL>(ws, t.bucket, need, line, memo, e, m, dn);
             if (need) {
                 empty = rotr_line<LS>(e, start);
                 cand = rotr_line<LS>(e | m, start);

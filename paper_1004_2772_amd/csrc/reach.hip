@@ -236,6 +236,8 @@ ModelView model_view(const reach_model *m, const uint2 *d_trans) {
     const uint32_t PK = v.P * v.K;
     v.magic_PK = PK == 1 ? 0u : (uint32_t)(((1ull << 32) + PK - 1) / PK);
     v.magic_K = v.K == 1 ? 0u : (uint32_t)(((1ull << 32) + v.K - 1) / v.K);
+    v.pad = 0;
+    v.key = 0;
     return v;
 }
 

@@ -13,6 +13,9 @@ struct ModelView {
     uint32_t P, L, S, K, W;
     uint32_t magic_PK;   // ceil(2^32 / (P*K)) for __umulhi division
     uint32_t magic_K;
+    uint32_t pad;
+    unsigned long long key;   // tells apart models whose transitions reuse one
+                              // buffer (0 where every model has a buffer of its own)
 };
 
 // Device-side state of a graph-driven exploration (REACH_F_GRAPH): the level

@@ -34,6 +34,7 @@
 #include "batch_kernels.h"
 #include "expand_device.h"
 #include "internal.h"
+#include "persistent.h"
 #include "reach_internal.h"
 
 using namespace lhs;
@@ -166,6 +167,330 @@ __global__ __launch_bounds__(kExpandBlock) void k_step(BatchSlot *slots, uint32_
         *arrived = 0;
 }
 
+// ---- persistent server ------------------------------------------------------
+//
+// One launch of resident workgroups serves every query: the batch's work
+// queue (persistent.h) of (query slot, tile) items, whose last-tile
+// finalisation advances a query's level, plus admission and completion.
+//  * Admission.  The host readies a slot (the query's constants in ms[slot],
+//    its s0 in roots[slot], its table emptied) with copies and a clearing
+//    kernel on its upload stream, then appends the slot to box->admit_slot
+//    and raises box->admit_tail, also by copies, in that order.  An idle
+//    workgroup takes the admission, inserts s0 and expands level 0 itself.
+//  * Completion.  The workgroup that finishes a query posts (slot, error) to
+//    a ring of records in pinned host memory (system scope, the sequence
+//    word last, after the query's progress and level counts are complete).
+//  * Work queue.  Each workgroup holds one queue position, taken with a
+//    fetch-and-add, and polls its cell; between polls it takes admissions.
+//  * Lifetime.  After a while without work, with no query admitted and
+//    unfinished, a workgroup leaves and closes the launch to admissions
+//    (box->closing); every other workgroup leaves once no query is left.
+//    The host starts a new launch when work arrives and the last one has
+//    ended (a query posted to a closing launch waits for the next); before
+//    it, the positions the last launch held unfilled are given back.  A
+//    query wider than the running launch's LDS rows closes it early (the
+//    host sets box->closing) and waits for the next launch, with the
+//    queries behind it.  The
+//    launch leaves one workgroup's room per CU for the host's clearing
+//    kernels.
+// Slots, tables and transition buffers are reused while a launch runs, so
+// everything the host writes is read past the caches (system scope), and
+// slot lines are read with coherent loads (expand_tile's CL).
+constexpr uint32_t kAdmitRing = 2048;      // admission entries (> 2 x max active)
+constexpr uint32_t kDoneRing = 2048;       // completion records (> 2 x max active)
+constexpr uint64_t kServeCells = 1ull << 23;   // work-queue cells (128 MiB)
+constexpr uint32_t kServeMaxLevels = 1u << 16; // levels of one served query
+constexpr uint32_t kIdleSleepMax = 8;      // back-off steps (~0.4 us each) of an idle workgroup
+constexpr uint32_t kIdleLeave = 384;       // checks (~5 ms) finding no query on the GPU
+                                           // before a workgroup leaves
+constexpr uint32_t kStallPolls = 1u << 19; // idle polls (~2 s) without any tile finished while
+                                           // queries are unfinished: the launch has stalled
+
+struct ServeBox {
+    unsigned long long admit_tail;   // admissions posted (host copies)
+    unsigned long long admit_head;   // admissions taken (workgroups)
+    unsigned long long done_tail;    // completion records handed out
+    uint32_t stop;                   // host copy: leave once idle
+    uint32_t closing;                // set by the first workgroup to leave; the
+                                     // host clears it before the next launch
+    uint32_t beat;                   // tiles finished and admissions taken (any launch)
+    uint32_t pad;
+    uint32_t admit_slot[kAdmitRing]; // slot of admission k, at k % kAdmitRing
+};
+
+struct DoneRec {
+    unsigned long long seq;          // position + 1 once the record is complete
+    uint32_t slot, error, n_levels, pad;
+};
+
+__device__ __forceinline__ unsigned long long ld_system(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint32_t ld_system(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// finalize_level's hook: post the finished query's completion record.
+struct ServeDone {
+    ServeBox *box;
+    DoneRec *done;
+    const ModelProgress *mp;
+    __device__ void operator()(uint32_t slot, uint32_t err) const {
+        const unsigned long long pos = atomicAdd(&box->done_tail, 1ull);
+        DoneRec *r = done + (pos % kDoneRing);
+        __hip_atomic_store(&r->slot, slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&r->error, err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&r->n_levels, ld_coherent(&mp[slot].n_levels), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&r->seq, pos + 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+};
+
+// The constants of slot i's query into LDS, read past every cache (the host
+// rewrites them between queries); block-wide.
+static_assert(sizeof(ModelState) % 8 == 0 && sizeof(ModelState) / 8 <= kExpandBlock, "model constants");
+__device__ __forceinline__ void load_model_state(ModelState *dst, const ModelState *src) {
+    constexpr uint32_t n = sizeof(ModelState) / 8;
+    if (threadIdx.x < n)
+        reinterpret_cast<unsigned long long *>(dst)[threadIdx.x] =
+            ld_system(reinterpret_cast<const unsigned long long *>(src) + threadIdx.x);
+    __syncthreads();
+}
+
+// Admit slot i's query (block-wide): progress and level 0, s0 inserted into
+// its (emptied) table and listed as the first frontier.
+template <uint32_t LS>
+__device__ void admit_query(const ModelState &M, ModelProgress *mp, LevelState *lv, uint32_t i,
+                            const uint32_t *roots) {
+    __shared__ uint32_t row[32];
+    const uint32_t tid = threadIdx.x;
+    if (tid < M.m.W)
+        row[tid] = ld_system(roots + 32u * i + tid);
+    __syncthreads();
+    if (tid < 64) {
+        LaneCounters cnt;
+        const LdsRowB v{row};
+        const bool active = tid == 0;
+        uint32_t slot = kNoSlot, code = kFull;
+        const uint64_t h = hash_vec(v, M.m.W, M.t.seed);
+        find_or_put<1, LS, LdsRowB, true>(M.t, v, h, active, slot, code, cnt);
+        if (active) {
+            ModelProgress &P = mp[i];
+            LevelState &L = lv[i];
+            LevelCounters *lc = M.lc;
+            st_coherent(M.fr[0], slot);
+            st_coherent(&P.total, 1ull);
+            st_coherent(&P.edges, 0ull);
+            st_coherent(&P.deadlocks, 0ull);
+            st_coherent(&P.cur, 0u);
+            st_coherent(&P.n_levels, 1u);
+            st_coherent(&P.done, 0u);
+            st_coherent(&P.capped, 0u);
+            st_coherent(&P.overflow, 0u);
+            st_coherent(&P.error, 0u);
+            st_coherent(M.levels, 1ull);
+            st_coherent(&lc->n_next, 0u);
+            st_coherent(&lc->abort, 0u);
+            st_coherent(&lc->edges, 0ull);
+            st_coherent(&lc->deadlocks, 0ull);
+            st_coherent(&L.front, (unsigned long long)M.fr[0]);
+            st_coherent(&L.next, (unsigned long long)M.fr[1]);
+            st_coherent(&L.n_front, 1u);
+            st_coherent(&L.limit, M.cap ? (uint32_t)min<unsigned long long>(M.cap - 1, 0xFFFFFFFFull) : 0xFFFFFFFFu);
+            st_coherent(&L.tiles_total, 1u);
+            st_coherent(&L.tiles_done, 0u);
+            st_coherent(&L.tile_rows, (uint32_t)kExpandBlock);
+            st_coherent(&L.key, M.m.key);
+        }
+        wait_vm_complete();
+    }
+    __syncthreads();
+}
+
+template <int G, uint32_t LS>
+__global__ __launch_bounds__(kExpandBlock) void k_serve(const ModelState *ms, ModelProgress *mp, LevelState *lv,
+                                                        QueueState *qs, QCell *ring, ServeBox *box, DoneRec *done,
+                                                        const uint32_t *roots, uint32_t tcap) {
+    extern __shared__ uint32_t smem[];
+    __shared__ ModelState s_M;               // constants of slot s_M_slot's query
+    __shared__ uint32_t s_act, s_slot, s_tile, s_fin, s_M_slot;
+    enum : uint32_t { kNone = 0, kTile = 1, kAdmit = 2, kLeave = 3 };
+    const uint32_t tid = threadIdx.x;
+    expand_begin();
+    if (tid == 0)
+        s_M_slot = 0xFFFFFFFFu;
+    bool kept = false;       // tile 0 of kept_slot's new level is this workgroup's
+    uint32_t kept_slot = 0;
+    // thread 0: the queue position this workgroup holds (taken with one
+    // fetch-and-add, so workgroups never contend for an item), polls without
+    // work, and idle polls without a beat
+    bool holding = false;
+    unsigned long long pos = 0;
+    uint32_t idle = 0, quiet = 0, stall = 0, last_beat = 0;
+    while (true) {
+        __syncthreads();     // the last decision has been read by every thread
+        if (tid == 0) {
+            uint32_t act = kNone, slot = 0, tile = 0;
+            if (queue_failed(qs)) {
+                act = kLeave;
+            } else if (kept) {
+                act = kTile;
+                slot = kept_slot;
+            } else {
+                if (!holding) {
+                    pos = atomicAdd(&qs->head, 1ull);
+                    holding = true;
+                }
+                QCell *c = ring + (pos & qs->mask);
+                if (ld_coherent(&c->seq) == pos + 1ull) {
+                    slot = ld_coherent(&c->model);
+                    tile = ld_coherent(&c->tile);
+                    wait_vm_complete();   // read before the cell is freed
+                    st_coherent(&c->seq, pos + qs->mask + 1ull);
+                    holding = false;
+                    act = kTile;
+                } else if (idle < 16 || (idle & 3u) == 0) {
+                    // nothing at the held position yet: admissions, or leave
+                    // once idle.  Leaving and admitting race, so each side
+                    // announces itself before it looks at the other (both
+                    // sequentially consistent): an admission counts itself in
+                    // `remaining`, then checks `closing`; a workgroup about to
+                    // leave sets `closing`, then checks `remaining`.  At
+                    // least one sees the other, so no query is admitted to a
+                    // launch whose workgroups have begun to leave.
+                    const bool closing = ld_coherent(&box->closing) != 0u;
+                    const unsigned long long ah = ld_coherent(&box->admit_head);
+                    // acquire: the host's copies of the slot's constants,
+                    // s0 and admission entry precede the tail it raised
+                    if (!closing && ah < __hip_atomic_load(&box->admit_tail, __ATOMIC_ACQUIRE,
+                                                           __HIP_MEMORY_SCOPE_SYSTEM)) {
+                        __hip_atomic_fetch_add(&qs->remaining, 1u, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+                        if (__hip_atomic_load(&box->closing, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT) == 0u &&
+                            atomicCAS(&box->admit_head, ah, ah + 1ull) == ah) {
+                            slot = ld_system(&box->admit_slot[ah % kAdmitRing]);
+                            act = kAdmit;
+                        } else {
+                            atomicSub(&qs->remaining, 1u);
+                        }
+                    } else if (ld_coherent(&qs->remaining) != 0u) {
+                        quiet = 0;
+                    } else if (++quiet >= kIdleLeave || closing || ld_system(&box->stop) != 0u) {
+                        // a read-modify-write even when closing is already
+                        // seen set (the host may have set it): it takes part
+                        // in the order the admissions see
+                        __hip_atomic_exchange(&box->closing, 1u, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+                        // the held position is never filled: no query is
+                        // left, and none can be admitted any more
+                        if (__hip_atomic_load(&qs->remaining, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+                            act = kLeave;
+                    }
+                }
+                if (act == kNone) {
+                    // bounded: with queries unfinished, some workgroup
+                    // finishes a tile every few microseconds
+                    const uint32_t b = ld_coherent(&box->beat);
+                    stall = b == last_beat ? stall + 1u : 0u;
+                    last_beat = b;
+                    if (stall > kStallPolls) {
+                        atomicCAS(&qs->error, 0u, (uint32_t)LHS_ESTALL);
+                        act = kLeave;
+                    }
+                    ++idle;
+                    for (uint32_t k = 0; k < min(idle, kIdleSleepMax); ++k)
+                        __builtin_amdgcn_s_sleep(16);
+                }
+            }
+            if (act == kTile || act == kAdmit) {
+                idle = 0;
+                stall = 0;
+            }
+            s_act = act;
+            s_slot = slot;
+            s_tile = tile;
+        }
+        __syncthreads();
+        const uint32_t act = s_act, i = s_slot, j = s_tile;
+        if (act == kLeave)
+            break;
+        if (act == kNone)
+            continue;
+        if (act == kAdmit) {
+            load_model_state(&s_M, ms + i);
+            if (tid == 0)
+                s_M_slot = i;
+            admit_query<LS>(s_M, mp, lv, i, roots);
+            kept = true;
+            kept_slot = i;
+            continue;
+        }
+        kept = false;
+        LevelState &L = lv[i];
+        // the constants are read again only when the slot holds another query
+        if (s_M_slot != i || s_M.m.key != ld_coherent(&L.key)) {
+            __syncthreads();   // every thread has compared before s_M changes
+            load_model_state(&s_M, ms + i);
+            if (tid == 0)
+                s_M_slot = i;
+        }
+        const uint32_t *front = reinterpret_cast<const uint32_t *>(ld_coherent(&L.front));
+        uint32_t *next = reinterpret_cast<uint32_t *>(ld_coherent(&L.next));
+        const uint32_t n_front = ld_coherent(&L.n_front);
+        const uint32_t limit = ld_coherent(&L.limit);
+        const uint32_t rows_per = ld_coherent(&L.tile_rows);
+        const uint64_t base = (uint64_t)j * rows_per;
+        const uint32_t rows = (uint32_t)min<uint64_t>(rows_per, n_front - base);
+        expand_tile<G, LS, true, false, false, false, true>(smem, s_M.t, s_M.m, front, base, rows, next, s_M.lc,
+                                                            limit, tcap);
+        wait_vm_complete();
+        __syncthreads();
+        if (tid == 0) {
+            const uint32_t total = ld_coherent(&L.tiles_total);
+            wait_vm_complete();
+            s_fin = atomicAdd(&L.tiles_done, 1u) + 1u == total;
+            atomicAdd(&box->beat, 1u);
+        }
+        __syncthreads();
+        if (s_fin && finalize_level<true>(s_M, mp, lv, i, qs, ring, ServeDone{box, done, mp})) {
+            kept = true;
+            kept_slot = i;
+        }
+    }
+}
+
+// Before a launch: positions taken by the workgroups of the last launch and
+// never filled are given back (every filled one was consumed: no query was
+// left), and admissions reopen.
+__global__ void k_serve_reopen(QueueState *qs, ServeBox *box) {
+    qs->head = qs->tail;
+    box->closing = 0;
+}
+
+// Work queue empty, every cell free, admission and completion counters at
+// the host's positions.
+__global__ void k_serve_init(QCell *ring, unsigned long long cells, QueueState *qs, ServeBox *box,
+                             unsigned long long posted, unsigned long long done_head) {
+    for (unsigned long long p = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; p < cells;
+         p += (unsigned long long)gridDim.x * blockDim.x) {
+        ring[p].seq = p;
+        ring[p].model = 0;
+        ring[p].tile = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        qs->head = 0;
+        qs->tail = 0;
+        qs->remaining = 0;
+        qs->error = 0;
+        qs->mask = cells - 1;
+        box->admit_tail = posted;
+        box->admit_head = posted;
+        box->done_tail = done_head;
+        box->stop = 0;
+        box->closing = 0;
+        box->beat = 0;
+        box->pad = 0;
+    }
+}
+
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -199,6 +524,45 @@ struct Query {
     int capped = 0;
     lhs_status status = LHS_OK;
     bool done = false;
+    uint32_t slot = 0xFFFFFFFFu;   // persistent server: its slot while on the GPU
+    uint64_t tiles_bound = 0;      // bound on its items in the work queue
+};
+
+// A query's items in the work queue at once: one level's tiles, full or cut
+// small (persistent.h's level_tile_rows), plus one.
+uint64_t queue_bound(const Query *q) {
+    return std::max<uint64_t>(q->capacity / kExpandBlock, kSmallLevel / kMinTileRows) + 1;
+}
+
+// Worker-owned state of the persistent server.
+struct Persist {
+    hipStream_t up = nullptr;          // uploads, clearing kernels and read-backs
+    hipEvent_t ev_end = nullptr;       // recorded after each launch
+    bool running = false;
+    uint32_t launch_W = 0;             // widest vector the running launch's LDS holds
+    uint64_t launches = 0;
+    ModelState *d_ms = nullptr;
+    ModelProgress *d_mp = nullptr;
+    LevelState *d_lv = nullptr;
+    LevelCounters *d_lc = nullptr;
+    QueueState *d_qs = nullptr;
+    QCell *d_ring = nullptr;
+    ServeBox *d_box = nullptr;
+    uint32_t *d_roots = nullptr;                  // [slot][32]
+    std::vector<unsigned long long *> d_levels;   // [slot] -> level counts, on first use
+    DoneRec *h_done = nullptr;                    // pinned; written by the device
+    DoneRec *h_done_dev = nullptr;                // ... its device address
+    ModelProgress *h_prog = nullptr;              // pinned read-backs
+    unsigned long long *h_lv = nullptr;
+    DevStatus *h_tst = nullptr;
+    QueueState *h_qs = nullptr;
+    uint32_t *h_word = nullptr;                   // pinned {0, 1}: box flag values
+    bool stop_sent = false;
+    bool close_sent = false;                      // the running launch was asked to drain
+    std::vector<Query *> slot_q;                  // query in each slot
+    std::vector<uint32_t> free_slots;
+    uint32_t live = 0;                            // posted and not yet completed
+    uint64_t posted = 0, done_head = 0, outstanding = 0;
 };
 
 uint64_t table_bytes(uint64_t capacity, uint32_t W) {
@@ -238,6 +602,9 @@ struct reach_server {
     void *h_stage = nullptr;
     size_t cap_stage = 0;
     std::multimap<size_t, uint2 *> trans_pool;
+    // persistent server (the default; REACH_SERVER_F_ROUNDS: host rounds)
+    bool persistent = false;
+    Persist ps;
     // stats (under mu)
     reach_server_stats stats{};
     double busy_s = 0;
@@ -546,6 +913,398 @@ lhs_status step_queries(reach_server *s, std::vector<Query *> &finished) {
     return LHS_OK;
 }
 
+// ---- persistent server: host side (worker thread) -------------------------
+lhs_status persist_reset(reach_server *s) {
+    Persist &P = s->ps;
+    hipLaunchKernelGGL(k_serve_init, dim3(4096), dim3(256), 0, P.up, P.d_ring, (unsigned long long)kServeCells,
+                       P.d_qs, P.d_box, (unsigned long long)P.posted, (unsigned long long)P.done_head);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(P.up) != hipSuccess)
+        return LHS_EDEVICE;
+    return LHS_OK;
+}
+
+lhs_status persist_init(reach_server *s) {
+    Persist &P = s->ps;
+    const uint32_t n = s->opts.max_active;
+    if (hipStreamCreateWithFlags(&P.up, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&P.ev_end, hipEventDisableTiming) != hipSuccess)
+        return LHS_EDEVICE;
+    if (hipMalloc(&P.d_ms, n * sizeof(ModelState)) != hipSuccess ||
+        hipMalloc(&P.d_mp, n * sizeof(ModelProgress)) != hipSuccess ||
+        hipMalloc(&P.d_lv, n * sizeof(LevelState)) != hipSuccess ||
+        hipMalloc(&P.d_lc, n * sizeof(LevelCounters)) != hipSuccess ||
+        hipMalloc(&P.d_qs, sizeof(QueueState)) != hipSuccess ||
+        hipMalloc(&P.d_ring, kServeCells * sizeof(QCell)) != hipSuccess ||
+        hipMalloc(&P.d_box, sizeof(ServeBox)) != hipSuccess ||
+        hipMalloc(&P.d_roots, (size_t)n * 32 * sizeof(uint32_t)) != hipSuccess ||
+        hipHostMalloc(&P.h_done, kDoneRing * sizeof(DoneRec), hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc(&P.h_prog, sizeof(ModelProgress), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&P.h_lv, kServeMaxLevels * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&P.h_tst, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&P.h_qs, sizeof(QueueState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&P.h_word, 2 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return LHS_ENOMEM;
+    }
+    std::memset(P.h_done, 0, kDoneRing * sizeof(DoneRec));
+    P.h_word[0] = 0;
+    P.h_word[1] = 1;
+    void *dev = nullptr;
+    if (hipHostGetDevicePointer(&dev, P.h_done, 0) != hipSuccess)
+        return LHS_EDEVICE;
+    P.h_done_dev = static_cast<DoneRec *>(dev);
+    P.slot_q.assign(n, nullptr);
+    P.d_levels.assign(n, nullptr);
+    for (uint32_t i = n; i-- > 0;)
+        P.free_slots.push_back(i);
+    return persist_reset(s);
+}
+
+void persist_free(reach_server *s) {
+    Persist &P = s->ps;
+    (void)hipFree(P.d_ms);
+    (void)hipFree(P.d_mp);
+    (void)hipFree(P.d_lv);
+    (void)hipFree(P.d_lc);
+    (void)hipFree(P.d_qs);
+    (void)hipFree(P.d_ring);
+    (void)hipFree(P.d_box);
+    (void)hipFree(P.d_roots);
+    for (auto p : P.d_levels)
+        (void)hipFree(p);
+    for (void *h : {(void *)P.h_done, (void *)P.h_prog, (void *)P.h_lv, (void *)P.h_tst, (void *)P.h_qs, (void *)P.h_word})
+        if (h)
+            (void)hipHostFree(h);
+    if (P.ev_end)
+        (void)hipEventDestroy(P.ev_end);
+    if (P.up)
+        (void)hipStreamDestroy(P.up);
+}
+
+// Ready the slots of newly admitted queries and post them to the running
+// (or next) launch: transitions uploaded, tables emptied, each slot's
+// constants and s0 written, then the admission entries, then the tail.
+lhs_status persist_post(reach_server *s, const std::vector<Query *> &qs) {
+    Persist &P = s->ps;
+    if (qs.empty())
+        return LHS_OK;
+    const uint32_t n = (uint32_t)qs.size();
+    Carve c;
+    const size_t o_ms = c.take<ModelState>(n), o_roots = c.take<uint32_t>((size_t)n * 32),
+                 o_adm = c.take<uint32_t>(n), o_tail = c.take<unsigned long long>(1);
+    size_t n_trans = 0;
+    for (Query *q : qs)
+        n_trans += (size_t)q->m.n_procs * q->m.n_locals * q->m.trans_per_local;
+    const size_t o_trans = c.take<uint2>(n_trans);
+    if (c.off > s->cap_stage) {
+        if (s->h_stage)
+            (void)hipHostFree(s->h_stage);
+        s->h_stage = nullptr;
+        s->cap_stage = 0;
+        size_t cap = 1 << 20;
+        while (cap < c.off)
+            cap <<= 1;
+        if (hipHostMalloc(&s->h_stage, cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            s->h_stage = nullptr;
+            return LHS_ENOMEM;
+        }
+        s->cap_stage = cap;
+    }
+    ModelState *ms = at<ModelState>(s->h_stage, o_ms);
+    uint32_t *roots = at<uint32_t>(s->h_stage, o_roots), *adm = at<uint32_t>(s->h_stage, o_adm);
+    uint2 *trans = at<uint2>(s->h_stage, o_trans);
+    std::memset(roots, 0, (size_t)n * 32 * sizeof(uint32_t));
+    size_t t_at = 0;
+    std::vector<uint2> packed;
+    for (uint32_t k = 0; k < n; ++k) {
+        Query *q = qs[k];
+        const uint32_t slot = P.free_slots.back();
+        P.free_slots.pop_back();
+        P.slot_q[slot] = q;
+        q->slot = slot;
+        ++P.live;
+        P.outstanding += q->tiles_bound;
+        if (!P.d_levels[slot] &&
+            hipMalloc(&P.d_levels[slot], kServeMaxLevels * sizeof(unsigned long long)) != hipSuccess) {
+            (void)hipGetLastError();
+            P.d_levels[slot] = nullptr;
+            return LHS_ENOMEM;
+        }
+        pack_model(&q->m, packed);
+        const size_t bytes = packed.size() * sizeof(uint2);
+        auto it = s->trans_pool.find(trans_class(bytes));
+        if (it != s->trans_pool.end()) {
+            q->d_trans = it->second;
+            s->trans_pool.erase(it);
+        } else if (hipMalloc(&q->d_trans, trans_class(bytes)) != hipSuccess) {
+            (void)hipGetLastError();
+            q->d_trans = nullptr;
+            return LHS_ENOMEM;
+        }
+        std::memcpy(trans + t_at, packed.data(), bytes);
+        LHS_HIP(hipMemcpyAsync(q->d_trans, trans + t_at, bytes, hipMemcpyHostToDevice, P.up));
+        t_at += packed.size();
+        q->t->last_stream = P.up;
+        if (lhs_clear(q->t, P.up) != LHS_OK)
+            return LHS_EDEVICE;
+        ModelState &M = ms[k];
+        std::memset(&M, 0, sizeof(M));
+        M.t = view(q->t);
+        M.m = model_view(&q->m, q->d_trans);
+        M.m.key = q->ticket;   // unique and nonzero: a later query may reuse this transition buffer
+        M.lc = P.d_lc + slot;
+        M.fr[0] = q->t->frontier[0];
+        M.fr[1] = q->t->frontier[1];
+        M.levels = P.d_levels[slot];
+        M.cap = q->m.state_cap;
+        M.max_levels = kServeMaxLevels;
+        std::memcpy(roots + 32 * k, q->init.data(), q->W * sizeof(uint32_t));
+        adm[k] = slot;
+        LHS_HIP(hipMemcpyAsync(P.d_ms + slot, &M, sizeof(M), hipMemcpyHostToDevice, P.up));
+        LHS_HIP(hipMemcpyAsync(P.d_roots + 32 * slot, roots + 32 * k, 32 * sizeof(uint32_t), hipMemcpyHostToDevice,
+                               P.up));
+        LHS_HIP(hipMemcpyAsync(&P.d_box->admit_slot[(P.posted + k) % kAdmitRing], adm + k, sizeof(uint32_t),
+                               hipMemcpyHostToDevice, P.up));
+    }
+    // the tail last: a workgroup that sees it finds every entry below it
+    P.posted += n;
+    *at<unsigned long long>(s->h_stage, o_tail) = P.posted;
+    LHS_HIP(hipMemcpyAsync(&P.d_box->admit_tail, at<unsigned long long>(s->h_stage, o_tail),
+                           sizeof(unsigned long long), hipMemcpyHostToDevice, P.up));
+    // the staging is reused by the next admission
+    LHS_HIP(hipStreamSynchronize(P.up));
+    return LHS_OK;
+}
+
+// Launch for the queries on the GPU: LDS for the widest of them, one
+// workgroup's room per CU left for the host's clearing kernels.
+lhs_status persist_launch(reach_server *s) {
+    Persist &P = s->ps;
+    uint32_t maxW = 1, tcap = 0;
+    for (Query *q : P.slot_q)
+        if (q) {
+            maxW = std::max(maxW, q->W);
+            tcap = std::max(tcap, trans_lds_entries(q->m.n_procs, q->m.n_locals, q->m.trans_per_local));
+        }
+    const uint32_t tps = s->cfg.tps_expand ? s->cfg.tps_expand : kDefaultTpsExpand;
+    const size_t lds = (size_t)expand_lds_words(maxW, tcap, tps) * sizeof(uint32_t);
+    const lhs_status rc = with_shape(tps, s->cfg.line_slots, [&](auto G, auto L) {
+        const void *fn = (const void *)k_serve<decltype(G)::value, decltype(L)::value>;
+        int ncu = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kExpandBlock, lds) != hipSuccess ||
+            per_cu < 1)
+            return LHS_EDEVICE;
+        const uint32_t grid = (uint32_t)ncu * (uint32_t)std::max(1, per_cu - 1);
+        hipLaunchKernelGGL(k_serve_reopen, dim3(1), dim3(1), 0, s->stream, P.d_qs, P.d_box);
+        hipLaunchKernelGGL((k_serve<decltype(G)::value, decltype(L)::value>), dim3(grid), dim3(kExpandBlock), lds,
+                           s->stream, (const ModelState *)P.d_ms, P.d_mp, P.d_lv, P.d_qs, P.d_ring, P.d_box,
+                           P.h_done_dev, (const uint32_t *)P.d_roots, tcap);
+        return hipGetLastError() == hipSuccess ? LHS_OK : LHS_EDEVICE;
+    });
+    if (rc != LHS_OK)
+        return rc;
+    LHS_HIP(hipEventRecord(P.ev_end, s->stream));
+    P.running = true;
+    P.close_sent = false;
+    P.launch_W = maxW;
+    ++P.launches;
+    return LHS_OK;
+}
+
+// Collect the completion records the device has written.
+lhs_status persist_collect(reach_server *s, std::vector<Query *> &finished) {
+    Persist &P = s->ps;
+    while (true) {
+        DoneRec &r = P.h_done[P.done_head % kDoneRing];
+        if (__atomic_load_n(&r.seq, __ATOMIC_ACQUIRE) != P.done_head + 1)
+            break;
+        const uint32_t slot = r.slot, err = r.error, nl = std::min(r.n_levels, kServeMaxLevels);
+        ++P.done_head;
+        if (slot >= P.slot_q.size() || !P.slot_q[slot])
+            return LHS_EDEVICE;
+        Query *q = P.slot_q[slot];
+        LHS_HIP(hipMemcpyAsync(P.h_prog, P.d_mp + slot, sizeof(ModelProgress), hipMemcpyDeviceToHost, P.up));
+        LHS_HIP(hipMemcpyAsync(P.h_lv, P.d_levels[slot], nl * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                               P.up));
+        LHS_HIP(hipMemcpyAsync(P.h_tst, q->t->status, sizeof(DevStatus), hipMemcpyDeviceToHost, P.up));
+        LHS_HIP(hipStreamSynchronize(P.up));
+        const ModelProgress &M = *P.h_prog;
+        q->levels.assign(P.h_lv, P.h_lv + nl);
+        q->total = M.total;
+        q->edges = M.edges;
+        q->dead = M.deadlocks;
+        q->capped = (int)M.capped;
+        q->wait_hits = P.h_tst->wait_hits;
+        q->status = err ? (lhs_status)err : (M.overflow ? LHS_EINVAL : LHS_OK);
+        P.slot_q[slot] = nullptr;
+        P.free_slots.push_back(slot);
+        --P.live;
+        P.outstanding -= q->tiles_bound;
+        q->slot = 0xFFFFFFFFu;
+        finished.push_back(q);
+    }
+    return LHS_OK;
+}
+
+// After a launch ended: a queue failure ends every query on the GPU and
+// starts the device state afresh.
+lhs_status persist_after_launch(reach_server *s, std::vector<Query *> &finished) {
+    Persist &P = s->ps;
+    P.running = false;
+    lhs_status rc = persist_collect(s, finished);
+    if (rc != LHS_OK)
+        return rc;
+    LHS_HIP(hipMemcpyAsync(P.h_qs, P.d_qs, sizeof(QueueState), hipMemcpyDeviceToHost, P.up));
+    LHS_HIP(hipStreamSynchronize(P.up));
+    if (!P.h_qs->error)
+        return LHS_OK;
+    const lhs_status err = (lhs_status)P.h_qs->error;
+    for (uint32_t i = 0; i < P.slot_q.size(); ++i)
+        if (Query *q = P.slot_q[i]) {
+            q->status = err;
+            P.slot_q[i] = nullptr;
+            P.free_slots.push_back(i);
+            finished.push_back(q);
+        }
+    P.live = 0;
+    P.outstanding = 0;
+    return persist_reset(s);
+}
+
+void persist_worker(reach_server *s) {
+    (void)hipSetDevice(s->device);
+    Persist &P = s->ps;
+    double busy_since = 0;
+    while (true) {
+        std::vector<Query *> admitted, finished;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            while (s->queue.empty() && P.live == 0 && !P.running && !s->stop)
+                s->cv_work.wait(lk);
+            if (s->stop && s->queue.empty() && P.live == 0 && !P.running)
+                return;
+            // first come first served, while a slot, room in the work queue
+            // and the budget allow; a query wider than the running launch's
+            // LDS waits for the next launch (and holds the queries behind it)
+            bool drain = false;
+            while (!s->queue.empty() && admitted.size() < P.free_slots.size()) {
+                Query *q = s->queue.front();
+                if (P.running && q->W > P.launch_W) {
+                    drain = true;
+                    break;
+                }
+                q->tiles_bound = queue_bound(q);
+                if (P.outstanding + q->tiles_bound > kServeCells / 2)
+                    break;
+                if (!acquire_table(s, q)) {
+                    if (P.live == 0 && admitted.empty() && s->pool.empty()) {
+                        s->queue.pop_front();
+                        q->status = LHS_ENOMEM;
+                        q->t_admit = q->t_done = now_s();
+                        q->done = true;
+                        s->stats.completed += 1;
+                        s->cv_done.notify_all();
+                        continue;
+                    }
+                    break;
+                }
+                s->queue.pop_front();
+                q->t_admit = now_s();
+                admitted.push_back(q);
+            }
+            s->stats.active = P.live + (uint32_t)admitted.size();
+            s->stats.queued = (uint32_t)s->queue.size();
+            s->stats.bytes_in_use = s->bytes_alloc;
+            s->stats.peak_bytes = std::max(s->stats.peak_bytes, s->bytes_alloc);
+            if (P.live == 0 && !admitted.empty())
+                busy_since = now_s();
+            if (drain && !P.close_sent) {
+                // the running launch admits no more queries and ends once
+                // its queries are done; the next one has room for this one
+                (void)hipMemcpyAsync(&P.d_box->closing, P.h_word + 1, sizeof(uint32_t), hipMemcpyHostToDevice,
+                                     P.up);
+                P.close_sent = true;
+            }
+        }
+        bool progress = !admitted.empty();
+        lhs_status rc = lhs::guard([&] { return persist_post(s, admitted); });
+        if (rc != LHS_OK) {
+            // the slots of the failed admissions are in an unknown state: end
+            // every query on the GPU and start over
+            for (Query *q : admitted)
+                if (q->slot == 0xFFFFFFFFu) {
+                    q->status = rc;
+                    finished.push_back(q);
+                }
+        }
+        if (rc == LHS_OK && !P.running && P.live > 0)
+            rc = lhs::guard([&] { return persist_launch(s); });
+        if (rc == LHS_OK) {
+            const size_t before = finished.size();
+            rc = lhs::guard([&] { return persist_collect(s, finished); });
+            progress |= finished.size() > before;
+        }
+        if (rc == LHS_OK && P.running) {
+            const hipError_t q = hipEventQuery(P.ev_end);
+            if (q == hipSuccess)
+                rc = lhs::guard([&] { return persist_after_launch(s, finished); });
+            else if (q != hipErrorNotReady)
+                rc = LHS_EDEVICE;
+        }
+        if (rc != LHS_OK) {
+            // a device failure ends every query on the GPU
+            if (P.running)
+                (void)hipEventSynchronize(P.ev_end);
+            P.running = false;
+            for (uint32_t i = 0; i < P.slot_q.size(); ++i)
+                if (Query *q = P.slot_q[i]) {
+                    q->status = rc;
+                    P.slot_q[i] = nullptr;
+                    P.free_slots.push_back(i);
+                    finished.push_back(q);
+                }
+            P.live = 0;
+            P.outstanding = 0;
+            (void)persist_reset(s);
+        }
+        const double t1 = now_s();
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            if (rc != LHS_OK)
+                s->fatal = rc;
+            for (Query *q : finished) {
+                release_table(s, q);
+                q->t_done = t1;
+                q->done = true;
+                s->stats.completed += 1;
+                if (q->status == LHS_OK)
+                    s->stats.states += q->total;
+            }
+            s->stats.steps = P.launches;
+            if (!finished.empty() && P.live == 0) {
+                s->busy_s += t1 - busy_since;
+                busy_since = t1;
+            }
+            uint64_t pooled = 0;
+            for (auto &e : s->pool)
+                pooled += table_bytes(e.second->capacity, e.second->W);
+            s->stats.bytes_pooled = pooled;
+            if (!finished.empty())
+                s->cv_done.notify_all();
+            if (s->stop && s->queue.empty() && P.live == 0 && P.running && !P.stop_sent) {
+                // let idle workgroups leave at once
+                (void)hipMemcpyAsync(&P.d_box->stop, P.h_word + 1, sizeof(uint32_t), hipMemcpyHostToDevice, P.up);
+                P.stop_sent = true;
+            }
+        }
+        // completion records are polled while a launch runs
+        if (!progress)
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
 void worker_main(reach_server *s) {
     (void)hipSetDevice(s->device);
     while (true) {
@@ -685,7 +1444,7 @@ static lhs_status reach_server_create_impl(const reach_server_opts *o, reach_ser
         s->opts.budget_bytes = kDefaultBudget;
     if (!s->opts.max_active)
         s->opts.max_active = kDefaultMaxActive;
-    if (s->opts.max_active > kDefaultMaxActive) {
+    if (s->opts.max_active > kDefaultMaxActive || (s->opts.flags & ~REACH_SERVER_F_ROUNDS)) {
         delete s;
         return LHS_EINVAL;
     }
@@ -708,12 +1467,21 @@ static lhs_status reach_server_create_impl(const reach_server_opts *o, reach_ser
         delete s;
         return LHS_EDEVICE;
     }
-    try {
-        s->worker = std::thread(worker_main, s);
-    } catch (...) {
+    s->persistent = !(s->opts.flags & REACH_SERVER_F_ROUNDS);
+    lhs_status rc = s->persistent ? persist_init(s) : LHS_OK;
+    if (rc == LHS_OK) {
+        try {
+            s->worker = std::thread(s->persistent ? persist_worker : worker_main, s);
+        } catch (...) {
+            rc = LHS_ENOMEM;
+        }
+    }
+    if (rc != LHS_OK) {
+        if (s->persistent)
+            persist_free(s);
         (void)hipStreamDestroy(s->stream);
         delete s;
-        throw;
+        return rc;
     }
     *out = s;
     return LHS_OK;
@@ -762,6 +1530,9 @@ static lhs_status reach_server_submit_impl(reach_server *s, const reach_model *m
             return LHS_EBUDGET;
     }
     q->limit = m->state_cap ? (uint32_t)std::min<uint64_t>(m->state_cap - 1, 0xFFFFFFFFull) : 0xFFFFFFFFu;
+    // the persistent work queue holds a full level of every query on the GPU
+    if (s->persistent && queue_bound(q.get()) > kServeCells / 2)
+        return LHS_EINVAL;
     q->levels.push_back(1);
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop)
@@ -860,6 +1631,10 @@ lhs_status reach_server_destroy(reach_server *s) {
             e.second->caller->served_by = nullptr;
         }
         delete e.second;
+    }
+    if (s->persistent) {
+        (void)hipStreamSynchronize(s->ps.up);
+        persist_free(s);
     }
     free_step_buffers(s);
     (void)hipFree(s->d_roots);

@@ -25,12 +25,17 @@ def lhs():
     return paper_1004_2772_amd
 
 
+# the persistent launch (default) and host rounds of level steps
+MODES = pytest.mark.parametrize("rounds", [False, True], ids=["persistent", "rounds"])
+
+
 def _golden_mix():
     with open(os.path.join(GOLDEN, "batch_models.json")) as f:
         return json.load(f)["models"]
 
 
-def test_serve_mix_matches_oracle(lhs):
+@MODES
+def test_serve_mix_matches_oracle(lhs, rounds):
     """48 queries drawn from the 64-model mix arrive at about 400/s, each on a
     caller table; every result, the reachable set included, equals the
     oracle's, and queries overlap on the GPU."""
@@ -39,11 +44,11 @@ def test_serve_mix_matches_oracle(lhs):
     rng = np.random.default_rng(4)
     picks = rng.integers(0, len(models), size=48)
     gaps = rng.exponential(1 / 400.0, size=len(picks))      # ~400 queries/s
-    print("\n[serve] 48 queries from the mix, caller tables", flush=True)
+    print(f"\n[serve] 48 queries from the mix, caller tables, rounds={rounds}", flush=True)
     cfg = lhs.config()
     tables = [lhs.Table(1 << 21, models[k].W, cfg) for k in picks]
     try:
-        with lhs.Server(capacity=1 << 21, cfg=cfg) as srv:
+        with lhs.Server(capacity=1 << 21, cfg=cfg, rounds=rounds) as srv:
             tickets = []
             for k, gap, t in zip(picks, gaps, tables):
                 time.sleep(gap)
@@ -77,7 +82,8 @@ def test_serve_mix_matches_oracle(lhs):
     assert overlaps > 0
 
 
-def test_serve_equals_alone(lhs):
+@MODES
+def test_serve_equals_alone(lhs, rounds):
     """Capped and uncapped queries, all submitted at once: each served result
     and set equals the model explored alone (reach_explore on its own table)
     and the oracle's; a capped query's table holds only the kept levels."""
@@ -97,7 +103,7 @@ def test_serve_equals_alone(lhs):
             alone_rows.append(t.dump()[0])
     tables = [lhs.Table(1 << 17, m.W, cfg) for m in models]
     try:
-        with lhs.Server(capacity=1 << 17, cfg=cfg) as srv:
+        with lhs.Server(capacity=1 << 17, cfg=cfg, rounds=rounds) as srv:
             ts = [srv.submit(m, table=t) for m, t in zip(models, tables)]
             got = [srv.wait(t)[0] for t in ts]
         n_capped = 0
@@ -115,11 +121,12 @@ def test_serve_equals_alone(lhs):
             t.close()
 
 
-def test_serve_caller_table_rules(lhs):
+@MODES
+def test_serve_caller_table_rules(lhs, rounds):
     """A caller table must match the query's width and the server's line
     width, and serves one query at a time; it is free again once collected."""
     m = gen.tiny_cyclic()
-    with lhs.Server(capacity=1 << 16, cfg=lhs.config(line_slots=16)) as srv:
+    with lhs.Server(capacity=1 << 16, cfg=lhs.config(line_slots=16), rounds=rounds) as srv:
         with lhs.Table(1 << 16, m.W + 1, lhs.config(line_slots=16)) as wide, \
                 lhs.Table(1 << 16, m.W, lhs.config(line_slots=8)) as narrow, \
                 lhs.Table(1 << 16, m.W, lhs.config(line_slots=16)) as ok:
@@ -141,11 +148,12 @@ def test_serve_caller_table_rules(lhs):
             assert e.value.name == "LHS_EINVAL"
 
 
-def test_serve_small_budget_queues(lhs):
+@MODES
+def test_serve_small_budget_queues(lhs, rounds):
     # room for two 2^16-slot tables of width <= 16 at a time
     models = [gen.big_model(cap=20_000 + 1000 * i) for i in range(8)]
     budget = 2 * ((1 << 16) * (8 + 4 * 16 + 8) + 4096) + 1000
-    with lhs.Server(budget_bytes=budget, capacity=1 << 16) as srv:
+    with lhs.Server(budget_bytes=budget, capacity=1 << 16, rounds=rounds) as srv:
         ts = [srv.submit(m) for m in models]
         got = [srv.wait(t)[0] for t in ts]
         st = srv.stats()
@@ -154,8 +162,9 @@ def test_serve_small_budget_queues(lhs):
         assert result_fields(g) == result_fields(oracle.reach(m))
 
 
-def test_serve_errors(lhs):
-    with lhs.Server(budget_bytes=1 << 20, capacity=1 << 12) as srv:
+@MODES
+def test_serve_errors(lhs, rounds):
+    with lhs.Server(budget_bytes=1 << 20, capacity=1 << 12, rounds=rounds) as srv:
         big = gen.guarded_model(5, 4, 8, 2, 3, 3)
         with pytest.raises(lhs.LhsError) as e:
             lhs.Server(capacity=24)
@@ -172,10 +181,17 @@ def test_serve_errors(lhs):
             srv.poll(good)
         assert e.value.name == "LHS_ENOTFOUND"
         del big
-    with lhs.Server(budget_bytes=1 << 20, capacity=1 << 16) as srv:
+    with lhs.Server(budget_bytes=1 << 20, capacity=1 << 16, rounds=rounds) as srv:
         with pytest.raises(lhs.LhsError) as e:
             srv.submit(gen.tiny_cyclic())                 # a 2^16-slot table never fits 1 MiB
         assert e.value.name == "LHS_EBUDGET"
+    if not rounds:
+        # the work queue holds a full level of each query: 2^31-slot tables
+        # are for the rounds server
+        with lhs.Server(capacity=1 << 31) as srv:
+            with pytest.raises(lhs.LhsError) as e:
+                srv.submit(gen.tiny_cyclic())
+            assert e.value.name == "LHS_EINVAL"
 
 
 def test_serve_client_threads(lhs):
@@ -230,3 +246,98 @@ def test_serve_client_threads(lhs):
         assert not any(t.is_alive() for t in ws)
         assert sorted(map(str, out)) == ["LHS_ENOTFOUND", "True"]
         assert srv.stats()["completed"] == 4 * 6 + 1
+
+
+def test_serve_persistent_relaunch_and_wider_query(lhs):
+    """The persistent launch ends once idle and a later query starts a new
+    one; a query wider than the running launch's rows waits for the next
+    launch (and holds the queries behind it); every result equals the
+    oracle's."""
+    models = gen.batch_models()
+    golden = _golden_mix()
+    narrow = [k for k, m in enumerate(models) if m.W <= 8][:6]
+    wide = max(range(len(models)), key=lambda k: models[k].W)
+    assert models[wide].W > 8
+    print(f"\n[serve] relaunch; narrow {narrow}, wide {wide}", flush=True)
+
+    def check(k, r):
+        g = golden[k]
+        assert (r.total, r.n_levels, r.level_counts, r.edges, r.deadlocks, r.capped) == \
+            (g["total"], g["n_levels"], g["level_counts"], g["edges"], g["deadlocks"], g["capped"]), k
+
+    with lhs.Server(capacity=1 << 21) as srv:
+        k0 = narrow[0]
+        check(k0, srv.wait(srv.submit(models[k0]))[0])
+        time.sleep(0.5)                                 # the launch has ended meanwhile
+        l1 = srv.stats()["steps"]
+        check(k0, srv.wait(srv.submit(models[k0]))[0])
+        assert srv.stats()["steps"] == l1 + 1
+        ks = narrow + [wide] + narrow
+        ts = [(k, srv.submit(models[k])) for k in ks]
+        for k, t in ts:
+            check(k, srv.wait(t)[0])
+        assert srv.stats()["completed"] == 2 + len(ks)
+
+
+def test_serve_reused_transition_buffer(lhs):
+    """A query whose transition buffer is handed on to the next query while
+    the launch keeps running (large queries hold it open): workgroups that
+    cached the first query's transitions in LDS must not use them for the
+    second.  Both results equal the oracle's."""
+    models = gen.batch_models()
+    golden = _golden_mix()
+    big = sorted(range(len(models)), key=lambda k: -golden[k]["total"])[:4]
+    a = gen.guarded_model(7101, 5, 6, 2, 3, 3, cap=30_000)
+    b = gen.guarded_model(7102, 5, 6, 2, 3, 3, cap=30_000)     # same sizes, other transitions
+    wa, wb = result_fields(oracle.reach(a)), result_fields(oracle.reach(b))
+    assert wa != wb
+    print(f"\n[serve] transition buffer handed on; holding launch with {big}", flush=True)
+    with lhs.Server(capacity=1 << 21) as srv:
+        hold = [srv.submit(models[k]) for k in big]
+        ra, _ = srv.wait(srv.submit(a))
+        steps = srv.stats()["steps"]
+        rb, _ = srv.wait(srv.submit(b))
+        same_launch = srv.stats()["steps"] == steps
+        for t in hold:
+            srv.wait(t)
+    assert result_fields(ra) == wa
+    assert result_fields(rb) == wb
+    print("second query in the same launch:", same_launch, flush=True)
+
+
+def test_serve_query_without_lds_transitions_joins_a_launch(lhs):
+    """A query posted to a running launch whose LDS holds fewer transition
+    entries than it has reads its transitions from memory, and its narrower
+    tile rows and masks land where the running queries' LDS copies of their
+    transitions lie: those copies must be staged again, not trusted.  The
+    running queries (widths 10-17, at most 96 transitions) and the joining
+    ones (width 7, 228 and 288 transitions) are large, so their tiles
+    interleave on the same workgroups; every result equals the oracle's."""
+    models = gen.batch_models()
+    golden = _golden_mix()
+    hold = [58, 44, 34, 46, 14] * 2
+    join = [61, 53]
+    plk = lambda k: models[k].P * models[k].L * models[k].K
+    assert max(plk(k) for k in hold) < min(plk(k) for k in join)
+    assert min(models[k].W for k in hold) > max(models[k].W for k in join)
+
+    def check(k, r):
+        g = golden[k]
+        assert (r.total, r.n_levels, r.level_counts, r.edges, r.deadlocks) == \
+            (g["total"], g["n_levels"], g["level_counts"], g["edges"], g["deadlocks"]), k
+
+    print(f"\n[serve] queries {join} posted to the launch of queries {hold}", flush=True)
+    with lhs.Server(capacity=1 << 21) as srv:
+        # every table allocated once and pooled, so that posting is quick
+        for t in [srv.submit(models[k]) for k in hold + join]:
+            srv.wait(t)
+        time.sleep(0.1)                        # that launch has ended
+        l0 = srv.stats()["steps"]
+        th = [(k, srv.submit(models[k])) for k in hold]
+        time.sleep(0.001)                      # the next launch has started
+        tj = [(k, srv.submit(models[k])) for k in join]
+        for k, t in th + tj:
+            check(k, srv.wait(t)[0])
+        launches = srv.stats()["steps"] - l0
+    print("launches:", launches, flush=True)
+    assert launches == 1
