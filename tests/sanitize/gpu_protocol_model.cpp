@@ -30,16 +30,30 @@
 // enqueues the others.  Models are N independent cyclic L-state processes;
 // results are checked against a sequential BFS.
 //
+// Part 4, the persistent server: a host thread posts queries (a slot's
+// constants and table, then an admission entry, then the admission tail)
+// to running workers and collects completion records; workers hold one ring
+// position each (fetch-and-add) and take admissions between polls; the
+// launch ends when its workers leave after a quiet spell, or early when the
+// host asks it to drain, and the host starts another for queries posted too
+// late.  Leaving and admitting announce themselves before each looks at the
+// other (sequentially consistent), and an admission checks that no worker
+// of its launch has left.  Slots are reused by later queries.
+//
 // Planted mistakes (compile with -DPLANT=n) remove one ordering each; the
 // test expects TSan (or a result check) to catch every one:
 //   1 publish DONE before writing the row      2 publish DONE relaxed
 //   3 compare a matching row without DONE      4 free a ring cell relaxed
-//   5 count a finished tile relaxed
+//   5 count a finished tile relaxed            6 raise the admission tail relaxed
+//   7 publish a completion record relaxed      8 fill a completion record after
+//                                                publishing it
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <set>
@@ -342,8 +356,10 @@ void expand_tile(Model &m, uint32_t j, Queue &q) {
 }
 
 // Finalise model i's level (its last tile is done).  Returns true when the
-// model has a next level, whose tile 0 the caller then expands.
-bool finalize(std::vector<Model> &ms, uint32_t i, Queue &q) {
+// model has a next level, whose tile 0 the caller then expands; on_done(i)
+// runs once the model is finished.
+template <class OnDone>
+bool finalize(std::vector<Model> &ms, uint32_t i, Queue &q, OnDone on_done) {
     Model &m = ms[i];
     LevelState &L = m.lv;
     const uint32_t n_next = m.n_next.load(std::memory_order_relaxed);
@@ -377,6 +393,7 @@ bool finalize(std::vector<Model> &ms, uint32_t i, Queue &q) {
     m.dead.store(0, std::memory_order_relaxed);
     if (done) {
         q.remaining.fetch_sub(1, std::memory_order_release);
+        on_done(i);
         return false;
     }
     if (nt > 1) {
@@ -422,7 +439,7 @@ void worker(std::vector<Model> &ms, Queue &q) {
 #else
         const uint32_t done = m.lv.tiles_done.fetch_add(1, std::memory_order_acq_rel) + 1;
 #endif
-        kept = done == total && finalize(ms, mi, q);
+        kept = done == total && finalize(ms, mi, q, [](uint32_t) {});
     }
 }
 
@@ -609,12 +626,298 @@ int part3() {
     return bad.load();
 }
 
+// ---------------------------------------------------------------- part 4 ---
+constexpr uint32_t kSlots = 4, kAdmitRing = 8, kDoneRing = 8, kQuiet = 400, kStallPolls = 1u << 22;
+
+struct DoneRec {
+    std::atomic<uint64_t> seq{0};
+    uint32_t slot = 0, n_levels = 0;   // payload
+};
+
+struct Server {
+    std::vector<Model> ms{kSlots};             // per-slot query state (payload)
+    Queue q;
+    std::atomic<uint64_t> admit_tail{0}, admit_head{0}, done_tail{0};
+    uint32_t admit_slot[kAdmitRing] = {};      // payload
+    DoneRec done[kDoneRing];
+    std::atomic<uint32_t> closing{0}, stop{0}, beat{0}, left{0}, alive{0};
+};
+
+// One worker of a launch: the kernel's decision loop.
+void serve_worker(Server &S) {
+    Queue &q = S.q;
+    bool kept = false, holding = false;
+    uint32_t mi = 0, tile = 0, quiet = 0, stall = 0, last_beat = 0;
+    uint64_t pos = 0;
+    auto on_done = [&S](uint32_t i) {
+        const uint64_t p = S.done_tail.fetch_add(1, std::memory_order_relaxed);
+        DoneRec &r = S.done[p % kDoneRing];
+#if PLANT == 8
+        r.seq.store(p + 1, std::memory_order_release);
+        r.slot = i;
+        r.n_levels = (uint32_t)S.ms[i].levels.size();
+#else
+        r.slot = i;
+        r.n_levels = (uint32_t)S.ms[i].levels.size();
+#if PLANT == 7
+        r.seq.store(p + 1, std::memory_order_relaxed);
+#else
+        r.seq.store(p + 1, std::memory_order_release);   // system-scope release
+#endif
+#endif
+    };
+    while (true) {
+        if (q.error.load(std::memory_order_relaxed))
+            break;
+        bool have = false, admit = false;
+        if (kept) {
+            tile = 0;
+            have = true;
+        } else {
+            if (!holding) {
+                pos = q.head.fetch_add(1, std::memory_order_relaxed);
+                holding = true;
+            }
+            Cell &c = q.ring[pos & q.mask];
+            if (c.seq.load(std::memory_order_acquire) == pos + 1) {
+                mi = c.model;
+                tile = c.tile;
+                c.seq.store(pos + q.mask + 1, std::memory_order_release);
+                holding = false;
+                have = true;
+            } else {
+                const bool closing = S.closing.load(std::memory_order_relaxed) != 0;
+                const uint64_t ah = S.admit_head.load(std::memory_order_relaxed);
+                if (!closing && ah < S.admit_tail.load(std::memory_order_acquire)) {
+                    q.remaining.fetch_add(1, std::memory_order_seq_cst);
+                    uint64_t e = ah;
+                    if (S.closing.load(std::memory_order_seq_cst) == 0 &&
+                        S.admit_head.compare_exchange_strong(e, ah + 1, std::memory_order_relaxed)) {
+                        if (S.left.load(std::memory_order_seq_cst) != 0)
+                            q.error.store(5, std::memory_order_relaxed);   // admitted to a draining launch
+                        mi = S.admit_slot[ah % kAdmitRing];
+                        admit = true;
+                    } else {
+                        q.remaining.fetch_sub(1, std::memory_order_relaxed);
+                    }
+                } else if (q.remaining.load(std::memory_order_relaxed) != 0) {
+                    quiet = 0;
+                } else if (++quiet >= kQuiet || closing || S.stop.load(std::memory_order_relaxed)) {
+                    S.closing.exchange(1, std::memory_order_seq_cst);
+                    if (q.remaining.load(std::memory_order_seq_cst) == 0) {
+                        S.left.fetch_add(1, std::memory_order_seq_cst);
+                        break;
+                    }
+                }
+                if (!admit) {
+                    const uint32_t b = S.beat.load(std::memory_order_relaxed);
+                    stall = b == last_beat ? stall + 1 : 0;
+                    last_beat = b;
+                    if (stall > kStallPolls) {
+                        q.error.store(4, std::memory_order_relaxed);
+                        break;
+                    }
+                    std::this_thread::yield();
+                    continue;
+                }
+            }
+        }
+        stall = 0;
+        Model &m = S.ms[mi];
+        if (admit) {
+            // the slot's constants and table come from the host; s0 and
+            // level 0 are set up here, and tile 0 is this worker's
+            m.levels.assign(1, 1);
+            m.total = 1;
+            m.p_edges = m.p_dead = 0;
+            m.capped = false;
+            m.n_next.store(0, std::memory_order_relaxed);
+            m.abort.store(0, std::memory_order_relaxed);
+            m.edges.store(0, std::memory_order_relaxed);
+            m.dead.store(0, std::memory_order_relaxed);
+            std::vector<uint32_t> s0(m.N, 0);
+            uint32_t at = 0;
+            if (find_or_put(*m.t, s0.data(), at) != kNew)
+                q.error.store(6, std::memory_order_relaxed);
+            m.fr[0][0] = at;
+            m.lv.cur = 0;
+            m.lv.n_front = 1;
+            m.lv.limit = m.cap ? (uint32_t)(m.cap - 1) : 0xFFFFFFFFu;
+            m.lv.tiles_total = 1;
+            m.lv.tile_rows = kTileRows;
+            m.lv.tiles_done.store(0, std::memory_order_relaxed);
+            kept = true;
+            continue;
+        }
+        expand_tile(m, tile, q);
+        const uint32_t total = m.lv.tiles_total;
+        const uint32_t done = m.lv.tiles_done.fetch_add(1, std::memory_order_acq_rel) + 1;
+        S.beat.fetch_add(1, std::memory_order_relaxed);
+        kept = done == total && finalize(S.ms, mi, q, on_done);
+    }
+    S.alive.fetch_sub(1, std::memory_order_release);
+}
+
+int part4() {
+    // queries: cyclic models, some capped, each with its expected result
+    struct Spec {
+        uint32_t N, L;
+        uint64_t cap;
+    };
+    const Spec specs[] = {{2, 9, 0}, {3, 5, 0}, {4, 4, 0}, {2, 20, 0}, {3, 6, 60}, {4, 3, 40}, {5, 3, 0}, {3, 4, 0}};
+    const uint32_t n_specs = sizeof(specs) / sizeof(specs[0]);
+    std::vector<std::vector<uint64_t>> w_levels(n_specs);
+    std::vector<uint64_t> w_edges(n_specs);
+    std::vector<bool> w_capped(n_specs);
+    std::vector<std::set<std::vector<uint32_t>>> w_set(n_specs);
+    uint64_t widest = 0;
+    for (uint32_t k = 0; k < n_specs; ++k) {
+        bool c = false;
+        bfs(specs[k].N, specs[k].L, specs[k].cap, w_levels[k], w_edges[k], c, w_set[k]);
+        w_capped[k] = c;
+        widest = std::max(widest, *std::max_element(w_levels[k].begin(), w_levels[k].end()));
+    }
+    Server S;
+    Queue &q = S.q;
+    // the ring holds a full level of every slot plus one held position per worker
+    const uint32_t workers = 4;
+    uint64_t cells = 16;
+    while (cells < kSlots * ((widest + kTileRows - 1) / kTileRows + 1) + workers)
+        cells <<= 1;
+    q.mask = cells - 1;
+    q.ring.reset(new Cell[cells]);
+    for (uint64_t p = 0; p < cells; ++p) {
+        q.ring[p].seq.store(p, std::memory_order_relaxed);
+        q.ring[p].model = q.ring[p].tile = 0;
+    }
+    const uint32_t n_queries = 160;
+    std::vector<uint32_t> slot_spec(kSlots, 0), free_slots;
+    for (uint32_t i = 0; i < kSlots; ++i)
+        free_slots.push_back(i);
+    std::vector<std::thread> launch;
+    uint64_t posted = 0, done_head = 0, launches = 0, drains = 0;
+    uint32_t live = 0, bad = 0, completed = 0, seed = 12345;
+    auto rnd = [&seed] {
+        seed = seed * 1103515245u + 12345u;
+        return seed >> 16;
+    };
+    auto start_launch = [&] {
+        // no worker of the last launch is alive (joined): positions it held
+        // unfilled are given back, admissions reopen
+        q.head.store(q.tail.load(std::memory_order_relaxed), std::memory_order_relaxed);
+        S.closing.store(0, std::memory_order_relaxed);
+        S.left.store(0, std::memory_order_relaxed);
+        S.alive.store(workers, std::memory_order_relaxed);
+        for (uint32_t w = 0; w < workers; ++w)
+            launch.emplace_back(serve_worker, std::ref(S));
+        ++launches;
+    };
+    auto join_launch = [&] {
+        for (auto &t : launch)
+            t.join();
+        launch.clear();
+    };
+    auto collect = [&] {
+        while (true) {
+            DoneRec &r = S.done[done_head % kDoneRing];
+            if (r.seq.load(std::memory_order_acquire) != done_head + 1)
+                break;
+            const uint32_t slot = r.slot, nl = r.n_levels;
+            ++done_head;
+            Model &m = S.ms[slot];
+            const uint32_t k = slot_spec[slot];
+            std::set<std::vector<uint32_t>> got;
+            for (uint32_t s = 0; s < m.t->capacity(); ++s)
+                if (m.t->slot[s].load(std::memory_order_relaxed) & kDone)
+                    got.insert(std::vector<uint32_t>(&m.t->data[(size_t)s * m.N], &m.t->data[(size_t)s * m.N] + m.N));
+            const bool ok = nl == m.levels.size() && m.levels == w_levels[k] && m.p_edges == w_edges[k] &&
+                            m.capped == w_capped[k] && got == w_set[k];
+            if (!ok) {
+                ++bad;
+                printf("part4: query on slot %u (model %u) WRONG\n", slot, k);
+            }
+            ++completed;
+            --live;
+            free_slots.push_back(slot);
+        }
+    };
+    for (uint32_t n = 0; n < n_queries && !q.error.load();) {
+        collect();
+        if (S.alive.load(std::memory_order_acquire) == 0 && !launch.empty())
+            join_launch();
+        if (!free_slots.empty()) {
+            // post: the slot's constants and a fresh table, the entry, then the tail
+            const uint32_t slot = free_slots.back();
+            free_slots.pop_back();
+            const uint32_t k = rnd() % n_specs;
+            Model &m = S.ms[slot];
+            m.N = specs[k].N;
+            m.L = specs[k].L;
+            m.cap = specs[k].cap;
+            uint64_t states = 1;
+            for (uint32_t p = 0; p < m.N; ++p)
+                states *= m.L;
+            uint32_t cap = 64;
+            while (cap < 2 * states + 64)
+                cap <<= 1;
+            m.t.reset(new Table(m.N, 8, cap));
+            m.fr[0].assign(cap, 0);
+            m.fr[1].assign(cap, 0);
+            slot_spec[slot] = k;
+            S.admit_slot[posted % kAdmitRing] = slot;
+            ++posted;
+#if PLANT == 6
+            S.admit_tail.store(posted, std::memory_order_relaxed);
+#else
+            S.admit_tail.store(posted, std::memory_order_release);   // copies in stream order
+#endif
+            ++live;
+            ++n;
+            if (rnd() % 16 == 0 && !launch.empty()) {
+                S.closing.store(1, std::memory_order_relaxed);      // drain for a wider query
+                ++drains;
+            }
+        }
+        if (launch.empty() && live > 0)
+            start_launch();
+        if (rnd() % 8 == 0)
+            std::this_thread::sleep_for(std::chrono::microseconds(rnd() % 3000));   // quiet spells
+        else
+            std::this_thread::yield();
+    }
+    // the rest: wait for every query, relaunching for queries posted too late
+    for (uint64_t spins = 0; live > 0 && !q.error.load(); ++spins) {
+        collect();
+        if (S.alive.load(std::memory_order_acquire) == 0 && !launch.empty())
+            join_launch();
+        if (launch.empty() && live > 0)
+            start_launch();
+        std::this_thread::yield();
+        if (spins > kSpin) {
+            ++bad;
+            break;
+        }
+    }
+    S.stop.store(1, std::memory_order_relaxed);
+    join_launch();
+    if (q.error.load()) {
+        printf("part4: error %u\n", q.error.load());
+        ++bad;
+    }
+    printf("part4: %u queries on %u slots in %llu launches (%llu drains asked), errors %u\n", completed, kSlots,
+           (unsigned long long)launches, (unsigned long long)drains, bad);
+    if (launches < 2 || completed != n_queries)
+        ++bad;   // no relaunch was exercised, or a query was lost
+    return (int)bad;
+}
+
 }  // namespace
 
 int main() {
     const int a = part1();
     const int b = part2();
     const int c = part3();
-    printf("errors %d\n", a + b + c);
-    return a + b + c ? 1 : 0;
+    const int d = part4();
+    printf("errors %d\n", a + b + c + d);
+    return a + b + c + d ? 1 : 0;
 }

@@ -37,9 +37,11 @@ def _protocol_model(tmp_path, plant):
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 def test_gpu_protocol_model_under_thread_sanitizer(tmp_path):
     """Find-or-put's claim / row write / publish / bounded wait, the batch
-    ring with last-tile level finalisation, and the ring alone, modelled with
-    threads and the kernels' orderings: no race, and every result equals a
-    sequential BFS (gpu_protocol_model.cpp)."""
+    ring with last-tile level finalisation, the ring alone, and the
+    persistent server (admission into running workers, completion records,
+    draining and relaunch, slot reuse), modelled with threads and the
+    kernels' orderings: no race, and every result equals a sequential BFS
+    (gpu_protocol_model.cpp)."""
     r = _protocol_model(tmp_path, 0)
     assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
     assert r.returncode == 0 and "errors 0" in r.stdout, r.stdout + r.stderr[-2000:]
@@ -53,6 +55,9 @@ def test_gpu_protocol_model_under_thread_sanitizer(tmp_path):
     (3, "matching row compared without waiting for DONE"),
     (4, "ring cell freed before its item is read"),
     (5, "finished tile counted without ordering"),
+    (6, "admission tail raised without release"),
+    (7, "completion record published without release"),
+    (8, "completion record filled after it is published"),
 ])
 def test_gpu_protocol_model_catches_planted_mistakes(tmp_path, plant, what):
     r = _protocol_model(tmp_path, plant)
