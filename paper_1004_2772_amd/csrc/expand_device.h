@@ -18,6 +18,26 @@ namespace lhs {
 constexpr int kExpandBlock = 256;
 constexpr uint32_t kQueue = 512;   // LDS successor ring (2 passes of 256)
 
+// A next frontier appended in segments (single-model levels): kSegs
+// segments of `size` entries at buf + k * size, with append cursors
+// cur[k * kSegStride] (a 128-byte line each).
+struct SegOut {
+    uint32_t *buf;
+    uint32_t *cur;
+    uint32_t size;
+    DevStatus *status;   // EFULL if the segments cannot take a flush
+};
+
+// The frontier such a level produced, as the next level reads it: n[k]
+// entries in segment k, tiles[k] = tiles (of kExpandBlock entries, never
+// across segments) in the segments before k.
+struct SegFront {
+    const uint32_t *buf;
+    uint32_t size;
+    uint32_t n[kSegs];
+    uint32_t tiles[kSegs + 1];
+};
+
 // Successor of an LDS row: row with s[p] = target and, if ew != NONE,
 // s[ew] = ev (ew already offset by P).  Descriptor: x = row word offset from
 // the LDS base | p << 16 | ew << 24 (0xFF = no effect), y = target | ev << 16.
@@ -83,6 +103,10 @@ static __shared__ uint32_t s_nnew, s_nbase, s_abort, s_eager;
 static __shared__ uint32_t s_pushed;
 // Set when a wait for a frontier entry ran out (AWAIT): the launch stops.
 static __shared__ uint32_t s_stall;
+// Segmented appends (SEG): this workgroup's estimate of the level's new
+// states so far, and the pieces of the segments its current flush fills.
+static __shared__ uint32_t s_seg_est, s_seg_np;
+static __shared__ uint32_t s_seg_pos[2 * kSegs + 1], s_seg_off[2 * kSegs + 1];
 
 // Call once at kernel start, before the first expand_tile.
 __device__ __forceinline__ void expand_begin() {
@@ -96,6 +120,7 @@ __device__ __forceinline__ void expand_begin() {
         s_eager = 0;
         s_pushed = 0;
         s_stall = 0;
+        s_seg_est = 0;
     }
 }
 
@@ -146,14 +171,93 @@ __device__ __forceinline__ void flush_new_slots(const uint32_t *nbuf, uint32_t *
     }
 }
 
+// Segmented appends: the buffered new slots go to one of kSegs segments of
+// the next frontier, each with its own append cursor on a line of its own,
+// so that the workgroups of the GPU spread their cursor atomics over kSegs
+// addresses (one atomic address saturates at a few million operations per
+// second, and a level appends far more often).  A workgroup starts at the
+// segment of its XCD (workgroups are dealt to the XCDs in turn); a flush
+// that does not fit its segment takes the rest from the following ones.
+// The level's exact count is only needed near the cap: this workgroup keeps
+// an estimate from its cursor (the segments fill evenly), turns eager when
+// the estimate comes within kEagerRoom of `limit`, and then sums the
+// cursors after every flush to set the abort flag.  Block-wide, uniform.
+template <bool COHERENT>
+__device__ __forceinline__ void flush_new_slots_seg(const uint32_t *nbuf, const SegOut &so, LevelCounters *lc,
+                                                    uint32_t limit) {
+    __syncthreads();
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nn = s_nnew;
+    if (tid == 0) {
+        if (nn) {
+            uint32_t k = blockIdx.x & (kSegs - 1), rem = nn, np = 0, off = 0, first = 0;
+            // every segment visited twice at most: a visited one that is
+            // full stays full, and the segments hold every slot of the table
+            for (uint32_t tries = 0; rem && tries < 2 * kSegs; ++tries) {
+                const uint32_t b = atomicAdd(so.cur + k * kSegStride, rem);
+                if (tries == 0)
+                    first = b;
+                if (b < so.size) {
+                    const uint32_t n = min(rem, so.size - b);
+                    s_seg_pos[np] = k * so.size + b;
+                    s_seg_off[np] = off;
+                    ++np;
+                    off += n;
+                    rem -= n;
+                }
+                k = (k + 1) & (kSegs - 1);
+            }
+            s_seg_off[np] = off;
+            s_seg_np = np;
+            if (rem)   // more new slots than the table has slots: cannot happen
+                set_error(so.status, 3u /* LHS_EFULL */);
+            s_pushed += nn;
+            s_seg_est = max(s_seg_est, (uint32_t)min<uint64_t>((uint64_t)kSegs * ((uint64_t)first + nn), 0xFFFFFFFFull));
+            if (limit != 0xFFFFFFFFu && ((uint64_t)s_seg_est + kEagerRoom > limit || s_eager)) {
+                s_eager = 1;
+                uint64_t total = 0;
+                for (uint32_t q = 0; q < kSegs; ++q)
+                    total += min(ld_coherent(so.cur + q * kSegStride), so.size);
+                if (total > limit) {
+                    __hip_atomic_store(&lc->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s_abort = 1;
+                }
+            }
+        }
+        if (s_eager && !s_abort)
+            s_abort = __hip_atomic_load(&lc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (nn) {
+        const uint32_t np = s_seg_np, placed = s_seg_off[np];
+        for (uint32_t i = tid; i < placed; i += kExpandBlock) {
+            uint32_t p = 0;
+            while (p + 1 < np && i >= s_seg_off[p + 1])
+                ++p;
+            const uint32_t pos = s_seg_pos[p] + (i - s_seg_off[p]);
+            if (COHERENT)
+                st_coherent(so.buf + pos, nbuf[i]);
+            else
+                so.buf[pos] = nbuf[i];
+        }
+        __syncthreads();
+        if (tid == 0)
+            s_nnew = 0;
+        __syncthreads();
+    }
+}
+
 // Deferred mode: append the workgroup's remaining new states and add its
 // accumulated edge/deadlock counts to lc.  Call by all threads after the
 // last expand_tile of the launch (also after an aborted tile: every claimed
 // slot must be listed in next[] for the rollback).
-template <int G, bool COHERENT = false>
+template <int G, bool COHERENT = false, bool SEG = false>
 __device__ __forceinline__ void expand_end(uint32_t *smem, uint32_t W, uint32_t tcap, uint32_t *next,
-                                           LevelCounters *lc, uint32_t limit) {
-    flush_new_slots<COHERENT>(expand_nbuf<G>(smem, W, tcap), next, lc, limit);
+                                           LevelCounters *lc, uint32_t limit, const SegOut &so = SegOut{}) {
+    if constexpr (SEG)
+        flush_new_slots_seg<COHERENT>(expand_nbuf<G>(smem, W, tcap), so, lc, limit);
+    else
+        flush_new_slots<COHERENT>(expand_nbuf<G>(smem, W, tcap), next, lc, limit);
     if (threadIdx.x == 0) {
         if (s_acc_edges)
             atomicAdd(&lc->edges, s_acc_edges);
@@ -225,11 +329,12 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
 // CL: slot lines are read with coherent loads (tables reused within one
 // launch, the persistent server).
 template <int G, uint32_t LS, bool COHERENT = false, bool DEFER = false, bool DEFER_COUNTS = DEFER,
-          bool AWAIT = false, bool CL = false>
+          bool AWAIT = false, bool CL = false, bool SEG = false>
 __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, const ModelView &m,
                                             const uint32_t *__restrict__ front, uint64_t base,
                                             uint32_t rows, uint32_t *__restrict__ next,
-                                            LevelCounters *lc, uint32_t limit, uint32_t tcap) {
+                                            LevelCounters *lc, uint32_t limit, uint32_t tcap,
+                                            const SegOut &so = SegOut{}) {
     constexpr uint32_t kBlock = kExpandBlock;
     const uint32_t W = m.W, stride = W | 1u;
     uint32_t *tile = smem;
@@ -259,7 +364,10 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
     if (tid == 0) {
         s_tail = 0;
         s_abort = __hip_atomic_load(&lc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t nn = __hip_atomic_load(&lc->n_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // SEG: the level's count is this workgroup's estimate (the cursors
+        // are read only near the cap)
+        const uint32_t nn = SEG ? s_seg_est : __hip_atomic_load(&lc->n_next, __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT);
         s_eager = limit != 0xFFFFFFFFu && (uint64_t)nn + kEagerRoom > limit;
     }
     if (restage)
@@ -358,7 +466,12 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
         return tr[idx];
     };
 
-    auto flush_new = [&]() { flush_new_slots<COHERENT>(nbuf, next, lc, limit); };
+    auto flush_new = [&]() {
+        if constexpr (SEG)
+            flush_new_slots_seg<COHERENT>(nbuf, so, lc, limit);
+        else
+            flush_new_slots<COHERENT>(nbuf, next, lc, limit);
+    };
     // ---- find-or-put of successors d0/d1/hq[0, take); new slots to nbuf ----
     auto fop_pass = [&](uint32_t take) {
         for (uint32_t r = 0; r < G; ++r) {

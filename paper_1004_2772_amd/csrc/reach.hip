@@ -17,30 +17,67 @@ using namespace lhs;
 
 namespace {
 
-// Expand frontier[0, n_front) of one model (one BFS level).
+// Tiles of a segmented frontier: every tile lies in one segment.
+__host__ __device__ inline void seg_tiles(SegFront &f) {
+    f.tiles[0] = 0;
+    for (uint32_t k = 0; k < kSegs; ++k)
+        f.tiles[k + 1] = f.tiles[k] + (f.n[k] + kExpandBlock - 1) / kExpandBlock;
+}
+
+__host__ __device__ inline uint64_t seg_total(const SegFront &f) {
+    uint64_t n = 0;
+    for (uint32_t k = 0; k < kSegs; ++k)
+        n += f.n[k];
+    return n;
+}
+
+// The frontier entries of tile `tile`: their address and count.
+__device__ __forceinline__ const uint32_t *seg_tile(const SegFront &f, uint32_t tile, uint32_t &rows) {
+    uint32_t t0 = f.tiles[0], nk = f.n[0];
+    uint64_t at = 0;
+#pragma unroll
+    for (uint32_t q = 1; q < kSegs; ++q)
+        if (tile >= f.tiles[q]) {
+            t0 = f.tiles[q];
+            nk = f.n[q];
+            at = (uint64_t)q * f.size;
+        }
+    const uint32_t j = tile - t0;
+    rows = min<uint32_t>(kExpandBlock, nk - j * kExpandBlock);
+    return f.buf + at + (uint64_t)j * kExpandBlock;
+}
+
+// Expand one BFS level of one model: the frontier's tiles, new states
+// appended to the segments of the next frontier.
 template <int G, uint32_t LS>
-__global__ __launch_bounds__(kExpandBlock) void k_expand(TableView t, ModelView m,
-                                                         const uint32_t *__restrict__ front,
-                                                         uint32_t n_front, uint32_t *__restrict__ next,
+__global__ __launch_bounds__(kExpandBlock) void k_expand(TableView t, ModelView m, SegFront f, SegOut o,
                                                          LevelCounters *lc, uint32_t limit, uint32_t tcap) {
     extern __shared__ uint32_t smem[];
     expand_begin();
-    for (uint64_t base = (uint64_t)blockIdx.x * kExpandBlock; base < n_front;
-         base += (uint64_t)gridDim.x * kExpandBlock) {
-        const uint32_t rows = (uint32_t)min<uint64_t>(kExpandBlock, n_front - base);
-        if (expand_tile<G, LS, false, true>(smem, t, m, front, base, rows, next, lc, limit, tcap))
+    const uint32_t n_tiles = f.tiles[kSegs];
+    for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        uint32_t rows = 0;
+        const uint32_t *front = seg_tile(f, tile, rows);
+        if (expand_tile<G, LS, false, true, true, false, false, true>(smem, t, m, front, 0, rows, nullptr, lc,
+                                                                      limit, tcap, o))
             break;
     }
-    expand_end<G>(smem, m.W, tcap, next, lc, limit);
+    expand_end<G, false, true>(smem, m.W, tcap, nullptr, lc, limit, o);
 }
 
-// Undo the inserts of a discarded level: zero the slots listed in next[].
-// Only slots claimed during that level are listed, and no earlier state's
-// probe sequence runs through a slot claimed later, so the table is exactly
-// the kept levels afterwards.
-__global__ void k_rollback(uint64_t *bucket, const uint32_t *next, uint32_t n) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        bucket[next[i]] = 0;
+// Undo the inserts of a discarded level: zero the slots listed in its
+// segments.  Only slots claimed during that level are listed, and no earlier
+// state's probe sequence runs through a slot claimed later, so the table is
+// exactly the kept levels afterwards.
+__device__ __forceinline__ void rollback_segments(uint64_t *bucket, const uint32_t *buf, uint32_t size,
+                                                  const uint32_t *n) {
+    for (uint32_t k = 0; k < kSegs; ++k)
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n[k]; i += gridDim.x * blockDim.x)
+            bucket[buf[(uint64_t)k * size + i]] = 0;
+}
+
+__global__ void k_rollback(uint64_t *bucket, SegFront f) {
+    rollback_segments(bucket, f.buf, f.size, f.n);
 }
 
 // ---- graph-driven levels (REACH_F_GRAPH) ----------------------------------
@@ -51,30 +88,42 @@ __global__ void k_rollback(uint64_t *bucket, const uint32_t *next, uint32_t n) {
 template <int G, uint32_t LS>
 __global__ __launch_bounds__(kExpandBlock) void k_expand_graph(const GraphCtx *ctx, uint32_t tcap) {
     extern __shared__ uint32_t smem[];
-    __shared__ uint32_t s_go, s_cur, s_nf, s_lim;
+    __shared__ uint32_t s_go, s_lim;
+    __shared__ SegFront s_f;
+    __shared__ SegOut s_o;
     if (threadIdx.x == 0) {
         s_go = !ctx->ctl.done;
-        s_cur = ctx->ctl.cur;
-        s_nf = ctx->ctl.n_front;
         s_lim = ctx->ctl.limit;
+        const uint32_t cur = ctx->ctl.cur;
+        s_f.buf = ctx->fr[cur];
+        s_f.size = ctx->seg_size;
+        for (uint32_t k = 0; k < kSegs; ++k)
+            s_f.n[k] = ctx->front_n[k];
+        seg_tiles(s_f);
+        s_o.buf = ctx->fr[cur ^ 1u];
+        s_o.cur = ctx->segs;
+        s_o.size = ctx->seg_size;
+        s_o.status = ctx->t.status;
     }
     __syncthreads();
     if (!s_go)
         return;
     const TableView t = ctx->t;
     const ModelView m = ctx->m;
-    const uint32_t *front = ctx->fr[s_cur];
-    uint32_t *next = ctx->fr[s_cur ^ 1u];
+    const SegFront f = s_f;
+    const SegOut o = s_o;
     LevelCounters *lc = ctx->lc;
-    const uint32_t n_front = s_nf, limit = s_lim;
+    const uint32_t limit = s_lim;
     expand_begin();
-    for (uint64_t base = (uint64_t)blockIdx.x * kExpandBlock; base < n_front;
-         base += (uint64_t)gridDim.x * kExpandBlock) {
-        const uint32_t rows = (uint32_t)min<uint64_t>(kExpandBlock, n_front - base);
-        if (expand_tile<G, LS, false, true>(smem, t, m, front, base, rows, next, lc, limit, tcap))
+    const uint32_t n_tiles = f.tiles[kSegs];
+    for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        uint32_t rows = 0;
+        const uint32_t *front = seg_tile(f, tile, rows);
+        if (expand_tile<G, LS, false, true, true, false, false, true>(smem, t, m, front, 0, rows, nullptr, lc,
+                                                                      limit, tcap, o))
             break;
     }
-    expand_end<G>(smem, m.W, tcap, next, lc, limit);
+    expand_end<G, false, true>(smem, m.W, tcap, nullptr, lc, limit, o);
 }
 
 // The host loop's per-level bookkeeping, on the device (one thread).
@@ -85,9 +134,18 @@ __global__ void k_finalize_graph(GraphCtx *ctx) {
         c.rollback_n = 0;
         return;
     }
-    const uint32_t n_next = lc->n_next;
+    uint32_t seg_n[kSegs];
+    uint64_t next_total = 0;
+    for (uint32_t k = 0; k < kSegs; ++k) {
+        seg_n[k] = min(ctx->segs[k * kSegStride], ctx->seg_size);
+        next_total += seg_n[k];
+        ctx->segs[k * kSegStride] = 0;
+    }
+    const uint32_t n_next = (uint32_t)next_total;
     if (c.cap && n_next > c.limit) {
         c.rollback_n = n_next;      // k_rollback_graph discards the level
+        for (uint32_t k = 0; k < kSegs; ++k)
+            ctx->rb_n[k] = seg_n[k];
         c.capped = 1;
         c.done = 1;
     } else {
@@ -102,6 +160,8 @@ __global__ void k_finalize_graph(GraphCtx *ctx) {
             c.levels[c.n_levels++] = n_next;
             c.total += n_next;
             c.n_front = n_next;
+            for (uint32_t k = 0; k < kSegs; ++k)
+                ctx->front_n[k] = seg_n[k];
             c.cur ^= 1u;
             c.limit = c.cap ? (uint32_t)min<unsigned long long>(c.cap - c.total, 0xFFFFFFFFull) : 0xFFFFFFFFu;
         }
@@ -113,11 +173,8 @@ __global__ void k_finalize_graph(GraphCtx *ctx) {
 }
 
 __global__ void k_rollback_graph(const GraphCtx *ctx) {
-    const uint32_t n = ctx->ctl.rollback_n;
-    const uint32_t *next = ctx->fr[ctx->ctl.cur ^ 1u];
-    uint64_t *bucket = ctx->t.bucket;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        bucket[next[i]] = 0;
+    if (ctx->ctl.rollback_n)
+        rollback_segments(ctx->t.bucket, ctx->fr[ctx->ctl.cur ^ 1u], ctx->seg_size, ctx->rb_n);
 }
 
 constexpr uint32_t kGraphLevels = 8;
@@ -129,11 +186,15 @@ __global__ void k_begin_parents(uint32_t *parent, const uint32_t *front, uint32_
     dead_rec[0] = 0;
 }
 
-__global__ void k_zero_level(LevelCounters *lc) {
-    lc->n_next = 0;
-    lc->abort = 0;
-    lc->edges = 0;
-    lc->deadlocks = 0;
+__global__ void k_zero_level(LevelCounters *lc, uint32_t *segs) {
+    if (threadIdx.x == 0) {
+        lc->n_next = 0;
+        lc->abort = 0;
+        lc->edges = 0;
+        lc->deadlocks = 0;
+    }
+    if (threadIdx.x < kSegs)
+        segs[threadIdx.x * kSegStride] = 0;
 }
 
 // ---- exploration without allocation (reach_explore_noalloc) ---------------
@@ -148,7 +209,8 @@ constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 constexpr size_t kNaFront0 = 0;
 constexpr size_t kNaFront1 = kNaFront0 + LHS_NOALLOC_MAX_CAPACITY * sizeof(uint32_t);
 constexpr size_t kNaLevel = kNaFront1 + LHS_NOALLOC_MAX_CAPACITY * sizeof(uint32_t);
-constexpr size_t kNaSeen = kNaLevel + align256(sizeof(LevelCounters));
+constexpr size_t kNaSegs = kNaLevel + align256(sizeof(LevelCounters));
+constexpr size_t kNaSeen = kNaSegs + align256(kSegCursorBytes);
 constexpr size_t kNaInit = kNaSeen + 256;
 constexpr size_t kNaRaw = kNaInit + align256(32 * sizeof(uint32_t));
 constexpr size_t kNaPacked = kNaRaw + align256(LHS_NOALLOC_MAX_TRANS * sizeof(reach_trans));
@@ -245,10 +307,32 @@ size_t expand_lds_bytes(uint32_t W, uint32_t tcap, uint32_t tps) {
     return (size_t)expand_lds_words(W, tcap, tps) * sizeof(uint32_t);
 }
 
-lhs_status launch_expand(lhs_table *t, const TableView &tv, const ModelView &mv, const uint32_t *front,
-                         uint32_t n_front, uint32_t *next, LevelCounters *lc, uint32_t limit,
-                         hipStream_t s) {
-    const uint64_t tiles = (n_front + kExpandBlock - 1) / kExpandBlock;
+// The first frontier, s0 alone in segment 0 of buf; a frontier from the
+// segment cursors a level left (host copy).
+SegFront seg_root(const uint32_t *buf, uint32_t size) {
+    SegFront f{};
+    f.buf = buf;
+    f.size = size;
+    f.n[0] = 1;
+    seg_tiles(f);
+    return f;
+}
+
+SegFront seg_front(const uint32_t *buf, uint32_t size, const uint32_t *cursors) {
+    SegFront f{};
+    f.buf = buf;
+    f.size = size;
+    for (uint32_t k = 0; k < kSegs; ++k)
+        f.n[k] = std::min(cursors[k * kSegStride], size);
+    seg_tiles(f);
+    return f;
+}
+
+uint32_t seg_size(const lhs_table *t) { return (uint32_t)(t->capacity / kSegs); }
+
+lhs_status launch_expand(lhs_table *t, const TableView &tv, const ModelView &mv, const SegFront &f,
+                         const SegOut &o, LevelCounters *lc, uint32_t limit, hipStream_t s) {
+    const uint64_t tiles = f.tiles[kSegs];
     const uint32_t tc = trans_lds_entries(mv.P, mv.L, mv.K);
     const size_t lds = expand_lds_bytes(mv.W, tc, tps_expand(t));
     const lhs_status rc = with_shape(tps_expand(t), t->line_slots, [&](auto G, auto L) {
@@ -263,7 +347,7 @@ lhs_status launch_expand(lhs_table *t, const TableView &tv, const ModelView &mv,
             return LHS_EDEVICE;
         const uint32_t blocks = exploration_grid(t, std::min<uint64_t>(tiles, (uint64_t)ncu * per_cu));
         hipLaunchKernelGGL((k_expand<decltype(G)::value, decltype(L)::value>), dim3(blocks), dim3(kExpandBlock),
-                           lds, s, tv, mv, front, n_front, next, lc, limit, tc);
+                           lds, s, tv, mv, f, o, lc, limit, tc);
         return LHS_OK;
     });
     if (rc != LHS_OK)
@@ -276,8 +360,9 @@ lhs_status ensure_bfs_buffers(lhs_table *t) {
         return LHS_OK;
     if (hipMalloc(&t->frontier[0], t->capacity * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&t->frontier[1], t->capacity * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc(&t->level, sizeof(LevelCounters)) != hipSuccess ||
-        hipHostMalloc(&t->level_host, 256 + sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
+        hipMalloc(&t->level, 256 + kSegCursorBytes) != hipSuccess ||
+        hipHostMalloc(&t->level_host, 256 + kSegCursorBytes + sizeof(DevStatus), hipHostMallocDefault) !=
+            hipSuccess) {
         (void)hipGetLastError();
         (void)hipFree(t->frontier[0]);
         (void)hipFree(t->frontier[1]);
@@ -286,7 +371,10 @@ lhs_status ensure_bfs_buffers(lhs_table *t) {
         t->level = nullptr;
         return LHS_ENOMEM;
     }
-    t->status_host = reinterpret_cast<DevStatus *>(reinterpret_cast<char *>(t->level_host) + 256);
+    t->segs = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(t->level) + 256);
+    t->segs_host = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(t->level_host) + 256);
+    t->status_host =
+        reinterpret_cast<DevStatus *>(reinterpret_cast<char *>(t->level_host) + 256 + kSegCursorBytes);
     return LHS_OK;
 }
 
@@ -316,38 +404,43 @@ lhs_status explore_host_loop(lhs_table *t, const reach_model *m, const uint2 *d_
         return rc;
     levels.push_back(1);
     uint64_t total = 1, edges = 0, dead = 0;
-    uint32_t n_cur = 1, cur = 0;
+    uint32_t cur = 0;
+    const uint32_t size = seg_size(t);
+    SegFront f = seg_root(t->frontier[0], size);
     int capped = 0;
     while (true) {
         uint32_t limit = 0xFFFFFFFFu;
         if (m->state_cap)
             limit = (uint32_t)std::min<uint64_t>(m->state_cap - total, 0xFFFFFFFFull);
-        hipLaunchKernelGGL(k_zero_level, dim3(1), dim3(1), 0, s, t->level);
-        rc = launch_expand(t, tv, mv, t->frontier[cur], n_cur, t->frontier[cur ^ 1], t->level, limit, s);
+        hipLaunchKernelGGL(k_zero_level, dim3(1), dim3(64), 0, s, t->level, t->segs);
+        const SegOut o{t->frontier[cur ^ 1], t->segs, size, t->status};
+        rc = launch_expand(t, tv, mv, f, o, t->level, limit, s);
         if (rc != LHS_OK)
             return rc;
-        LHS_HIP(hipMemcpyAsync(t->level_host, t->level, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
+        LHS_HIP(hipMemcpyAsync(t->level_host, t->level, 256 + kSegCursorBytes, hipMemcpyDeviceToHost, s));
         LHS_HIP(hipMemcpyAsync(t->status_host, t->status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
         LHS_HIP(hipStreamSynchronize(s));
         if (t->status_host->error)
             return (lhs_status)t->status_host->error;
         const LevelCounters lc = *t->level_host;
-        if (m->state_cap && lc.n_next > limit) {
-            hipLaunchKernelGGL(k_rollback, dim3(std::min<uint32_t>((lc.n_next + 255) / 256, 4096)),
-                               dim3(256), 0, s, t->bucket, t->frontier[cur ^ 1], lc.n_next);
+        const SegFront next = seg_front(t->frontier[cur ^ 1], size, t->segs_host);
+        const uint64_t n_next = seg_total(next);
+        if (m->state_cap && n_next > limit) {
+            hipLaunchKernelGGL(k_rollback, dim3((uint32_t)std::min<uint64_t>((n_next + 255) / 256, 4096)),
+                               dim3(256), 0, s, t->bucket, next);
             LHS_HIP(hipGetLastError());
             capped = 1;
             break;
         }
         edges += lc.edges;
         dead += lc.deadlocks;
-        if (lc.n_next == 0)
+        if (n_next == 0)
             break;
         if (levels.size() >= max_levels)
             return LHS_EINVAL;
-        levels.push_back(lc.n_next);
-        total += lc.n_next;
-        n_cur = lc.n_next;
+        levels.push_back(n_next);
+        total += n_next;
+        f = next;
         cur ^= 1;
     }
     LHS_HIP(hipStreamSynchronize(s));
@@ -396,9 +489,12 @@ lhs_status explore_graph(lhs_table *t, const reach_model *m, const uint2 *d_tran
         return rc;
     if (parents && (rc = begin_parents(t, s)) != LHS_OK)
         return rc;
-    hipLaunchKernelGGL(k_zero_level, dim3(1), dim3(1), 0, s, t->level);
+    hipLaunchKernelGGL(k_zero_level, dim3(1), dim3(64), 0, s, t->level, t->segs);
     GraphCtx &h = *h_ctx;
     std::memset(&h, 0, sizeof(h));
+    h.segs = t->segs;
+    h.seg_size = seg_size(t);
+    h.front_n[0] = 1;
     h.t = bfs_view(t, parents);
     h.m = model_view(m, d_trans);
     h.fr[0] = t->frontier[0];
@@ -690,6 +786,7 @@ static lhs_status reach_explore_noalloc_impl(const reach_model *m, lhs_table *t,
     char *base = static_cast<char *>(g_na_ptr[dev]);
     uint32_t *fr[2] = {reinterpret_cast<uint32_t *>(base + kNaFront0), reinterpret_cast<uint32_t *>(base + kNaFront1)};
     LevelCounters *lc = reinterpret_cast<LevelCounters *>(base + kNaLevel);
+    uint32_t *segs = reinterpret_cast<uint32_t *>(base + kNaSegs);
     uint8_t *seen = reinterpret_cast<uint8_t *>(base + kNaSeen);
     uint32_t *d_init = reinterpret_cast<uint32_t *>(base + kNaInit);
     uint32_t *raw = reinterpret_cast<uint32_t *>(base + kNaRaw);
@@ -712,39 +809,46 @@ static lhs_status reach_explore_noalloc_impl(const reach_model *m, lhs_table *t,
     const ModelView mv = model_view(m, d_trans);
     const TableView tv = bfs_view(t, false);
     h_level_counts[0] = 1;
-    uint32_t n_levels = 1, n_cur = 1, cur = 0;
+    uint32_t n_levels = 1, cur = 0;
     uint64_t total = 1, edges = 0, dead = 0;
+    const uint32_t size = seg_size(t);
+    SegFront f = seg_root(fr[0], size);
     int capped = 0;
     LevelCounters h_lc{};
+    uint32_t h_segs[kSegs * kSegStride];
     DevStatus h_st{};
     while (true) {
         const uint32_t limit =
             m->state_cap ? (uint32_t)std::min<uint64_t>(m->state_cap - total, 0xFFFFFFFFull) : 0xFFFFFFFFu;
-        hipLaunchKernelGGL(k_zero_level, dim3(1), dim3(1), 0, s, lc);
-        if ((rc = launch_expand(t, tv, mv, fr[cur], n_cur, fr[cur ^ 1], lc, limit, s)) != LHS_OK)
+        hipLaunchKernelGGL(k_zero_level, dim3(1), dim3(64), 0, s, lc, segs);
+        const SegOut o{fr[cur ^ 1], segs, size, t->status};
+        if ((rc = launch_expand(t, tv, mv, f, o, lc, limit, s)) != LHS_OK)
             return rc;
         LHS_HIP(hipMemcpyAsync(&h_lc, lc, sizeof(h_lc), hipMemcpyDeviceToHost, s));
+        LHS_HIP(hipMemcpyAsync(h_segs, segs, kSegCursorBytes, hipMemcpyDeviceToHost, s));
         LHS_HIP(hipMemcpyAsync(&h_st, t->status, sizeof(h_st), hipMemcpyDeviceToHost, s));
         LHS_HIP(hipStreamSynchronize(s));
         if (h_st.error)
             return (lhs_status)h_st.error;
-        if (m->state_cap && h_lc.n_next > limit) {
+        const SegFront next = seg_front(fr[cur ^ 1], size, h_segs);
+        const uint64_t n_next = seg_total(next);
+        if (m->state_cap && n_next > limit) {
             // discard the level: zero the slots it claimed
-            hipLaunchKernelGGL(k_rollback, dim3(std::min<uint32_t>((h_lc.n_next + 255) / 256, 4096)), dim3(256), 0,
-                               s, t->bucket, fr[cur ^ 1], h_lc.n_next);
+            hipLaunchKernelGGL(k_rollback, dim3((uint32_t)std::min<uint64_t>((n_next + 255) / 256, 4096)),
+                               dim3(256), 0, s, t->bucket, next);
             LHS_HIP(hipGetLastError());
             capped = 1;
             break;
         }
         edges += h_lc.edges;
         dead += h_lc.deadlocks;
-        if (h_lc.n_next == 0)
+        if (n_next == 0)
             break;
         if (n_levels == max_levels)
             return LHS_EINVAL;   // more levels than the caller's array holds
-        h_level_counts[n_levels++] = h_lc.n_next;
-        total += h_lc.n_next;
-        n_cur = h_lc.n_next;
+        h_level_counts[n_levels++] = n_next;
+        total += n_next;
+        f = next;
         cur ^= 1;
     }
     LHS_HIP(hipMemcpyAsync(&h_st, t->status, sizeof(h_st), hipMemcpyDeviceToHost, s));

@@ -18,6 +18,12 @@ struct ModelView {
                               // buffer (0 where every model has a buffer of its own)
 };
 
+// Segmented next frontiers of single-model levels (expand_device.h): the
+// number of segments and the distance of their append cursors, in words.
+constexpr uint32_t kSegs = 8;
+constexpr uint32_t kSegStride = 32;
+constexpr size_t kSegCursorBytes = kSegs * kSegStride * sizeof(uint32_t);
+
 // Device-side state of a graph-driven exploration (REACH_F_GRAPH): the level
 // loop's bookkeeping, advanced by a kernel after every level so that levels
 // can be replayed from a captured graph without the host.
@@ -36,6 +42,10 @@ struct GraphCtx {
     uint32_t *fr[2];
     LevelCounters *lc;
     LevelCtl ctl;
+    uint32_t *segs;              // append cursors of the next frontier
+    uint32_t seg_size;           // entries per segment
+    uint32_t front_n[kSegs];     // entries per segment of the current frontier
+    uint32_t rb_n[kSegs];        // ... of a discarded level (k_rollback_graph)
 };
 
 // Shared state of an exploration without level barriers (REACH_F_ASYNC).
