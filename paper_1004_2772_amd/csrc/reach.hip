@@ -186,6 +186,21 @@ __global__ void k_begin_parents(uint32_t *parent, const uint32_t *front, uint32_
     dead_rec[0] = 0;
 }
 
+// A level's counters, segment counts and the table's status to the host
+// loop's pinned summary, then the counters and cursors cleared for the next
+// level.
+__global__ void k_level_done(LevelCounters *lc, uint32_t *segs, const DevStatus *st, LevelSummary *out) {
+    if (threadIdx.x == 0) {
+        out->lc = *lc;
+        out->st = *st;
+        *lc = LevelCounters{0, 0, 0, 0};
+    }
+    if (threadIdx.x < kSegs) {
+        out->seg_n[threadIdx.x] = segs[threadIdx.x * kSegStride];
+        segs[threadIdx.x * kSegStride] = 0;
+    }
+}
+
 __global__ void k_zero_level(LevelCounters *lc, uint32_t *segs) {
     if (threadIdx.x == 0) {
         lc->n_next = 0;
@@ -318,12 +333,12 @@ SegFront seg_root(const uint32_t *buf, uint32_t size) {
     return f;
 }
 
-SegFront seg_front(const uint32_t *buf, uint32_t size, const uint32_t *cursors) {
+SegFront seg_front(const uint32_t *buf, uint32_t size, const uint32_t *cursors, uint32_t stride) {
     SegFront f{};
     f.buf = buf;
     f.size = size;
     for (uint32_t k = 0; k < kSegs; ++k)
-        f.n[k] = std::min(cursors[k * kSegStride], size);
+        f.n[k] = std::min(cursors[k * stride], size);
     seg_tiles(f);
     return f;
 }
@@ -361,20 +376,23 @@ lhs_status ensure_bfs_buffers(lhs_table *t) {
     if (hipMalloc(&t->frontier[0], t->capacity * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&t->frontier[1], t->capacity * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&t->level, 256 + kSegCursorBytes) != hipSuccess ||
-        hipHostMalloc(&t->level_host, 256 + kSegCursorBytes + sizeof(DevStatus), hipHostMallocDefault) !=
-            hipSuccess) {
+        hipHostMalloc(&t->level_host, sizeof(LevelSummary), hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer(&t->summary_dev, t->level_host, 0) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipFree(t->frontier[0]);
         (void)hipFree(t->frontier[1]);
         (void)hipFree(t->level);
+        if (t->level_host)
+            (void)hipHostFree(t->level_host);
         t->frontier[0] = t->frontier[1] = nullptr;
         t->level = nullptr;
+        t->level_host = nullptr;
         return LHS_ENOMEM;
     }
     t->segs = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(t->level) + 256);
-    t->segs_host = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(t->level_host) + 256);
-    t->status_host =
-        reinterpret_cast<DevStatus *>(reinterpret_cast<char *>(t->level_host) + 256 + kSegCursorBytes);
+    LevelSummary *sum = reinterpret_cast<LevelSummary *>(t->level_host);
+    t->seg_n_host = sum->seg_n;
+    t->status_host = &sum->st;
     return LHS_OK;
 }
 
@@ -408,22 +426,24 @@ lhs_status explore_host_loop(lhs_table *t, const reach_model *m, const uint2 *d_
     const uint32_t size = seg_size(t);
     SegFront f = seg_root(t->frontier[0], size);
     int capped = 0;
+    hipLaunchKernelGGL(k_zero_level, dim3(1), dim3(64), 0, s, t->level, t->segs);
     while (true) {
         uint32_t limit = 0xFFFFFFFFu;
         if (m->state_cap)
             limit = (uint32_t)std::min<uint64_t>(m->state_cap - total, 0xFFFFFFFFull);
-        hipLaunchKernelGGL(k_zero_level, dim3(1), dim3(64), 0, s, t->level, t->segs);
         const SegOut o{t->frontier[cur ^ 1], t->segs, size, t->status};
         rc = launch_expand(t, tv, mv, f, o, t->level, limit, s);
         if (rc != LHS_OK)
             return rc;
-        LHS_HIP(hipMemcpyAsync(t->level_host, t->level, 256 + kSegCursorBytes, hipMemcpyDeviceToHost, s));
-        LHS_HIP(hipMemcpyAsync(t->status_host, t->status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+        // the level's summary lands in pinned memory (and the counters are
+        // cleared for the next level) in one small launch
+        hipLaunchKernelGGL(k_level_done, dim3(1), dim3(64), 0, s, t->level, t->segs, (const DevStatus *)t->status,
+                           static_cast<LevelSummary *>(t->summary_dev));
         LHS_HIP(hipStreamSynchronize(s));
         if (t->status_host->error)
             return (lhs_status)t->status_host->error;
         const LevelCounters lc = *t->level_host;
-        const SegFront next = seg_front(t->frontier[cur ^ 1], size, t->segs_host);
+        const SegFront next = seg_front(t->frontier[cur ^ 1], size, t->seg_n_host, 1);
         const uint64_t n_next = seg_total(next);
         if (m->state_cap && n_next > limit) {
             hipLaunchKernelGGL(k_rollback, dim3((uint32_t)std::min<uint64_t>((n_next + 255) / 256, 4096)),
@@ -830,7 +850,7 @@ static lhs_status reach_explore_noalloc_impl(const reach_model *m, lhs_table *t,
         LHS_HIP(hipStreamSynchronize(s));
         if (h_st.error)
             return (lhs_status)h_st.error;
-        const SegFront next = seg_front(fr[cur ^ 1], size, h_segs);
+        const SegFront next = seg_front(fr[cur ^ 1], size, h_segs, kSegStride);
         const uint64_t n_next = seg_total(next);
         if (m->state_cap && n_next > limit) {
             // discard the level: zero the slots it claimed

@@ -24,6 +24,15 @@ constexpr uint32_t kSegs = 8;
 constexpr uint32_t kSegStride = 32;
 constexpr size_t kSegCursorBytes = kSegs * kSegStride * sizeof(uint32_t);
 
+// What a level leaves for the host loop, written by one small kernel into
+// pinned host memory: its counters, its segment counts and the table's
+// status (one write, no copies).
+struct LevelSummary {
+    LevelCounters lc;
+    uint32_t seg_n[kSegs];
+    lhs::DevStatus st;
+};
+
 // Device-side state of a graph-driven exploration (REACH_F_GRAPH): the level
 // loop's bookkeeping, advanced by a kernel after every level so that levels
 // can be replayed from a captured graph without the host.
