@@ -173,6 +173,88 @@ struct BatchModel {
 
 }  // namespace
 
+namespace lhs {
+
+lhs_status explore_prefix(lhs_table *t, const TableView &tv, const ModelView &mv, uint64_t cap, PrefixArea *d,
+                          PrefixArea *h, hipStream_t s, PrefixOut &out) {
+    // level 0 (s0 at frontier[0][0]) is tile 0 of queue position 0
+    const size_t head = offsetof(PrefixArea, levels);
+    std::memset(h, 0, head);
+    h->qs.tail = 1;
+    h->qs.remaining = 1;
+    h->qs.mask = kPrefixCells - 1;
+    ModelState &M = h->ms;
+    M.t = tv;
+    M.m = mv;
+    M.lc = t->level;
+    M.fr[0] = t->frontier[0];
+    M.fr[1] = t->frontier[1];
+    M.levels = d->levels;
+    M.cap = cap;
+    M.max_levels = kPrefixLevels;
+    M.handover = kPrefixHandover;
+    h->mp.total = 1;
+    h->mp.n_levels = 1;
+    LevelState &L = h->lv;
+    L.front = (unsigned long long)M.fr[0];
+    L.next = (unsigned long long)M.fr[1];
+    L.n_front = 1;
+    L.limit = cap ? (uint32_t)std::min<uint64_t>(cap - 1, 0xFFFFFFFFull) : 0xFFFFFFFFu;
+    L.tiles_total = 1;
+    L.tile_rows = kExpandBlock;
+    LHS_HIP(hipMemcpyAsync(d, h, head, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_init_ring, dim3(kPrefixCells / 256), dim3(256), 0, s, d->ring,
+                       (unsigned long long)kPrefixCells, 1u);
+    LHS_HIP(hipGetLastError());
+    const uint32_t tps = tps_expand(t);
+    const uint32_t tcap = trans_lds_entries(mv.P, mv.L, mv.K);
+    const size_t lds = (size_t)expand_lds_words(mv.W, tcap, tps) * sizeof(uint32_t);
+    lhs_status rc = with_shape(tps, t->line_slots, [&](auto G, auto LS) {
+        const void *fn = (const void *)k_batch_persistent<decltype(G)::value, decltype(LS)::value>;
+        int dev = 0, ncu = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kExpandBlock, lds) != hipSuccess ||
+            per_cu < 1)
+            return LHS_EDEVICE;
+        // the workgroups that fit at once, at most kPrefixGrid: every one
+        // holds a queue position while the levels are small
+        const uint32_t grid =
+            exploration_grid(t, std::min<uint64_t>((uint64_t)ncu * per_cu, kPrefixGrid));
+        const ModelState *ms = &d->ms;
+        ModelProgress *mp = &d->mp;
+        LevelState *lv = &d->lv;
+        QueueState *qs = &d->qs;
+        QCell *ring = d->ring;
+        uint32_t tc = tcap;
+        void *args[] = {&ms, &mp, &lv, &qs, &ring, &tc};
+        return hipLaunchKernel(fn, dim3(grid), dim3(kExpandBlock), args, lds, s) == hipSuccess ? LHS_OK
+                                                                                                : LHS_EDEVICE;
+    });
+    if (rc != LHS_OK)
+        return rc;
+    LHS_HIP(hipMemcpyAsync(h, d, offsetof(PrefixArea, ring), hipMemcpyDeviceToHost, s));
+    LHS_HIP(hipMemcpyAsync(t->status_host, t->status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    LHS_HIP(hipStreamSynchronize(s));
+    if (h->qs.error)
+        return (lhs_status)h->qs.error;
+    if (t->status_host->error)
+        return (lhs_status)t->status_host->error;
+    const ModelProgress &P = h->mp;
+    if (!P.done || P.overflow || P.n_levels > kPrefixLevels)
+        return LHS_EDEVICE;
+    out.levels.assign(h->levels + 1, h->levels + P.n_levels);
+    out.total = P.total;
+    out.edges = P.edges;
+    out.deadlocks = P.deadlocks;
+    out.cur = P.cur;
+    out.handed = P.handed != 0;
+    out.capped = P.capped != 0;
+    return LHS_OK;
+}
+
+}  // namespace lhs
+
 extern "C" {
 
 static lhs_status reach_explore_batch_impl(const reach_model *const *models, uint32_t n, const reach_opts *o,

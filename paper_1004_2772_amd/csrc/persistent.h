@@ -68,7 +68,8 @@ struct ModelState {
     uint32_t *fr[2];
     unsigned long long *levels;   // [max_levels] level counts (coherent stores)
     unsigned long long cap;
-    uint32_t max_levels, pad;
+    uint32_t max_levels;
+    uint32_t handover;            // stop after a level of more states (0 = never)
 };
 
 // Per-model progress: updated by whichever workgroup finalises a level, so
@@ -76,6 +77,7 @@ struct ModelState {
 struct ModelProgress {
     unsigned long long total, edges, deadlocks;
     uint32_t cur, n_levels, done, capped, overflow, error;
+    uint32_t handed, pad;   // handed: stopped after a level above M.handover
 };
 
 // Called by thread 0 of the finalising workgroup once model i is finished
@@ -110,6 +112,24 @@ __device__ __forceinline__ uint32_t level_tile_rows(QueueState *qs, uint32_t n_s
         rows <<= 1;
     return rows;
 }
+
+// A single-model exploration's first levels, run in one persistent launch
+// until a level exceeds a threshold (explore_prefix): its work queue, model
+// constants, progress, level state and level counts, in one region (device,
+// and its pinned mirror).
+constexpr uint32_t kPrefixHandover = 1u << 16;   // states of a level the prefix still expands
+constexpr uint32_t kPrefixLevels = 4096;
+constexpr uint32_t kPrefixGrid = 256;
+constexpr uint32_t kPrefixCells = 8192;   // > tiles of a level of kPrefixHandover states + kPrefixGrid
+static_assert(kPrefixCells >= 2 * (kPrefixHandover / kMinTileRows + 1 + kPrefixGrid), "prefix ring");
+struct PrefixArea {
+    QueueState qs;
+    ModelState ms;
+    ModelProgress mp;
+    LevelState lv;
+    unsigned long long levels[kPrefixLevels];
+    QCell ring[kPrefixCells];
+};
 
 // Finalise model i's level (M = its constants); block-wide.  Called by the workgroup that
 // completed its last tile.  Returns (uniformly) true when the model has a
@@ -163,6 +183,16 @@ __device__ bool finalize_level(const ModelState &M, ModelProgress *mp, LevelStat
                 st_coherent(&P.total, total);
                 const uint32_t cur = ld_coherent(&P.cur) ^ 1u;
                 st_coherent(&P.cur, cur);
+                if (M.handover && (n_next > M.handover || nl + 1u == M.max_levels)) {
+                    // a level too wide (or one level array full): the
+                    // caller expands it and the rest
+                    st_coherent(&P.handed, 1u);
+                    done = 1;
+                }
+            }
+            if (!done) {
+                const uint32_t cur = ld_coherent(&P.cur);
+                const unsigned long long total = ld_coherent(&P.total);
                 const uint32_t rows_per = level_tile_rows(qs, n_next);
                 nt = (n_next + rows_per - 1) / rows_per;
                 const uint64_t room = M.cap ? M.cap - total : 0xFFFFFFFFull;

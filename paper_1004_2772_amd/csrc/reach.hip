@@ -12,6 +12,7 @@
 #include "internal.h"
 #include "reach_internal.h"
 #include "expand_device.h"
+#include "persistent.h"
 
 using namespace lhs;
 
@@ -405,10 +406,24 @@ uint64_t auto_capacity(const reach_model *m) {
     return c;
 }
 
-// Host-driven level loop on table t (already sized, W matching).
+// A frontier of n entries stored densely from buf, as segments.
+SegFront seg_dense(const uint32_t *buf, uint32_t size, uint64_t n) {
+    SegFront f{};
+    f.buf = buf;
+    f.size = size;
+    for (uint32_t k = 0; k < kSegs; ++k) {
+        const uint64_t from = (uint64_t)k * size;
+        f.n[k] = n > from ? (uint32_t)std::min<uint64_t>(n - from, size) : 0u;
+    }
+    seg_tiles(f);
+    return f;
+}
+
+// Host-driven level loop on table t (already sized, W matching); with a
+// prefix area, the first (small) levels run in one persistent launch.
 lhs_status explore_host_loop(lhs_table *t, const reach_model *m, const uint2 *d_trans,
                              uint32_t max_levels, hipStream_t s, reach_result *r,
-                             uint32_t *d_init, bool parents) {
+                             uint32_t *d_init, bool parents, PrefixArea *d_pre, PrefixArea *h_pre) {
     const ModelView mv = model_view(m, d_trans);
     const TableView tv = bfs_view(t, parents);
     std::vector<uint64_t> levels;
@@ -427,7 +442,24 @@ lhs_status explore_host_loop(lhs_table *t, const reach_model *m, const uint2 *d_
     SegFront f = seg_root(t->frontier[0], size);
     int capped = 0;
     hipLaunchKernelGGL(k_zero_level, dim3(1), dim3(64), 0, s, t->level, t->segs);
-    while (true) {
+    bool finished = false;
+    if (d_pre) {
+        PrefixOut pre;
+        rc = explore_prefix(t, tv, mv, m->state_cap, d_pre, h_pre, s, pre);
+        if (rc != LHS_OK)
+            return rc;
+        levels.insert(levels.end(), pre.levels.begin(), pre.levels.end());
+        if (levels.size() > max_levels)
+            return LHS_EINVAL;
+        total = pre.total;
+        edges = pre.edges;
+        dead = pre.deadlocks;
+        capped = pre.capped;
+        cur = pre.cur;
+        finished = !pre.handed;
+        f = seg_dense(t->frontier[cur], size, levels.back());
+    }
+    while (!finished) {
         uint32_t limit = 0xFFFFFFFFu;
         if (m->state_cap)
             limit = (uint32_t)std::min<uint64_t>(m->state_cap - total, 0xFFFFFFFFull);
@@ -659,7 +691,8 @@ static lhs_status reach_explore_impl(const reach_model *m, const reach_opts *o, 
     // model upload through the device's workspace: one copy, no allocation
     Carve c;
     const size_t o_trans = c.take<uint2>(packed.size()), o_init = c.take<uint32_t>(W);
-    const size_t upload = c.off, o_ctx = c.take<GraphCtx>(1), o_actl = c.take<AsyncCtl>(1);
+    const size_t upload = c.off, o_ctx = c.take<GraphCtx>(1), o_actl = c.take<AsyncCtl>(1),
+                 o_pre = c.take<PrefixArea>(1);
     Workspace &ws = workspace(dev);
     std::unique_lock<std::mutex> lock(ws.mu);
     rc = ensure_bfs_buffers(t);
@@ -693,7 +726,8 @@ static lhs_status reach_explore_impl(const reach_model *m, const reach_opts *o, 
         else if (opts.flags & REACH_F_GRAPH)
             rc = explore_graph(t, m, d_trans, max_levels, s, r, d_init, at<GraphCtx>(ws.host, o_ctx), parents);
         else
-            rc = explore_host_loop(t, m, d_trans, max_levels, s, r, d_init, parents);
+            rc = explore_host_loop(t, m, d_trans, max_levels, s, r, d_init, parents, at<PrefixArea>(ws.dev, o_pre),
+                                   at<PrefixArea>(ws.host, o_pre));
         (void)hipEventRecord(ws.ev[1], s);
         if (hipEventSynchronize(ws.ev[1]) == hipSuccess) {
             float ms = 0;

@@ -76,6 +76,21 @@ void pack_model(const reach_model *m, std::vector<uint2> &out);
 ModelView model_view(const reach_model *m, const uint2 *d_trans);
 size_t expand_lds_bytes(uint32_t W, uint32_t tcap, uint32_t tps);
 lhs_status ensure_bfs_buffers(lhs_table *t);
+
+// The first levels of a single-model BFS in one persistent launch (the batch
+// kernel on one model), until a level exceeds kPrefixHandover states: small
+// levels then cost a tile's latency each instead of a launch and a host
+// round trip.  s0 must be frontier[0][0] and the level counters zero.
+struct PrefixArea;
+struct PrefixOut {
+    std::vector<uint64_t> levels;   // counts of levels 1, 2, ...
+    uint64_t total = 1, edges = 0, deadlocks = 0;
+    uint32_t cur = 0;               // frontier buffer of the last level
+    bool handed = false;            // stopped after a level above the threshold
+    bool capped = false;
+};
+lhs_status explore_prefix(lhs_table *t, const TableView &tv, const ModelView &mv, uint64_t cap,
+                          PrefixArea *d_area, PrefixArea *h_area, hipStream_t s, PrefixOut &out);
 uint64_t auto_capacity(const reach_model *m);
 // The view a BFS on t expands with: predecessor records when requested.
 TableView bfs_view(lhs_table *t, bool parents);

@@ -288,6 +288,7 @@ __device__ void admit_query(const ModelState &M, ModelProgress *mp, LevelState *
             st_coherent(&P.capped, 0u);
             st_coherent(&P.overflow, 0u);
             st_coherent(&P.error, 0u);
+            st_coherent(&P.handed, 0u);
             st_coherent(M.levels, 1ull);
             st_coherent(&lc->n_next, 0u);
             st_coherent(&lc->abort, 0u);
