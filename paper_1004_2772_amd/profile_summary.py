@@ -19,11 +19,12 @@
         stores, 64-byte row stores, 64-byte row loads and 64-bit CAS; copy-
         calibrated as above.
     python -m paper_1004_2772_amd.profile_summary traffic-sum FETCH_DB WRITE_DB --kernel K1 [--kernel K2] \
-        --runs R [--take D] --units N --unit-name NAME --copy-bytes B --out JSON [--cmd "..."]
+        --runs R [--take D1 [--take D2]] --units N --unit-name NAME --copy-bytes B --out JSON [--cmd "..."]
         FETCH_SIZE / WRITE_SIZE summed over the dispatches of the named kernels
-        (the first D in dispatch order, default all), divided by R (the program
-        ran the same work R times in them), scaled by the copy
-        probe as above; per run and per unit (e.g. per edge of an exploration).
+        (of each, the first D in dispatch order: one --take per kernel, or one
+        for all; default all), divided by R (the program ran the same work R
+        times in them), scaled by the copy probe as above; per run and per
+        unit (e.g. per edge of an exploration).
 """
 from __future__ import annotations
 
@@ -121,7 +122,7 @@ def main(argv=None):
     ts.add_argument("write_db")
     ts.add_argument("--kernel", action="append", required=True)
     ts.add_argument("--runs", type=int, required=True)
-    ts.add_argument("--take", type=int, default=0)
+    ts.add_argument("--take", type=int, action="append", default=[])
     ts.add_argument("--units", type=int, required=True)
     ts.add_argument("--unit-name", default="units")
     ts.add_argument("--copy-bytes", type=int, required=True)
@@ -193,11 +194,15 @@ def main(argv=None):
         missing = [n for n in names if n not in fetch or n not in write]
         if missing:
             sys.exit(f"kernels missing from the counter runs: {missing}")
-        take = a.take or None
-        fl = [v for n in names for _, v in fetch[n]][:take]
-        wl = [v for n in names for _, v in write[n]][:take]
+        takes = a.take or [0]
+        if len(takes) == 1:
+            takes = takes * len(names)
+        if len(takes) != len(names):
+            sys.exit("give one --take per --kernel, or one for all")
+        fl = [v for n, k in zip(names, takes) for _, v in fetch[n][:k or None]]
+        wl = [v for n, k in zip(names, takes) for _, v in write[n][:k or None]]
         kf, kw = sum(fl) / a.runs, sum(wl) / a.runs
-        res = dict(kernels=names, runs=a.runs, dispatches_per_run=len(fl) / a.runs,
+        res = dict(kernels=names, takes=takes, runs=a.runs, dispatches_per_run=len(fl) / a.runs,
                    fetch_scale=f_fetch, write_scale=f_write,
                    fetch_bytes_per_run=kf * 1024.0 * f_fetch, write_bytes_per_run=kw * 1024.0 * f_write,
                    units_per_run=a.units, unit=a.unit_name, command=a.cmd)

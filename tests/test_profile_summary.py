@@ -73,3 +73,19 @@ def test_probes_take_the_timed_dispatch_of_each_probe(tmp_path):
     assert r["random_256B_line_read"]["fetch_bytes"] == 256.0
     assert r["slot_store_8B"]["fetch_bytes"] == 16.0 and r["slot_store_8B"]["write_bytes"] == 8.0
     assert r["cas_64bit"]["write_bytes"] == 64.0 and r["cas_64bit"]["accesses"] == 1 << 26
+
+
+def test_traffic_sum_takes_per_kernel(tmp_path):
+    copy_bytes = 1 << 20
+    A = "void (anonymous namespace)::k_a<1, 8u>(int*)"
+    Bk = "(anonymous namespace)::k_b(int*)"
+    # two runs of [A, B, B], then more A and B work outside the runs
+    runs = [(A, 1024, 5.0), (Bk, 1024, 1.0), (Bk, 1024, 2.0)] * 2 + [(A, 1024, 1000.0), (Bk, 1024, 1000.0)]
+    f = _db(tmp_path / "f.db", "FETCH_SIZE", [(COPY, 4096, copy_bytes / 1024)] + runs)
+    w = _db(tmp_path / "w.db", "WRITE_SIZE", [(COPY, 4096, copy_bytes / 1024)] + runs)
+    out = tmp_path / "s.json"
+    ps.main(["traffic-sum", f, w, "--kernel", "void k_a<1, 8u>", "--kernel", "k_b", "--take", "2", "--take", "4",
+             "--runs", "2", "--units", "1", "--unit-name", "run", "--copy-bytes", str(copy_bytes), "--out", str(out)])
+    r = json.loads(out.read_text())
+    assert r["dispatches_per_run"] == 3
+    assert r["fetch_bytes_per_run"] == (5.0 + 1.0 + 2.0) * 1024
