@@ -203,7 +203,7 @@ constexpr uint32_t kServeMaxLevels = 1u << 16; // levels of one served query
 constexpr uint32_t kIdleSleepMax = 8;      // back-off steps (~0.4 us each) of an idle workgroup
 constexpr uint32_t kIdleLeave = 384;       // checks (~5 ms) finding no query on the GPU
                                            // before a workgroup leaves
-constexpr uint32_t kStallPolls = 1u << 19; // idle polls (~2 s) without any tile finished while
+constexpr uint32_t kStallPolls = 1u << 19; // idle polls (~2 s) without any level finished while
                                            // queries are unfinished: the launch has stalled
 
 struct ServeBox {
@@ -213,7 +213,7 @@ struct ServeBox {
     uint32_t stop;                   // host copy: leave once idle
     uint32_t closing;                // set by the first workgroup to leave; the
                                      // host clears it before the next launch
-    uint32_t beat;                   // tiles finished and admissions taken (any launch)
+    uint32_t beat;                   // levels finished (any launch)
     uint32_t pad;
     uint32_t admit_slot[kAdmitRing]; // slot of admission k, at k % kAdmitRing
 };
@@ -387,8 +387,8 @@ __global__ __launch_bounds__(kExpandBlock) void k_serve(const ModelState *ms, Mo
                     }
                 }
                 if (act == kNone) {
-                    // bounded: with queries unfinished, some workgroup
-                    // finishes a tile every few microseconds
+                    // bounded: with queries unfinished, some level
+                    // finishes every few milliseconds at most
                     const uint32_t b = ld_coherent(&box->beat);
                     stall = b == last_beat ? stall + 1u : 0u;
                     last_beat = b;
@@ -448,7 +448,12 @@ __global__ __launch_bounds__(kExpandBlock) void k_serve(const ModelState *ms, Mo
             const uint32_t total = ld_coherent(&L.tiles_total);
             wait_vm_complete();
             s_fin = atomicAdd(&L.tiles_done, 1u) + 1u == total;
-            atomicAdd(&box->beat, 1u);
+            // progress for the idle workgroups' stall bound: one per level
+            // (a level, even a query's deepest chain of one-tile levels,
+            // ends well within the bound), not one per tile on a shared
+            // address
+            if (s_fin)
+                atomicAdd(&box->beat, 1u);
         }
         __syncthreads();
         if (s_fin && finalize_level<true>(s_M, mp, lv, i, qs, ring, ServeDone{box, done, mp})) {
