@@ -112,3 +112,22 @@ def test_repeatable(lhs):
     a, _ = _gpu(lhs, m)
     b, _ = _gpu(lhs, m)
     assert result_fields(a) == result_fields(b)
+
+
+@pytest.mark.parametrize("workers", [1, 3])
+def test_level_spills_across_segments(lhs, workers):
+    """With one or three workgroups every new state goes to their one or three
+    segment cursors, so the 164 086-state level of this model overflows its
+    first segment (2^20 slots / 8) into the next ones.  The next level reads
+    it across segments, and the capped level after it is rolled back across
+    them.  Counts and set equal the oracle's."""
+    m = gen.big_model(cap=400_000)
+    print(f"\n[reach] level spill, {workers} workgroup(s)", flush=True)
+    want = oracle.reach(m, keep_states=True)
+    assert max(want.level_counts) > (1 << 20) // 8
+    with lhs.Table(1 << 20, m.W) as t:
+        t.set_workers(workers)
+        got = lhs.reach_explore(m, table=t)
+        rows, _ = check_table_invariants(t)
+    assert result_fields(got) == result_fields(want)
+    assert_same_set(rows, want.states, "big model capped at 400 000")
