@@ -341,3 +341,27 @@ def test_serve_query_without_lds_transitions_joins_a_launch(lhs):
         launches = srv.stats()["steps"] - l0
     print("launches:", launches, flush=True)
     assert launches == 1
+
+
+@MODES
+def test_serve_destroy_with_queries_outstanding(lhs, rounds):
+    """Destroying a server while queries are queued and on the GPU ends every
+    one of them first (the worker drains its queue) and returns; a caller
+    table it held is free again afterwards and keeps its query's set."""
+    models = gen.batch_models()
+    golden = _golden_mix()
+    big = sorted(range(len(models)), key=lambda k: -golden[k]["total"])[:3]
+    k0 = big[0]
+    print(f"\n[serve] destroy with {big} and more outstanding, rounds={rounds}", flush=True)
+    with lhs.Table(1 << 21, models[k0].W, lhs.config()) as t:
+        srv = lhs.Server(capacity=1 << 21, cfg=lhs.config(), rounds=rounds)
+        srv.submit(models[k0], table=t)
+        for k in big[1:] + list(range(8)):
+            srv.submit(models[k])
+        t0 = time.time()
+        srv.close()
+        assert time.time() - t0 < 60
+        rows, _ = t.dump()
+        assert len(rows) == golden[k0]["total"]
+        d = oracle.digest(rows)
+        assert [d[0], hex(d[1]), hex(d[2])] == golden[k0]["digest"]
