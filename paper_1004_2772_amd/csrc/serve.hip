@@ -1,7 +1,14 @@
 // Reachability server with continuous batching (reach_server_*).
 //
-// A worker thread owns the GPU side.  It works in rounds of kRoundSteps BFS
-// level steps; between rounds it
+// A worker thread owns the GPU side, in one of two modes.
+//
+// Persistent (the default).  One launch of resident workgroups serves every
+// query on the GPU: a query is admitted, expanded level by level and retired
+// inside the launch, and the host only readies slots, posts admissions and
+// reads completion records (the protocol is described above k_serve below).
+//
+// Rounds (REACH_SERVER_F_ROUNDS).  The worker works in rounds of kRoundSteps
+// BFS level steps; between rounds it
 //   * admits queued queries, first come first served, while their tables fit
 //     the device-memory budget (tables come from a resident pool keyed by
 //     capacity and width; pooled tables of other shapes are freed when room
@@ -13,10 +20,11 @@
 // finishes last does every query's level bookkeeping (level count, cap test,
 // frontier swap, the next step's tile prefix), so a round runs without the
 // host and a step costs one kernel boundary.  A capped level is not undone:
-// the query ends there and its table is emptied when it is next handed out.  A query that arrives while
-// others are on the GPU joins at the next round and its work overlaps
-// theirs; its result is exactly the one reach_explore computes for it alone
-// (same kernels, its own table).
+// the query ends there and its table is emptied when it is next handed out.
+//
+// In both modes a query that arrives while others are on the GPU joins them
+// and its work overlaps theirs; its result is exactly the one reach_explore
+// computes for it alone (same expansion, its own table).
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
