@@ -63,6 +63,7 @@ struct SuccVec {
 //   tr       [tcap] u64  the model's packed transitions (when they fit)
 //   pick     [256]       the (state, enabled pair) of each successor of the
 //                        current pass (P*K <= 64), in the mask area
+//   dedup    [512]       the pass's successors by hash (G = 1), behind pick
 //     (queue [kQueue]    enabled (state, process, transition) when P*K > 64,
 //                        in the same words)
 //   succ_cnt [256]       successors per tile state (edges, deadlocks)
@@ -76,6 +77,8 @@ constexpr uint32_t kNewBuf = 1536;
 constexpr uint32_t kEagerRoom = 1u << 22;
 constexpr uint32_t kMaskArea = 2 * kExpandBlock + 258;
 static_assert(kQueue <= kMaskArea, "queue shares the mask area");
+constexpr uint32_t kDedupCells = 512;   // twice the successors of a pass
+static_assert(kExpandBlock + kDedupCells <= kMaskArea, "pick and the dedup cells share the mask area");
 __host__ __device__ constexpr uint32_t expand_lds_words(uint32_t W, uint32_t tcap, uint32_t G) {
     return kExpandBlock * (W | 1u) + 2 * tcap + kMaskArea + kExpandBlock +
            (G > 1 ? 4 * kExpandBlock : 0u) + kNewBuf;
@@ -301,8 +304,12 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
 // from the LDS copy of the transition table; a block prefix sum over the mask
 // popcounts numbers the tile's successors.  Before each pass of 256, every
 // state lane writes its successors that fall in the pass, in bit order, to
-// their places in an LDS list, and lane q of the pass takes entry q.  Wider models (P*K > 64) enumerate candidates 256 at a time into an
-// LDS ring.
+// their places in an LDS list, and lane q of the pass takes entry q.  With
+// one lane per operation, successors of a pass that are the same state are
+// merged in an LDS hash set before the table is probed (interleavings of
+// independent moves make such diamonds common among neighbouring frontier
+// states), so each distinct state of a pass costs one find-or-put.  Wider
+// models (P*K > 64) enumerate candidates 256 at a time into an LDS ring.
 //
 // New states are compacted into LDS and appended to next[] with one atomic
 // per workgroup and flush: the level's append cursor is a single address that
@@ -473,10 +480,11 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
             flush_new_slots<COHERENT>(nbuf, next, lc, limit);
     };
     // ---- find-or-put of successors d0/d1/hq[0, take); new slots to nbuf ----
-    auto fop_pass = [&](uint32_t take) {
+    // skip (G == 1): this lane's successor is another lane's in the same pass
+    auto fop_pass = [&](uint32_t take, bool skip) {
         for (uint32_t r = 0; r < G; ++r) {
             const uint32_t q = r * NG + gi;
-            const bool active = q < take;
+            const bool active = q < take && !(G == 1 && skip);
             uint32_t slot, code;
             if constexpr (G == 1) {
                 find_or_put_wave<LS, SuccVec, CL>(t, &ws[tid / 64], smem, make_uint2(my_d0, my_d1), my_h,
@@ -508,17 +516,20 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
             flush_new();
         return s_abort != 0;
     };
-    // decode successor (st, p, k) into hq/d0/d1[i] (G > 1) or this lane's
-    // registers (G == 1, i == tid)
-    auto stage_successor = [&](uint32_t i, uint32_t st, uint32_t p, uint32_t k) {
+    // successor (p, k) of tile row st
+    auto succ_of = [&](uint32_t st, uint32_t p, uint32_t k) -> SuccVec {
         const uint32_t *row = tile + st * stride;
         const uint2 x = trans_at(((uint64_t)p * m.L + row[p]) * m.K + k);
         const uint32_t evar = x.x >> 24;
-        const uint32_t ew = evar == 0xFFu ? 0xFFu : m.P + evar;
-        const SuccVec v{row, p, x.x & 0xFFFFu, ew == 0xFFu ? 0xFFFFFFFFu : ew, x.y >> 16};
+        return SuccVec{row, p, x.x & 0xFFFFu, evar == 0xFFu ? 0xFFFFFFFFu : m.P + evar, x.y >> 16};
+    };
+    // decode successor (st, p, k) into hq/d0/d1[i] (G > 1) or this lane's
+    // registers (G == 1, i == tid)
+    auto stage_successor = [&](uint32_t i, uint32_t st, const SuccVec &v) {
+        const uint32_t ew = v.ew == 0xFFFFFFFFu ? 0xFFu : v.ew;
         const uint64_t h = hash_vec(v, W, t.seed);
-        const uint32_t e0 = (st * stride) | (p << 16) | (ew << 24);
-        const uint32_t e1 = (x.x & 0xFFFFu) | ((x.y >> 16) << 16);
+        const uint32_t e0 = (st * stride) | (v.p << 16) | (ew << 24);
+        const uint32_t e1 = v.target | (v.ev << 16);
         if constexpr (G == 1) {
             my_h = h;
             my_d0 = e0;
@@ -568,6 +579,12 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
         // that fall in the pass into `pick` (the mask area); lane q of the
         // pass then stages successor s0 + q.
         uint32_t *pick = reinterpret_cast<uint32_t *>(masks);
+        uint32_t *dedup = pick + kBlock;
+        auto pick_succ = [&](uint32_t e) -> SuccVec {
+            const uint32_t j = e & 0xFFu;
+            const uint32_t p = m.K == 1 ? j : __umulhi(j, m.magic_K);
+            return succ_of(e >> 8, p, j - p * m.K);
+        };
         for (uint32_t s0 = 0; s0 < total && !aborted; s0 += kBlock) {
             const uint32_t take = min(total - s0, kBlock);
             while (rem && nextq < s0 + kBlock) {
@@ -575,14 +592,51 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
                 rem &= rem - 1;
                 ++nextq;
             }
+            if constexpr (G == 1)
+                for (uint32_t i = tid; i < kDedupCells; i += kBlock)
+                    dedup[i] = 0;
             __syncthreads();
+            bool skip = false;
             if (tid < take) {
-                const uint32_t e = pick[tid], j = e & 0xFFu;
-                const uint32_t p = m.K == 1 ? j : __umulhi(j, m.magic_K);
-                stage_successor(tid, e >> 8, p, j - p * m.K);
+                const uint32_t e = pick[tid];
+                const SuccVec v = pick_succ(e);
+                stage_successor(tid, e >> 8, v);
+                if constexpr (G == 1) {
+                    // Successors of one pass that are the same state (two
+                    // interleavings reaching it) go to the table once.  Each
+                    // lane claims a cell of an LDS hash set keyed by its
+                    // hash; a lane that meets its own hash tag in a cell
+                    // stops there, and takes that lane's find-or-put as its
+                    // own once the full rows compare equal (a tag that
+                    // belongs to another state leaves it on its own).  The
+                    // lane that claimed the cell never skips.
+                    const uint32_t tag = (uint32_t)(my_h >> 41) << 9;
+                    uint32_t c = (uint32_t)(my_h >> 32) & (kDedupCells - 1), other = 0;
+                    for (;;) {
+                        const uint32_t old = atomicCAS(&dedup[c], 0u, tag | (tid + 1));
+                        if (old == 0)
+                            break;
+                        if ((old & ~511u) == tag) {
+                            other = old & 511u;
+                            break;
+                        }
+                        c = (c + 1) & (kDedupCells - 1);
+                    }
+                    if (other) {
+                        // one compare per lane, its words loaded independently
+                        const SuccVec o = pick_succ(pick[other - 1]);
+                        uint32_t diff = 0, w = 0;
+                        for (; w + 4 <= W; w += 4)
+                            diff |= (v.get(w) ^ o.get(w)) | (v.get(w + 1) ^ o.get(w + 1)) |
+                                    (v.get(w + 2) ^ o.get(w + 2)) | (v.get(w + 3) ^ o.get(w + 3));
+                        for (; w < W; ++w)
+                            diff |= v.get(w) ^ o.get(w);
+                        skip = diff == 0;
+                    }
+                }
             }
             __syncthreads();
-            aborted = fop_pass(take);
+            aborted = fop_pass(take, skip);
         }
     } else {
         // ---- wide models: candidates 256 at a time into the LDS ring ------
@@ -627,11 +681,11 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
             const uint32_t take = min(tail - head, kBlock);
             if (tid < take) {
                 const uint32_t e = queue[(head + tid) & (kQueue - 1)];
-                stage_successor(tid, e & 0xFFu, (e >> 8) & 0xFFu, e >> 16);
+                stage_successor(tid, e & 0xFFu, succ_of(e & 0xFFu, (e >> 8) & 0xFFu, e >> 16));
             }
             __syncthreads();
             head += take;
-            if (fop_pass(take)) {
+            if (fop_pass(take, false)) {
                 aborted = true;
                 break;
             }

@@ -659,12 +659,31 @@ __device__ __forceinline__ void find_or_put_wave(const TableView &t, WaveScratch
                 known_done = (donem >> k) & 1u;
             }
         }
-        // ---- claim phase ----------------------------------------------------
+        // ---- claim phase, with the compare of matches already seen DONE ----
+        // Rows of slots the snapshot showed DONE are compared while the
+        // claims are in flight: their loads are issued after that snapshot
+        // completed, behind the acquire below, and DONE never goes away.
+        const bool early = kind == 2 && known_done;
+        const uint64_t em = __ballot(early);
+        if (em)
+            after_done_observed();
         bool won = false;
-        if (kind == 1) {
-            uint64_t old = 0;
+        uint64_t old = 0;
+        if (kind == 1)
             __hip_atomic_compare_exchange_strong(t.bucket + slot, &old, memo, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (em) {
+            const bool eq = coop_rows_equal<Vec>(ws, smem, t.data, t.W, early, slot, d);
+            if (early) {
+                if (eq) {
+                    out_slot = slot;
+                    out_code = kSeen;
+                    finished = true;
+                }
+                kind = 0;   // a different row: the walk goes on
+            }
+        }
+        if (kind == 1) {
             if (old == 0) {
                 won = true;
             } else {
