@@ -182,17 +182,45 @@ typedef struct lhs_info {
     uint32_t tps_expand;
     uint64_t lines_probed; /* lines examined by find-or-puts while counted
                               (lhs_set_counters); the paper's probe count     */
+    uint64_t merged;       /* successors that explorations merged into an
+                              equal successor of the same pass while counted
+                              (lhs_set_counters, lhs_set_merge)               */
 } lhs_info;
 
 /* Table geometry and device counters (synchronises the last stream). */
 lhs_status lhs_get_info(lhs_table *t, lhs_info *out);
 
 /* Optional device counters for later calls on t: LHS_COUNT_LINES adds the
- * number of lines every find-or-put examines to lhs_info.lines_probed (one
- * more atomic per wavefront; off by default).  0 turns them off; the counts
- * restart at lhs_clear.  LHS_EINVAL for unknown bits. */
+ * number of lines every find-or-put examines to lhs_info.lines_probed,
+ * LHS_COUNT_MERGED the successors merged by explorations to lhs_info.merged
+ * (one more atomic per wavefront each; off by default).  0 turns them off;
+ * the counts restart at lhs_clear.  LHS_EINVAL for unknown bits. */
 #define LHS_COUNT_LINES 1u
+#define LHS_COUNT_MERGED 2u
 lhs_status lhs_set_counters(lhs_table *t, uint32_t flags);
+
+/* How explorations on t (reach_explore in every mode, the batch, the
+ * server) treat successors of one expansion pass that are the same state.
+ * Algorithm 1 runs find-or-put once per successor.  Two interleavings of
+ * independent moves often reach one state from neighbouring frontier
+ * states, and find-or-put of an equal vector has one answer (its slot), so
+ * with LHS_MERGE_ON (the default) a workgroup gives each distinct state of
+ * a pass of 256 successors one find-or-put in the table, and the equal ones
+ * take it as seen.  The test is exact: a hash-tag match is confirmed on the
+ * full vectors, else the successor runs its own find-or-put.
+ *   LHS_MERGE_OFF          one find-or-put per successor, as Algorithm 1;
+ *   LHS_MERGE_NARROW_TAGS  merging with one-bit tags, so that most tag
+ *                          matches belong to other states (a check of that
+ *                          path: slower, same results).
+ * Reachable set, level counts, edges and deadlocks do not depend on the
+ * mode; wait and CAS-failure counts do.  Applies to expansions with one
+ * lane per successor (lhs_set_threads_per_state 1, the default) of models
+ * with at most 64 (process, transition) pairs.  LHS_EINVAL for a null table
+ * or an unknown mode. */
+#define LHS_MERGE_ON 0u
+#define LHS_MERGE_OFF 1u
+#define LHS_MERGE_NARROW_TAGS 2u
+lhs_status lhs_set_merge(lhs_table *t, uint32_t mode);
 
 /* Number of workers of the explorations on t (reach_explore, with or
  * without REACH_F_GRAPH / REACH_F_ASYNC): at most max_workgroups workgroups

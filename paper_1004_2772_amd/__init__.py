@@ -29,13 +29,18 @@ REACH_F_GRAPH = 2
 REACH_F_PARENTS = 4
 REACH_F_ASYNC = 8
 REACH_SERVER_F_ROUNDS = 1
+COUNT_LINES = 1
+COUNT_MERGED = 2
+MERGE_ON = 0
+MERGE_OFF = 1
+MERGE_NARROW_TAGS = 2
 PROBES = {"double": 0, "linear": 1, "quadratic": 2}
 TUNE_TABLE, TUNE_BATCH = 0, 1
 
 #: every symbol include/lhs.h declares
 EXPORTS = ["lhs_strerror", "lhs_create", "lhs_create_ex", "lhs_get_config", "lhs_destroy",
            "lhs_clear", "lhs_find_or_put", "lhs_set_threads_per_state", "lhs_set_counters",
-           "lhs_set_workers", "lhs_tune_load", "lhs_tune_clear", "lhs_tune_lookup",
+           "lhs_set_merge", "lhs_set_workers", "lhs_tune_load", "lhs_tune_clear", "lhs_tune_lookup",
            "lhs_check", "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info",
            "reach_explore", "reach_result_free", "reach_explore_noalloc", "reach_explore_batch", "reach_trace",
            "reach_deadlock_slots",
@@ -58,7 +63,7 @@ class LhsInfo(ctypes.Structure):
                 ("wait_hits", ctypes.c_uint64), ("cas_failures", ctypes.c_uint64),
                 ("error", ctypes.c_uint32), ("probe", ctypes.c_uint32),
                 ("tps_find_or_put", ctypes.c_uint32), ("tps_expand", ctypes.c_uint32),
-                ("lines_probed", ctypes.c_uint64)]
+                ("lines_probed", ctypes.c_uint64), ("merged", ctypes.c_uint64)]
 
 
 class LhsConfig(ctypes.Structure):
@@ -152,6 +157,7 @@ def lib() -> ctypes.CDLL:
         L.lhs_set_threads_per_state.argtypes = [p, u32]
         L.lhs_set_counters.argtypes = [p, u32]
         L.lhs_set_workers.argtypes = [p, u32]
+        L.lhs_set_merge.argtypes = [p, u32]
         L.lhs_count.argtypes = [p, ctypes.POINTER(u64)]
         L.lhs_dump.argtypes = [p, p, p, u64, ctypes.POINTER(u64)]
         L.lhs_dump_slots.argtypes = [p, p]
@@ -182,7 +188,8 @@ def lib() -> ctypes.CDLL:
         L.lhs_probe_copy.argtypes = [p, p, u64, p]
         for name in ("lhs_probe_random_lines", "lhs_probe_random_cas", "lhs_probe_random_access", "lhs_probe_copy",
                      "lhs_create", "lhs_destroy", "lhs_clear", "lhs_find_or_put", "lhs_check",
-                     "lhs_set_threads_per_state", "lhs_set_counters", "lhs_set_workers", "lhs_create_ex",
+                     "lhs_set_threads_per_state", "lhs_set_counters", "lhs_set_merge", "lhs_set_workers",
+                     "lhs_create_ex",
                      "lhs_get_config",
                      "lhs_tune_load", "lhs_tune_clear", "lhs_tune_lookup",
                      "lhs_count", "lhs_dump", "lhs_dump_slots", "lhs_get_info", "reach_explore",
@@ -319,8 +326,15 @@ class Table:
         _check(lib().lhs_set_threads_per_state(self.handle, tps), "lhs_set_threads_per_state")
 
     def set_counters(self, flags: int):
-        """LHS_COUNT_LINES (1): count lines probed (lhs_info.lines_probed)."""
+        """LHS_COUNT_LINES (1): count lines probed (lhs_info.lines_probed);
+        LHS_COUNT_MERGED (2): count successors merged in expansion passes
+        (lhs_info.merged)."""
         _check(lib().lhs_set_counters(self.handle, flags), "lhs_set_counters")
+
+    def set_merge(self, mode: int):
+        """MERGE_ON (default), MERGE_OFF or MERGE_NARROW_TAGS: how explorations
+        on this table treat equal successors of one expansion pass."""
+        _check(lib().lhs_set_merge(self.handle, mode), "lhs_set_merge")
 
     def set_workers(self, max_workgroups: int):
         """At most this many workgroups expand states in explorations on this

@@ -29,8 +29,10 @@ namespace {
 
 constexpr uint32_t kMaxBatch = 1024;   // models per call (tile prefix lives in LDS)
 
+// With 8-slot lines, at least four waves per SIMD (at most 128 VGPRs): four
+// workgroups per CU, as the LDS layout allows.  Wider lines would spill.
 template <int G, uint32_t LS>
-__global__ __launch_bounds__(kExpandBlock) void k_batch_persistent(const ModelState *__restrict__ ms,
+__global__ __launch_bounds__(kExpandBlock, LS == 8 ? 4 : 1) void k_batch_persistent(const ModelState *__restrict__ ms,
                                                                    ModelProgress *mp, LevelState *lv,
                                                                    QueueState *qs, QCell *ring,
                                                                    uint32_t tcap) {

@@ -601,7 +601,7 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
                 const uint32_t e = pick[tid];
                 const SuccVec v = pick_succ(e);
                 stage_successor(tid, e >> 8, v);
-                if constexpr (G == 1) {
+                if (G == 1 && !(t.flags & kNoMerge)) {
                     // Successors of one pass that are the same state (two
                     // interleavings reaching it) go to the table once.  Each
                     // lane claims a cell of an LDS hash set keyed by its
@@ -609,8 +609,11 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
                     // stops there, and takes that lane's find-or-put as its
                     // own once the full rows compare equal (a tag that
                     // belongs to another state leaves it on its own).  The
-                    // lane that claimed the cell never skips.
-                    const uint32_t tag = (uint32_t)(my_h >> 41) << 9;
+                    // lane that claimed the cell never skips.  (kNarrowTags
+                    // keeps one tag bit, so that most tag matches are other
+                    // states: a check of that path.)
+                    const uint32_t tag = ((uint32_t)(my_h >> 41) << 9) &
+                                         ((t.flags & kNarrowTags) ? 1u << 9 : ~0u);
                     uint32_t c = (uint32_t)(my_h >> 32) & (kDedupCells - 1), other = 0;
                     for (;;) {
                         const uint32_t old = atomicCAS(&dedup[c], 0u, tag | (tid + 1));
@@ -632,6 +635,7 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
                         for (; w < W; ++w)
                             diff |= v.get(w) ^ o.get(w);
                         skip = diff == 0;
+                        cnt.merged += skip;
                     }
                 }
             }

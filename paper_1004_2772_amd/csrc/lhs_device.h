@@ -43,15 +43,19 @@ struct DevStatus {
     unsigned long long wait_hits;
     unsigned long long cas_failures;
     unsigned long long lines;   // lines probed (only while counted, see TableView::flags)
+    unsigned long long merged;  // successors merged into an equal one of their pass (counted)
 };
 
-enum : uint32_t { kCountLines = 1 };
+// TableView::flags: counters to keep, and how expansions merge equal
+// successors of a pass (expand_tile)
+enum : uint32_t { kCountLines = 1, kCountMerged = 2, kNoMerge = 4, kNarrowTags = 8 };
 
 // Per-lane event counts, reduced per wavefront before touching DevStatus.
 struct LaneCounters {
     uint32_t waits = 0;
     uint32_t cas_failures = 0;
     uint32_t lines = 0;
+    uint32_t merged = 0;
 };
 
 // Probe sequence across lines (after the home line's walk).
@@ -71,7 +75,7 @@ struct TableView {
     // kDeadRecord deadlock states expanded]
     uint32_t *parent;
     uint32_t *dead_rec;
-    uint32_t flags;          // kCountLines: add lines probed to status->lines
+    uint32_t flags;          // kCount*, kNoMerge, kNarrowTags
 };
 constexpr uint32_t kDeadRecord = 1024;
 
@@ -749,6 +753,7 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
 __device__ __forceinline__ void flush_counters(const TableView &t, const LaneCounters &c) {
     const uint32_t w = wave_sum(c.waits), f = wave_sum(c.cas_failures);
     const uint32_t l = (t.flags & kCountLines) ? wave_sum(c.lines) : 0u;
+    const uint32_t mg = (t.flags & kCountMerged) ? wave_sum(c.merged) : 0u;
     if (__lane_id() == 0) {
         if (w)
             atomicAdd(&t.status->wait_hits, (unsigned long long)w);
@@ -756,6 +761,8 @@ __device__ __forceinline__ void flush_counters(const TableView &t, const LaneCou
             atomicAdd(&t.status->cas_failures, (unsigned long long)f);
         if (l)
             atomicAdd(&t.status->lines, (unsigned long long)l);
+        if (mg)
+            atomicAdd(&t.status->merged, (unsigned long long)mg);
     }
 }
 

@@ -137,10 +137,7 @@ __global__ void k_zero_u64(uint64_t *p, uint64_t n) {
 }
 
 __global__ void k_zero_status(DevStatus *st) {
-    st->error = 0;
-    st->wait_hits = 0;
-    st->cas_failures = 0;
-    st->lines = 0;
+    *st = DevStatus{};
 }
 
 // Done slots are scanned in chunks of kLineSlots slots (any line width).
@@ -407,9 +404,16 @@ lhs_status lhs_set_threads_per_state(lhs_table *t, uint32_t tps) {
 }
 
 lhs_status lhs_set_counters(lhs_table *t, uint32_t flags) {
-    if (!t || (flags & ~LHS_COUNT_LINES))
+    if (!t || (flags & ~(LHS_COUNT_LINES | LHS_COUNT_MERGED)))
         return LHS_EINVAL;
     t->counters = flags;
+    return LHS_OK;
+}
+
+lhs_status lhs_set_merge(lhs_table *t, uint32_t mode) {
+    if (!t || mode > LHS_MERGE_NARROW_TAGS)
+        return LHS_EINVAL;
+    t->merge = mode;
     return LHS_OK;
 }
 
@@ -529,6 +533,7 @@ lhs_status lhs_get_info(lhs_table *t, lhs_info *out) {
     out->wait_hits = st.wait_hits;
     out->cas_failures = st.cas_failures;
     out->lines_probed = st.lines;
+    out->merged = st.merged;
     out->error = st.error;
     return LHS_OK;
 }

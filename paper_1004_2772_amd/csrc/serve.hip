@@ -110,10 +110,7 @@ __device__ void step_finalize(BatchSlot *slots, StepCtl *ctl, LevelCounters *lc,
             if (C.done)
                 S.n_front = 0;
             lc[a] = LevelCounters{0, 0, 0, 0};
-            st[a].error = 0;
-            st[a].wait_hits = 0;
-            st[a].cas_failures = 0;
-            st[a].lines = 0;
+            st[a] = DevStatus{};
             tiles = (S.n_front + kExpandBlock - 1) / kExpandBlock;
         }
         scan[a] = tiles;
@@ -514,10 +511,7 @@ __global__ void k_zero_step(LevelCounters *lc, DevStatus *st, uint32_t n, uint32
         *arrived = 0;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         lc[i] = LevelCounters{0, 0, 0, 0};
-        st[i].error = 0;
-        st[i].wait_hits = 0;
-        st[i].cas_failures = 0;
-        st[i].lines = 0;
+        st[i] = DevStatus{};
     }
 }
 

@@ -136,6 +136,12 @@ def test_set_workers_rejects_null():
     assert lhs.lib().lhs_set_workers(None, 4) == 1
 
 
+def test_set_merge_and_counters_reject_bad_arguments():
+    L = lhs.lib()
+    assert L.lhs_set_merge(None, lhs.MERGE_ON) == 1
+    assert L.lhs_set_counters(None, lhs.COUNT_MERGED) == 1
+
+
 def test_probes_reject_bad_arguments():
     L = lhs.lib()
     fake, sink = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21)   # never dereferenced: rejected first

@@ -65,6 +65,31 @@ def test_batch_small_vs_oracle(lhs, flags):
             t.close()
 
 
+@pytest.mark.parametrize("mode", ["off", "narrow_tags"])
+def test_batch_merge_modes_vs_oracle(lhs, mode):
+    """The persistent batch with equal successors not merged, or merged
+    through one-bit tags, on half of its tables: every result is still the
+    oracle's."""
+    code = {"off": lhs.MERGE_OFF, "narrow_tags": lhs.MERGE_NARROW_TAGS}[mode]
+    models = _mixed_models(12, 4) + [gen.big_model(cap=1 << 16)]
+    caps = [40_000] * 12 + [1 << 16]
+    wants = [oracle.reach(m, cap=c, keep_states=True) for m, c in zip(models, caps)]
+    print(f"\n[batch] merge={mode} 13 models", flush=True)
+    tables = [lhs.Table(1 << 18, m.W) for m in models]
+    try:
+        for i, t in enumerate(tables):
+            if i % 2 == 0:
+                t.set_merge(code)
+        got = lhs.reach_explore_batch(models, tables=tables, caps=caps)
+        for m, g, w, t in zip(models, got, wants, tables):
+            assert result_fields(g) == result_fields(w), m.describe()
+            rows, _ = t.dump()
+            assert_same_set(rows, w.states, m.describe())
+    finally:
+        for t in tables:
+            t.close()
+
+
 def test_batch_equals_alone(lhs):
     models = _mixed_models(8, 3) + [gen.big_model(cap=1 << 16), gen.tiny_cyclic()]
     for m in models:

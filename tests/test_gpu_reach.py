@@ -67,6 +67,39 @@ def test_golden(lhs, fx):
         assert_same_set(rows, oracle.reach(m, cap=case["cap"], keep_states=True).states, fx["name"])
 
 
+@pytest.mark.parametrize("mode", ["on", "off", "narrow_tags"])
+def test_merge_modes(lhs, mode):
+    """Equal successors of one expansion pass merged before the table is
+    probed (the default), not merged (one find-or-put per successor), or
+    merged through one-bit hash tags (most tag matches are then other states
+    and fall back to their own find-or-put): set, level counts, edges and
+    deadlocks are the oracle's in every mode, and the merge counter says what
+    happened."""
+    code = {"on": lhs.MERGE_ON, "off": lhs.MERGE_OFF, "narrow_tags": lhs.MERGE_NARROW_TAGS}[mode]
+    cases = [(gen.tiny_cyclic(), None), (gen.big_model(cap=1 << 18), 1 << 18)]
+    cases += [(m, 5000) for m in _random_models(6, 91)]
+    merged = {}
+    for m, cap in cases:
+        print(f"\n[reach] merge={mode} {m.describe()}", flush=True)
+        want = oracle.reach(m, cap=cap, keep_states=True)
+        with lhs.Table(_capacity_for(max(want.total, cap or 0)), m.W) as t:
+            t.set_merge(code)
+            t.set_counters(lhs.COUNT_MERGED)
+            got = lhs.reach_explore(m, cap=cap, table=t)
+            rows, _ = check_table_invariants(t)
+            merged[m.name or m.seed] = (t.info()["merged"], got.edges)
+        assert result_fields(got) == result_fields(want), m.describe()
+        assert_same_set(rows, want.states, m.describe())
+    print(f"[reach] merged/edges: {merged}", flush=True)
+    big, edges = merged["big12x16"]
+    if mode == "off":
+        assert all(v == 0 for v, _ in merged.values())
+    elif mode == "on":
+        # neighbouring states' interleavings meet: a large share of a pass repeats
+        assert big > edges // 10
+    assert all(v < e or e == 0 for v, e in merged.values())
+
+
 def _random_models(n, seed):
     rng = np.random.default_rng(seed)
     for i in range(n):
