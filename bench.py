@@ -22,7 +22,9 @@ Extra legs in the same JSON line:
                  its table's line width, and its launch time over the sum of
                  its accesses priced at the probes' rates.
   bfs          : level-synchronous BFS of the 12-process x 16-local synthetic
-                 model capped at 2^27 states (states/s, edges/s).
+                 model capped at 2^27 states (states/s, edges/s); the same BFS
+                 with one find-or-put per successor (merging of equal
+                 successors of a pass off), and the share of edges merged.
   batch        : the 64-model mix (2-16 processes, widths 4-32, 10^3-10^6
                  states each) explored in one persistent launch, in one launch
                  per step, and one model at a time, on the same tables.
@@ -419,6 +421,27 @@ def main():
         bfs["graph_levels"] = {"median_ms": round(gg, 2), "states_per_s": round(rg.total / (gg / 1e3), 1),
                                "same_result": (rg.total, rg.level_counts, rg.edges) ==
                                               (res.total, res.level_counts, res.edges)}
+        # equal successors of a pass merged (the default) against one
+        # find-or-put per successor, and the share of edges merged
+        table.set_merge(lhs.MERGE_OFF)
+        oruns = []
+        for i in range(1 + max(1, min(args.steps, 3))):
+            ro = lhs.reach_explore(m, table=table)
+            if i:
+                oruns.append(ro.gpu_ms)
+        table.set_merge(lhs.MERGE_ON)
+        table.set_counters(lhs.COUNT_MERGED)
+        rc = lhs.reach_explore(m, table=table)
+        merged = table.info()["merged"]
+        table.set_counters(0)
+        om = sorted(oruns)[len(oruns) // 2]
+        bfs["merge"] = {"merged_edges": merged, "merged_per_edge": round(merged / rc.edges, 4),
+                        "merge_off_median_ms": round(om, 2), "merge_off_wait_hits": ro.wait_hits,
+                        "speedup_of_merging": round(om / gms, 3),
+                        "same_result": (ro.total, ro.level_counts, ro.edges, ro.deadlocks) ==
+                                       (res.total, res.level_counts, res.edges, res.deadlocks) ==
+                                       (rc.total, rc.level_counts, rc.edges, rc.deadlocks)}
+        log(f"bfs merging off: {om:.1f} ms; merged {merged} of {rc.edges} edges")
         # the paper's speedup S = T_1 / T_N and efficiency E = S / N over N
         # workers (one workgroup of 256 lanes each), on a 2^22-state prefix
         # of the same model
