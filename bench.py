@@ -405,6 +405,25 @@ def main():
                "deadlocks": res.deadlocks, "capped": res.capped, "median_ms": round(gms, 2),
                "states_per_s": round(res.total / (gms / 1e3), 1),
                "edges_per_s": round(res.edges / (gms / 1e3), 1), "wait_hits": res.wait_hits}
+        # algorithmic bytes of the exploration: per edge one 128-byte slot
+        # line and one row (as for find-or-put), per expanded state its row
+        # and frontier index, per new state its frontier entry
+        expanded = res.total - (res.level_counts[-1] if res.capped else 0)
+        per_edge, per_exp = spec_bytes_per_op(m.W), 4 * m.W + 4
+        bfs_bytes = res.edges * per_edge + expanded * per_exp + (res.total - 1) * 4
+        bfs_gbs = bfs_bytes / (gms / 1e3) / 1e9
+        bfs["roofline"] = {"bound": "hbm", "kernel": "k_expand (the whole exploration, its first levels in "
+                                                     "k_batch_persistent)",
+                           "bytes_per_edge": per_edge, "bytes_per_expanded_state": per_exp,
+                           "bytes_per_new_state": 4, "algorithmic_bytes": bfs_bytes,
+                           "achieved": round(bfs_gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                           "frac": round(bfs_gbs / 8000.0, 4)}
+        tpath = os.path.join(ROOT, "profiles", "k_expand_bfs2p27_traffic.json")
+        if os.path.exists(tpath) and args.bfs_cap == 1 << 27:
+            with open(tpath) as f:
+                tr = json.load(f)
+            bfs["roofline"]["traffic_bytes_per_edge"] = round(tr["fetch_bytes_per_edge"] + tr["write_bytes_per_edge"], 1)
+            bfs["roofline"]["traffic_source"] = "k_expand_bfs2p27_traffic.json (rocprofv3 FETCH_SIZE + WRITE_SIZE)"
         golden = os.path.join(ROOT, "tests", "golden", "big_model.json")
         if os.path.exists(golden) and args.bfs_cap == 1 << 27:
             with open(golden) as f:

@@ -189,7 +189,7 @@ def test_lines_probed_counter(lhs, tps):
         # about 1.5 lines per insert when filling to 97.7 %
         assert 1.3 * len(rows) < t.info()["lines_probed"] < 2.0 * len(rows)
         with pytest.raises(lhs.LhsError):
-            t.set_counters(2)
+            t.set_counters(4)                           # bits 1 and 2 are the only counters
 
 
 @pytest.mark.parametrize("tps", [0, 1])
