@@ -1,13 +1,15 @@
 // BFS level expansion of one tile of frontier states, shared by the
-// single-model kernel, the multi-model step kernel and the persistent batch
-// kernel.
+// single-model kernel, the graph-driven level kernel, the multi-model step
+// kernel, the persistent batch kernel, the order-free kernel and the
+// persistent server.
 //
 // One tile = up to 256 frontier states of one model:
 //   frontier slot indices -> state rows staged in LDS -> guarded successor
-//   enumeration by all lanes, compacted into an LDS ring -> hashing (one lane
-//   per successor) -> find-or-put -> wave ballot/prefix compaction of the new
-//   states into the next frontier, plus edge and deadlock counts.  Successors
-//   never go to HBM except as the table's own inserts.
+//   enumeration by all lanes, in passes of 256 successors -> hashing (one
+//   lane per successor) -> equal successors of the pass merged in LDS ->
+//   find-or-put -> wave ballot/prefix compaction of the new states into the
+//   next frontier, plus edge and deadlock counts.  Successors never go to
+//   HBM except as the table's own inserts.
 #pragma once
 
 #include "internal.h"
