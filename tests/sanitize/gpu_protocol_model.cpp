@@ -40,13 +40,25 @@
 // other (sequentially consistent), and an admission checks that no worker
 // of its launch has left.  Slots are reused by later queries.
 //
-// Planted mistakes (compile with -DPLANT=n) remove one ordering each; the
-// test expects TSan (or a result check) to catch every one:
+// Part 5, the merge of equal successors of an expansion pass: lanes write
+// their successors (the pass's list, plain memory), meet at the pass
+// barrier, and each claims a cell of a hash set (atomics) with its hash tag
+// and lane; a lane that meets its own tag stops there and takes that lane's
+// find-or-put as its own once the two vectors compare equal, and the lane
+// holding the cell always probes.  Checked per pass: every distinct vector
+// keeps a lane that probes, every merged lane's lane holds an equal vector
+// and probes, and with distinct hashes each vector probes exactly once.
+// Hashes are full, cut to one tag bit, or forced to collide across vectors.
+//
+// Planted mistakes (compile with -DPLANT=n) remove one ordering or check
+// each; the test expects TSan (or a result check) to catch every one:
 //   1 publish DONE before writing the row      2 publish DONE relaxed
 //   3 compare a matching row without DONE      4 free a ring cell relaxed
 //   5 count a finished tile relaxed            6 raise the admission tail relaxed
 //   7 publish a completion record relaxed      8 fill a completion record after
 //                                                publishing it
+//   9 merge on a tag match without comparing  10 read another lane's successor
+//     the vectors                                 without the pass barrier
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -56,6 +68,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <random>
 #include <set>
 #include <thread>
 #include <vector>
@@ -911,6 +924,118 @@ int part4() {
     return (int)bad;
 }
 
+
+// ---------------------------------------------------------------- part 5 ---
+// A reusable barrier for the lanes of one pass (the workgroup barrier).
+struct PassBarrier {
+    std::atomic<uint32_t> arrived{0}, phase{0};
+    uint32_t n;
+    explicit PassBarrier(uint32_t n_) : n(n_) {}
+    void wait() {
+        const uint32_t ph = phase.load(std::memory_order_acquire);
+        if (arrived.fetch_add(1, std::memory_order_acq_rel) + 1 == n) {
+            arrived.store(0, std::memory_order_relaxed);
+            phase.store(ph + 1, std::memory_order_release);
+        } else {
+            while (phase.load(std::memory_order_acquire) == ph)
+                std::this_thread::yield();
+        }
+    }
+};
+
+int part5() {
+    constexpr uint32_t kLanes = 32, kCells = 2 * kLanes, W = 6;
+    constexpr int kTrials = 60;
+    enum HashMode { kFull, kOneBit, kCollide };
+    std::mt19937_64 rnd(0x5EED5);
+    unsigned bad = 0, merged_total = 0;
+    for (int trial = 0; trial < 3 * kTrials; ++trial) {
+        const HashMode mode = HashMode(trial % 3);
+        // the pass's successors: drawn from a small pool, so that many repeat
+        const uint32_t pool = 2 + (uint32_t)(rnd() % 12);
+        std::vector<std::vector<uint32_t>> pool_rows(pool, std::vector<uint32_t>(W));
+        for (auto &r : pool_rows)
+            for (auto &w : r)
+                w = (uint32_t)(rnd() % 4);
+        std::vector<uint32_t> pick(kLanes);
+        for (auto &x : pick)
+            x = (uint32_t)(rnd() % pool);
+        std::vector<uint32_t> succ((size_t)kLanes * W);   // payload: the pass's list
+        std::unique_ptr<std::atomic<uint32_t>[]> cells(new std::atomic<uint32_t>[kCells]);
+        for (uint32_t i = 0; i < kCells; ++i)
+            cells[i].store(0, std::memory_order_relaxed);
+        std::vector<uint8_t> skip(kLanes, 0);
+        std::vector<uint32_t> rep(kLanes, 0);
+        PassBarrier bar(kLanes);
+        auto lane = [&](uint32_t l) {
+            uint32_t *mine = &succ[(size_t)l * W];
+            for (uint32_t w = 0; w < W; ++w)
+                mine[w] = pool_rows[pick[l]][w];
+#if PLANT != 10
+            bar.wait();   // the list is complete (the pass barrier)
+#endif
+            uint64_t h = hash_row(mine, W);
+            if (mode == kCollide)
+                h = mix64(h & 3);      // four hashes for the whole pool
+            uint32_t tag = (uint32_t)(h >> 41) << 9;
+            if (mode == kOneBit)
+                tag &= 1u << 9;
+            uint32_t c = (uint32_t)(h >> 32) & (kCells - 1), other = 0;
+            for (;;) {
+                uint32_t old = 0;
+                if (cells[c].compare_exchange_strong(old, tag | (l + 1), std::memory_order_relaxed))
+                    break;
+                if ((old & ~511u) == tag) {
+                    other = old & 511u;
+                    break;
+                }
+                c = (c + 1) & (kCells - 1);
+            }
+            if (other) {
+                const uint32_t *o = &succ[(size_t)(other - 1) * W];
+                bool eq = true;
+#if PLANT != 9
+                for (uint32_t w = 0; w < W; ++w)
+                    eq = eq && mine[w] == o[w];
+#endif
+                skip[l] = eq;
+                rep[l] = other - 1;
+            }
+        };
+        std::vector<std::thread> th;
+        for (uint32_t l = 0; l < kLanes; ++l)
+            th.emplace_back(lane, l);
+        for (auto &t : th)
+            t.join();
+        // per distinct vector: the lanes that probe the table
+        std::map<std::vector<uint32_t>, uint32_t> probing;
+        for (uint32_t l = 0; l < kLanes; ++l)
+            probing[pool_rows[pick[l]]] += !skip[l];
+        for (auto &kv : probing)
+            if (kv.second == 0)
+                ++bad;   // a state no lane puts into the table: lost
+        std::set<uint64_t> hashes;
+        for (auto &kv : probing)
+            hashes.insert(hash_row(kv.first.data(), W));
+        const bool distinct = hashes.size() == probing.size();
+        for (uint32_t l = 0; l < kLanes; ++l) {
+            if (!skip[l])
+                continue;
+            ++merged_total;
+            if (skip[rep[l]] || pool_rows[pick[rep[l]]] != pool_rows[pick[l]])
+                ++bad;   // merged into a lane that does not probe, or into another state
+        }
+        if (mode == kFull && distinct)
+            for (auto &kv : probing)
+                if (kv.second != 1)
+                    ++bad;   // a repeat that the full hash should have merged
+    }
+    printf("part5: %d passes, %u successors merged, errors %u\n", 3 * kTrials, merged_total, bad);
+    if (merged_total == 0)
+        ++bad;
+    return (int)bad;
+}
+
 }  // namespace
 
 int main() {
@@ -918,6 +1043,7 @@ int main() {
     const int b = part2();
     const int c = part3();
     const int d = part4();
-    printf("errors %d\n", a + b + c + d);
-    return a + b + c + d ? 1 : 0;
+    const int e = part5();
+    printf("errors %d\n", a + b + c + d + e);
+    return a + b + c + d + e ? 1 : 0;
 }

@@ -39,8 +39,9 @@ def test_gpu_protocol_model_under_thread_sanitizer(tmp_path):
     """Find-or-put's claim / row write / publish / bounded wait, the batch
     ring with last-tile level finalisation, the ring alone, and the
     persistent server (admission into running workers, completion records,
-    draining and relaunch, slot reuse), modelled with threads and the
-    kernels' orderings: no race, and every result equals a sequential BFS
+    draining and relaunch, slot reuse), and the merge of a pass's equal
+    successors, modelled with threads and the kernels' orderings: no race,
+    every result equals a sequential BFS, and no merged pass loses a state
     (gpu_protocol_model.cpp)."""
     r = _protocol_model(tmp_path, 0)
     assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
@@ -58,6 +59,8 @@ def test_gpu_protocol_model_under_thread_sanitizer(tmp_path):
     (6, "admission tail raised without release"),
     (7, "completion record published without release"),
     (8, "completion record filled after it is published"),
+    (9, "successors merged on a tag match without comparing the vectors"),
+    (10, "another lane's successor read without the pass barrier"),
 ])
 def test_gpu_protocol_model_catches_planted_mistakes(tmp_path, plant, what):
     r = _protocol_model(tmp_path, plant)
