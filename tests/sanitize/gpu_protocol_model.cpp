@@ -50,6 +50,20 @@
 // and probes, and with distinct hashes each vector probes exactly once.
 // Hashes are full, cut to one tag bit, or forced to collide across vectors.
 //
+// Part 6, a level's new states appended to eight segments of the next
+// frontier: workgroups buffer new states and flush them with one fetch-and-
+// add on the cursor of their own segment, a flush that does not fit takes
+// the rest from the following segments, and a flush that finds every
+// segment full reports EFULL.  Each workgroup estimates the level's count as
+// eight times its cursor, turns eager (a flush after every pass) within a
+// margin of the cap, and from then on sums the eight cursors after each
+// flush and raises the abort flag past the cap.  Workgroups take tiles in a
+// grid stride and look at the abort flag at every tile.  Checked per level:
+// the segments' first min(cursor, size) entries hold every appended state
+// exactly once, EFULL is reported exactly when the states outnumber the
+// segments' room, and the abort is never raised below the cap.  Workgroup
+// counts that are not multiples of eight fill the segments unevenly.
+//
 // Planted mistakes (compile with -DPLANT=n) remove one ordering or check
 // each; the test expects TSan (or a result check) to catch every one:
 //   1 publish DONE before writing the row      2 publish DONE relaxed
@@ -59,6 +73,8 @@
 //                                                publishing it
 //   9 merge on a tag match without comparing  10 read another lane's successor
 //     the vectors                                 without the pass barrier
+//  11 place a flush past the end of a         12 abort on the workgroup's own
+//     segment                                    estimate, without the cursors
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -1036,6 +1052,177 @@ int part5() {
     return (int)bad;
 }
 
+
+// ---------------------------------------------------------------- part 6 ---
+constexpr uint32_t kSegsM = 8;
+
+struct SegLevel {
+    uint32_t size;                                   // entries per segment
+    std::unique_ptr<std::atomic<uint32_t>[]> cur;    // append cursors
+    std::vector<uint32_t> buf;                       // payload: kSegsM * size entries
+    std::atomic<uint32_t> abort{0}, efull{0};
+    explicit SegLevel(uint32_t s) : size(s), cur(new std::atomic<uint32_t>[kSegsM]), buf((size_t)kSegsM * s, 0) {
+        for (uint32_t k = 0; k < kSegsM; ++k)
+            cur[k].store(0, std::memory_order_relaxed);
+    }
+};
+
+// One workgroup's state across its tiles (the kernel's LDS scalars).
+struct SegWorker {
+    uint32_t b;                       // workgroup index
+    uint32_t est = 0;                 // 8 x the largest cursor seen
+    bool eager = false, aborted = false;
+    std::vector<uint32_t> nbuf;       // buffered new states
+};
+
+void seg_flush(SegLevel &lv, SegWorker &w, uint32_t limit, uint32_t room) {
+    const uint32_t nn = (uint32_t)w.nbuf.size();
+    if (nn) {
+        struct Piece { uint32_t pos, off, n; };
+        Piece pc[2 * kSegsM];
+        uint32_t k = w.b & (kSegsM - 1), rem = nn, np = 0, off = 0, first = 0;
+        for (uint32_t tries = 0; rem && tries < 2 * kSegsM; ++tries) {
+            const uint32_t b = lv.cur[k].fetch_add(rem, std::memory_order_relaxed);
+            if (tries == 0)
+                first = b;
+#if PLANT == 11
+            if (b < lv.size) {
+                const uint32_t n = rem;
+#else
+            if (b < lv.size) {
+                const uint32_t n = std::min(rem, lv.size - b);
+#endif
+                pc[np++] = Piece{k * lv.size + b, off, n};
+                off += n;
+                rem -= n;
+            }
+            k = (k + 1) & (kSegsM - 1);
+        }
+        if (rem)
+            lv.efull.store(1, std::memory_order_relaxed);
+        w.est = std::max<uint32_t>(w.est, (uint32_t)std::min<uint64_t>(8ull * ((uint64_t)first + nn), 0xFFFFFFFFull));
+        if (limit != 0xFFFFFFFFu && ((uint64_t)w.est + room > limit || w.eager)) {
+            w.eager = true;
+            uint64_t total = 0;
+#if PLANT == 12
+            total = w.est;
+#else
+            for (uint32_t q = 0; q < kSegsM; ++q)
+                total += std::min(lv.cur[q].load(std::memory_order_relaxed), lv.size);
+#endif
+            if (total > limit) {
+                lv.abort.store(1, std::memory_order_relaxed);
+                w.aborted = true;
+            }
+        }
+        for (uint32_t p = 0; p < np; ++p)
+            for (uint32_t i = 0; i < pc[p].n && pc[p].pos + i < lv.buf.size(); ++i)
+                lv.buf[pc[p].pos + i] = w.nbuf[pc[p].off + i];
+        w.nbuf.clear();
+    }
+    if (w.eager && !w.aborted)
+        w.aborted = lv.abort.load(std::memory_order_relaxed) != 0;
+}
+
+int part6() {
+    constexpr uint32_t kPass = 32, kBuf = 3 * kPass, kTileMax = 4 * kPass;
+    std::mt19937_64 rnd(0x5E6);
+    unsigned bad = 0, aborted_levels = 0, efull_levels = 0, uneven = 0;
+    const uint32_t worker_counts[] = {1, 3, 8, 9, 13, 16};
+    for (int trial = 0; trial < 48; ++trial) {
+        const uint32_t nw = worker_counts[trial % 6];
+        const uint32_t size = 64 + (uint32_t)(rnd() % 512);
+        const uint32_t tiles = 8 + (uint32_t)(rnd() % 96);
+        // new states per tile, each a distinct id: tile * kTileMax + i
+        std::vector<uint32_t> out(tiles);
+        uint64_t produced = 0;
+        for (auto &o : out) {
+            o = (uint32_t)(rnd() % (kTileMax + 1));
+            produced += o;
+        }
+        const int kind = (trial / 6) % 4;   // no cap, cap inside, cap above, segments too small
+        uint32_t limit = 0xFFFFFFFFu;
+        if (kind == 1)
+            limit = (uint32_t)(produced / 2);
+        else if (kind == 2)
+            limit = (uint32_t)(produced + 1);
+        const uint32_t seg = kind == 3 ? std::max<uint32_t>(1u, (uint32_t)(produced / (kSegsM + 2))) : size;
+        SegLevel lv(kind == 3 ? seg : std::max<uint32_t>(size, (uint32_t)(produced / kSegsM) + kTileMax));
+        const uint32_t room = nw * kBuf + kPass;
+        std::vector<uint64_t> pushed(nw, 0);
+        auto worker = [&](uint32_t b) {
+            SegWorker w;
+            w.b = b;
+            for (uint32_t t = b; t < tiles; t += nw) {
+                if (lv.abort.load(std::memory_order_relaxed))
+                    break;   // the tile's start
+                for (uint32_t p0 = 0; p0 < out[t] && !w.aborted; p0 += kPass) {
+                    for (uint32_t i = p0; i < std::min(out[t], p0 + kPass); ++i)
+                        w.nbuf.push_back(t * kTileMax + i);
+                    if (w.eager || w.nbuf.size() > kBuf - kPass) {
+                        pushed[b] += w.nbuf.size();
+                        seg_flush(lv, w, limit, room);
+                    }
+                }
+                if (w.aborted)
+                    break;
+            }
+            pushed[b] += w.nbuf.size();
+            seg_flush(lv, w, limit, room);   // the end of the launch
+        };
+        std::vector<std::thread> th;
+        for (uint32_t b = 0; b < nw; ++b)
+            th.emplace_back(worker, b);
+        for (auto &t : th)
+            t.join();
+        uint64_t total = 0, n_push = 0;
+        std::vector<uint32_t> seen_id((size_t)tiles * kTileMax, 0);
+        uint32_t lo = 0xFFFFFFFFu, hi = 0;
+        for (uint32_t k = 0; k < kSegsM; ++k) {
+            const uint32_t n = std::min(lv.cur[k].load(), lv.size);
+            lo = std::min(lo, n);
+            hi = std::max(hi, n);
+            total += n;
+            for (uint32_t i = 0; i < n; ++i) {
+                const uint32_t id = lv.buf[(size_t)k * lv.size + i];
+                if (id >= seen_id.size() || id % kTileMax >= out[id / kTileMax] || seen_id[id]++) {
+                    ++bad;   // not a state of this level, or one listed twice
+                    break;
+                }
+            }
+        }
+        for (auto x : pushed)
+            n_push += x;
+        const bool efull = lv.efull.load() != 0;
+        uneven += hi > lo + kBuf;
+        if (efull != (n_push > (uint64_t)kSegsM * lv.size)) {
+            printf("part6: trial %d: EFULL %d with %llu states for %u entries\n", trial, (int)efull,
+                   (unsigned long long)n_push, kSegsM * lv.size);
+            ++bad;
+        }
+        if (!efull && total != n_push) {
+            printf("part6: trial %d: %llu entries listed, %llu appended\n", trial, (unsigned long long)total,
+                   (unsigned long long)n_push);
+            ++bad;   // an appended state missing from the segments
+        }
+        if (!lv.abort.load() && !efull && n_push != produced)
+            ++bad;   // a level that was not aborted lost states
+        if (lv.abort.load()) {
+            ++aborted_levels;
+            if (total <= limit) {
+                printf("part6: trial %d: abort with %llu states, cap %u\n", trial, (unsigned long long)total, limit);
+                ++bad;   // aborted below the cap
+            }
+        }
+        efull_levels += efull;
+    }
+    printf("part6: 48 levels, %u aborted, %u with EFULL, %u filled unevenly, errors %u\n", aborted_levels,
+           efull_levels, uneven, bad);
+    if (aborted_levels == 0 || efull_levels == 0 || uneven == 0)
+        ++bad;   // a case the trials were meant to reach
+    return (int)bad;
+}
+
 }  // namespace
 
 int main() {
@@ -1044,6 +1231,7 @@ int main() {
     const int c = part3();
     const int d = part4();
     const int e = part5();
-    printf("errors %d\n", a + b + c + d + e);
-    return a + b + c + d + e ? 1 : 0;
+    const int f = part6();
+    printf("errors %d\n", a + b + c + d + e + f);
+    return a + b + c + d + e + f ? 1 : 0;
 }

@@ -39,10 +39,11 @@ def test_gpu_protocol_model_under_thread_sanitizer(tmp_path):
     """Find-or-put's claim / row write / publish / bounded wait, the batch
     ring with last-tile level finalisation, the ring alone, and the
     persistent server (admission into running workers, completion records,
-    draining and relaunch, slot reuse), and the merge of a pass's equal
-    successors, modelled with threads and the kernels' orderings: no race,
-    every result equals a sequential BFS, and no merged pass loses a state
-    (gpu_protocol_model.cpp)."""
+    draining and relaunch, slot reuse), the merge of a pass's equal
+    successors, and segmented appends to the next frontier with the cap's
+    abort, modelled with threads and the kernels' orderings: no race, every
+    result equals a sequential BFS, no merged pass loses a state, and every
+    appended state is listed once (gpu_protocol_model.cpp)."""
     r = _protocol_model(tmp_path, 0)
     assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
     assert r.returncode == 0 and "errors 0" in r.stdout, r.stdout + r.stderr[-2000:]
@@ -61,6 +62,8 @@ def test_gpu_protocol_model_under_thread_sanitizer(tmp_path):
     (8, "completion record filled after it is published"),
     (9, "successors merged on a tag match without comparing the vectors"),
     (10, "another lane's successor read without the pass barrier"),
+    (11, "a flush placed past the end of its segment"),
+    (12, "abort raised on the workgroup's own estimate, without the cursors"),
 ])
 def test_gpu_protocol_model_catches_planted_mistakes(tmp_path, plant, what):
     r = _protocol_model(tmp_path, plant)
