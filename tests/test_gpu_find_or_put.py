@@ -263,3 +263,32 @@ def test_host_buffers_refused(lhs):
         t.find_or_put(rows.cuda(), seen)
         t.check()
         assert sorted(seen.cpu().tolist()) == [0] + [1] * 7   # one of the equal rows inserts
+
+
+@pytest.mark.parametrize("W,tps", [(1, 0), (4, 0), (4, 4)])
+def test_max_capacity_2p32(lhs, W, tps):
+    """The largest table the API allows, 2^32 slots (32 GiB of slots, 16 or
+    64 GiB of rows): slot indices and line numbers use all 32 bits, and row
+    offsets (slot x W) pass 2^32 words at W = 4.  2^21 operations (2^20 rows
+    drawn twice, shuffled) in two calls, against the oracle; the stored set
+    by sorted rows; each dumped row's slot is the index its find-or-put
+    returned."""
+    import torch
+    torch.cuda.empty_cache()   # room for the table beside torch's cached blocks
+    cfg = None if tps == 0 else lhs.config(16, "double", tps, tps)
+    print(f"\n[fop] capacity 2^32 W={W} tps={tps}", flush=True)
+    rows, order = gen.dup_stream(0x32 + W, 1 << 20, W, 2)
+    stream = gen.gather(rows, order)
+    o_seen, o_id, distinct = oracle.stream(stream)
+    with lhs.Table(1 << 32, W, cfg) as t:
+        seen, idx, bounds = _run_stream(lhs, t, stream, 1 << 20)
+        check_stream_batches(o_id, distinct, seen, idx, bounds)
+        assert t.count() == distinct
+        got, slots = t.dump()
+    # indices reach the upper half of the 32-bit range
+    assert int(idx.max()) >= 1 << 31
+    assert np.array_equal(np.unique(got, axis=0), np.unique(stream, axis=0))
+    # the row stored in each slot is the row whose operations returned it
+    pos = np.searchsorted(slots, idx)
+    assert np.array_equal(slots[pos], idx)
+    assert np.array_equal(got[pos], stream)
