@@ -28,10 +28,12 @@
 // every workgroup is busy they go out in bulk.
 //
 // Termination: after every tile a workgroup adds (states it discovered,
-// appended or buffered - states it expanded) to ctl->work in one atomic, so
-// work only reaches 0 when no state is open anywhere (queued, buffered or
-// in a tile in flight); then no state can be discovered again and every
-// workgroup leaves.  The order of expansion varies from run to run, so
+// appended or buffered - states it expanded) to ctl->work in one atomic, and
+// an append in the middle of a tile first adds the states of that tile it
+// makes visible (another workgroup may expand them, and subtract them,
+// before the tile ends).  So work only reaches 0 when no state is open
+// anywhere (queued, buffered or in a tile in flight); then no state can be
+// discovered again and every workgroup leaves.  The order of expansion varies from run to run, so
 // per-level counts are not defined; the reachable set, edges and deadlocks
 // are (they do not depend on the order).
 #include <algorithm>
@@ -80,10 +82,14 @@ __global__ __launch_bounds__(kExpandBlock) void k_explore_async(TableView t, Mod
     const uint32_t tid = threadIdx.x;
     uint32_t *nbuf = expand_nbuf<G>(smem, m.W, tcap);
     // thread 0: the owned chunk is queue[base, base + kChunk), its first
-    // `used` entries already taken; `found` = new states this workgroup has
-    // discovered (appended or still buffered) as of its last work update
+    // `used` entries already taken.  s_found = new states this workgroup has
+    // discovered (appended or still buffered) that ctl->work holds
     uint64_t base = 0;
-    uint32_t used = kChunk, polls = 0, last_tail = 0, found = 0;
+    uint32_t used = kChunk, polls = 0, last_tail = 0;
+    if (tid == 0) {
+        s_open = &ctl->work;
+        s_found = 0;
+    }
     while (true) {
         if (tid == 0) {
             uint32_t take = 0, act = kStop;
@@ -137,7 +143,8 @@ __global__ __launch_bounds__(kExpandBlock) void k_explore_async(TableView t, Mod
         if (act == kStop)
             break;
         if (act == kPublish) {
-            flush_new_slots<true>(nbuf, queue, lc, limit);
+            // states held since the last tile: already counted
+            flush_new_slots<true, true>(nbuf, queue, lc, limit);
             continue;
         }
         // new states stay buffered across tiles while this chunk has work
@@ -146,8 +153,8 @@ __global__ __launch_bounds__(kExpandBlock) void k_explore_async(TableView t, Mod
         if (tid == 0) {
             // discovered - expanded, after the discoveries are counted
             const uint32_t now = s_pushed + s_nnew;
-            atomicAdd(&ctl->work, (unsigned long long)(now - found) - (unsigned long long)n);
-            found = now;
+            atomicAdd(&ctl->work, (unsigned long long)(now - s_found) - (unsigned long long)n);
+            s_found = now;
         }
         if (aborted)
             break;

@@ -108,6 +108,10 @@ static __shared__ uint32_t s_nnew, s_nbase, s_abort, s_eager;
 static __shared__ uint32_t s_pushed;
 // Set when a wait for a frontier entry ran out (AWAIT): the launch stops.
 static __shared__ uint32_t s_stall;
+// Exploration without level barriers: its count of open states, and how
+// many of this workgroup's new states (s_pushed + s_nnew) it already holds.
+static __shared__ unsigned long long *s_open;
+static __shared__ uint32_t s_found;
 // Segmented appends (SEG): this workgroup's estimate of the level's new
 // states so far, and the pieces of the segments its current flush fills.
 static __shared__ uint32_t s_seg_est, s_seg_np;
@@ -139,7 +143,12 @@ __device__ __forceinline__ uint32_t *expand_nbuf(uint32_t *smem, uint32_t W, uin
 // cursor (block-wide, uniform call).  Flags the level aborted when the cursor
 // passes `limit`; within kEagerRoom of it the workgroup turns eager (flushes
 // every pass and rereads the abort flag).
-template <bool COHERENT>
+// COUNT_OPEN (exploration without level barriers): new states that *s_open
+// does not hold yet, those found in the current tile, are added to it before
+// their entries are written.  A workgroup that expands one of them subtracts
+// it only after it has read the entry, so the count never reaches zero while
+// a tile that appended states is still running.
+template <bool COHERENT, bool COUNT_OPEN = false>
 __device__ __forceinline__ void flush_new_slots(const uint32_t *nbuf, uint32_t *next, LevelCounters *lc,
                                                 uint32_t limit) {
     __syncthreads();
@@ -147,6 +156,14 @@ __device__ __forceinline__ void flush_new_slots(const uint32_t *nbuf, uint32_t *
     const uint32_t nn = s_nnew;
     if (tid == 0) {
         if (nn) {
+            if constexpr (COUNT_OPEN) {
+                const uint32_t held = s_pushed + nn;
+                if (held > s_found) {
+                    atomicAdd(s_open, (unsigned long long)(held - s_found));
+                    s_found = held;
+                    wait_vm_complete();   // counted before any entry is written
+                }
+            }
             const uint32_t b = atomicAdd(&lc->n_next, nn);
             s_nbase = b;
             s_pushed += nn;
@@ -334,7 +351,8 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
 // only the counts in LDS.
 // AWAIT (with COHERENT): a frontier entry may still be in flight; 0xFFFFFFFF
 // marks one not yet written, which the staging lane waits for (bounded:
-// LHS_ESTALL and an aborted tile).
+// LHS_ESTALL and an aborted tile).  Appends in the middle of the tile count
+// their states as open first (flush_new_slots, COUNT_OPEN).
 // CL: slot lines are read with coherent loads (tables reused within one
 // launch, the persistent server).
 template <int G, uint32_t LS, bool COHERENT = false, bool DEFER = false, bool DEFER_COUNTS = DEFER,
@@ -479,7 +497,7 @@ __device__ __forceinline__ bool expand_tile(uint32_t *smem, const TableView &t, 
         if constexpr (SEG)
             flush_new_slots_seg<COHERENT>(nbuf, so, lc, limit);
         else
-            flush_new_slots<COHERENT>(nbuf, next, lc, limit);
+            flush_new_slots<COHERENT, AWAIT>(nbuf, next, lc, limit);
     };
     // ---- find-or-put of successors d0/d1/hq[0, take); new slots to nbuf ----
     // skip (G == 1): this lane's successor is another lane's in the same pass

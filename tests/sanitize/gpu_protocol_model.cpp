@@ -64,6 +64,20 @@
 // segments' room, and the abort is never raised below the cap.  Workgroup
 // counts that are not multiples of eight fill the segments unevenly.
 //
+// Part 7, exploration without level barriers: workers take 16-entry chunks
+// of one queue of slots in discovery order with a fetch-and-add, wait for
+// the chunk's entries to be written (unwritten entries hold 0xFFFFFFFF),
+// expand them, buffer new states and append them in bulk (mid-tile when
+// the buffer nears full, and when their own chunk runs dry or another
+// worker waits), and after every tile add (states discovered, appended or
+// buffered) - (states expanded) to a shared work count; states appended in
+// the middle of a tile are added to it before their entries are written.  A
+// worker leaves once its chunk is dry, it holds nothing back and the work
+// count is zero.
+// Checked per run: the queue lists the reachable set of a sequential BFS
+// exactly once, every entry is expanded exactly once, the edges are all
+// counted and the work count ends at zero.
+//
 // Planted mistakes (compile with -DPLANT=n) remove one ordering or check
 // each; the test expects TSan (or a result check) to catch every one:
 //   1 publish DONE before writing the row      2 publish DONE relaxed
@@ -75,11 +89,16 @@
 //     the vectors                                 without the pass barrier
 //  11 place a flush past the end of a         12 abort on the workgroup's own
 //     segment                                    estimate, without the cursors
+//  13 write a queue entry relaxed             14 count held-back states as open
+//                                                only once they are appended
+//  15 count states appended in the middle of a tile only when the tile ends
+//     (caught by the unsanitized repeated run of part 7: `model part7 N`)
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -1223,15 +1242,289 @@ int part6() {
     return (int)bad;
 }
 
+
+// ---------------------------------------------------------------- part 7 ---
+constexpr uint32_t kNoEntryM = 0xFFFFFFFFu;
+// polls without progress before a worker gives up (the kernel's bound is
+// about a second; a lost entry must end a run here within seconds)
+constexpr uint32_t kAsyncSpin = 1u << 20;
+
+// The explored model: N cyclic L-state processes (W = N), or a broom (W = 2):
+// a chain (a, 0) -> (a + 1, 0) for a < L whose last state (L, 0) has F
+// successors (L, 1..F), each a deadlock.
+struct AsyncModel {
+    bool broom;
+    uint32_t N, L, F;
+    uint32_t W() const { return broom ? 2u : N; }
+    void successors(const uint32_t *s, std::vector<std::vector<uint32_t>> &out) const {
+        out.clear();
+        if (!broom) {
+            for (uint32_t p = 0; p < N; ++p) {
+                std::vector<uint32_t> v(s, s + N);
+                v[p] = (v[p] + 1) % L;
+                out.push_back(v);
+            }
+        } else if (s[1] == 0 && s[0] < L) {
+            out.push_back({s[0] + 1, 0});
+        } else if (s[1] == 0) {
+            for (uint32_t k = 1; k <= F; ++k)
+                out.push_back({L, k});
+        }
+    }
+};
+
+struct AsyncRun {
+    AsyncModel m;
+    uint32_t nw;
+    uint32_t chunk_size, buf_size, pass;   // entries per chunk, new-state buffer, successors per pass
+    Table t;
+    std::unique_ptr<std::atomic<uint32_t>[]> queue;      // slots; kNoEntryM = unwritten
+    std::unique_ptr<std::atomic<uint8_t>[]> expanded;     // per entry, for the check
+    std::atomic<uint32_t> n_next{1}, chunk{0}, error{0};
+    std::atomic<uint64_t> work{1}, edges{0};
+    // the smallest cursor a leaving worker saw after deciding to leave: below
+    // the final cursor, a worker left while states were still to be found
+    std::atomic<uint32_t> left_at_min{0xFFFFFFFFu};
+    AsyncRun(const AsyncModel &m_, uint32_t nw_, uint32_t chunk_, uint32_t buf_, uint32_t pass_, uint32_t cap)
+        : m(m_), nw(nw_), chunk_size(chunk_), buf_size(buf_), pass(pass_), t(m_.W(), 8, cap),
+          queue(new std::atomic<uint32_t>[cap]), expanded(new std::atomic<uint8_t>[cap]) {
+        for (uint32_t i = 0; i < cap; ++i) {
+            queue[i].store(kNoEntryM, std::memory_order_relaxed);
+            expanded[i].store(0, std::memory_order_relaxed);
+        }
+    }
+};
+
+void async_worker(AsyncRun &r) {
+    const uint32_t W = r.m.W(), kChunkM = r.chunk_size, kBufM = r.buf_size;
+    uint64_t base = 0;
+    uint32_t used = kChunkM, pushed = 0, found = 0, polls = 0, last_tail = 0;
+    std::vector<uint32_t> nbuf;
+    auto flush = [&]() {
+#if PLANT != 15
+        // states that become visible here and are not in the work count yet
+        // (found in the current tile) are counted first: a worker that
+        // expands one subtracts it only after reading its entry
+        const uint32_t held = pushed + (uint32_t)nbuf.size();
+        if (held > found) {
+            r.work.fetch_add(held - found, std::memory_order_relaxed);
+            found = held;
+        }
+#endif
+        const uint32_t at = r.n_next.fetch_add((uint32_t)nbuf.size(), std::memory_order_relaxed);
+        for (uint32_t i = 0; i < nbuf.size(); ++i)
+#if PLANT == 13
+            r.queue[at + i].store(nbuf[i], std::memory_order_relaxed);
+#else
+            // the rows of these slots were written, and completed (vmcnt(0)),
+            // by this worker's own inserts before the entries are stored
+            r.queue[at + i].store(nbuf[i], std::memory_order_release);
+#endif
+        pushed += (uint32_t)nbuf.size();
+        nbuf.clear();
+    };
+    std::vector<uint32_t> row(W);
+    std::vector<std::vector<uint32_t>> succ;
+    while (true) {
+        enum { kStop, kExpand, kPublish } act = kStop;
+        uint32_t take = 0;
+        while (true) {
+            if (used == kChunkM) {
+                base = (uint64_t)r.chunk.fetch_add(1, std::memory_order_relaxed) * kChunkM;
+                used = 0;
+            }
+            const uint32_t tl = r.n_next.load(std::memory_order_relaxed);
+            const uint64_t end = std::min<uint64_t>(tl, base + kChunkM);
+            if (!nbuf.empty() && (uint64_t)tl < base + (uint64_t)(r.nw / 4 + 1) * kChunkM &&
+                (uint64_t)tl < (uint64_t)r.chunk.load(std::memory_order_relaxed) * kChunkM) {
+                act = kPublish;   // another worker owns a chunk nothing was appended to
+                break;
+            }
+            if (end > base + used) {
+                take = (uint32_t)(end - base - used);
+                act = kExpand;
+                break;
+            }
+            if (!nbuf.empty()) {
+                act = kPublish;   // this chunk is dry: hold nothing back
+                break;
+            }
+            if (r.work.load(std::memory_order_relaxed) == 0 || r.error.load(std::memory_order_relaxed))
+                break;
+            if (tl != last_tail) {
+                last_tail = tl;
+                polls = 0;
+            } else if (++polls > kAsyncSpin) {
+                r.error.store(4, std::memory_order_relaxed);
+                break;
+            }
+            std::this_thread::yield();
+        }
+        const uint64_t from = base + used;
+        used += take;
+        if (act == kStop) {
+            const uint32_t n = r.n_next.load(std::memory_order_relaxed);
+            uint32_t m = r.left_at_min.load(std::memory_order_relaxed);
+            while (n < m && !r.left_at_min.compare_exchange_weak(m, n, std::memory_order_relaxed)) {
+            }
+            break;
+        }
+        if (act == kPublish) {
+            flush();
+            continue;
+        }
+        uint64_t edges = 0;
+        for (uint64_t e = from; e < from + take; ++e) {
+            // the entry is below the cursor but may still be in flight
+            uint32_t slot, spins = 0;
+            while ((slot = r.queue[e].load(std::memory_order_acquire)) == kNoEntryM) {
+                if (++spins > kAsyncSpin) {
+                    r.error.store(4, std::memory_order_relaxed);
+                    return;
+                }
+                std::this_thread::yield();
+            }
+            r.expanded[e].fetch_add(1, std::memory_order_relaxed);
+            std::memcpy(row.data(), &r.t.data[(size_t)slot * W], W * 4u);   // the row (payload)
+            r.m.successors(row.data(), succ);
+            for (auto &v : succ) {
+                uint32_t at = 0;
+                const Code c = find_or_put(r.t, v.data(), at);
+                if (c == kNew)
+                    nbuf.push_back(at);
+                else if (c != kSeen)
+                    r.error.store(1, std::memory_order_relaxed);
+                // after every pass of successors: append when the buffer
+                // nears full (in the middle of the tile)
+                if (++edges % r.pass == 0 && nbuf.size() + r.pass > kBufM)
+                    flush();
+            }
+        }
+        r.edges.fetch_add(edges, std::memory_order_relaxed);
+        // open states: discovered (appended or held back) - expanded
+#if PLANT == 14
+        const uint32_t now = pushed;
+#else
+        const uint32_t now = pushed + (uint32_t)nbuf.size();
+#endif
+        r.work.fetch_add((uint64_t)(now - found) - (uint64_t)take, std::memory_order_relaxed);
+        found = now;
+    }
+}
+
+// Sequential BFS of the model: the reachable set and the edge count.
+void async_reference(const AsyncModel &m, std::set<std::vector<uint32_t>> &seen, uint64_t &edges) {
+    std::vector<std::vector<uint32_t>> stack{std::vector<uint32_t>(m.W(), 0)};
+    std::vector<std::vector<uint32_t>> succ;
+    seen = {stack[0]};
+    edges = 0;
+    while (!stack.empty()) {
+        const auto s = stack.back();
+        stack.pop_back();
+        m.successors(s.data(), succ);
+        edges += succ.size();
+        for (auto &v : succ)
+            if (seen.insert(v).second)
+                stack.push_back(v);
+    }
+}
+
+// One exploration; returns 1 on a wrong result, and sets `early` when a
+// worker left while states were still to be found.
+int async_run(const AsyncModel &m, uint32_t nw, uint32_t chunk, uint32_t buf, uint32_t pass, bool &early) {
+    std::set<std::vector<uint32_t>> want;
+    uint64_t want_edges = 0;
+    async_reference(m, want, want_edges);
+    uint32_t cap = 64;
+    while (cap < 4 * want.size())
+        cap <<= 1;
+    AsyncRun r(m, nw, chunk, buf, pass, cap);
+    const uint32_t W = m.W();
+    // s0 is entry 0, inserted before the launch
+    std::vector<uint32_t> s0(W, 0);
+    uint32_t slot0 = 0;
+    if (find_or_put(r.t, s0.data(), slot0) != kNew)
+        return 1;
+    r.queue[0].store(slot0, std::memory_order_relaxed);
+    std::vector<std::thread> th;
+    for (uint32_t b = 0; b < nw; ++b)
+        th.emplace_back(async_worker, std::ref(r));
+    for (auto &t : th)
+        t.join();
+    const uint32_t n = r.n_next.load();
+    std::set<std::vector<uint32_t>> got;
+    unsigned once = 1;
+    for (uint32_t e = 0; e < n; ++e) {
+        const uint32_t s = r.queue[e].load();
+        if (s == kNoEntryM)
+            continue;
+        got.insert(std::vector<uint32_t>(&r.t.data[(size_t)s * W], &r.t.data[(size_t)s * W] + W));
+        once &= r.expanded[e].load() == 1;
+    }
+    early = r.left_at_min.load() < n;
+    const bool ok = r.error.load() == 0 && n == want.size() && got == want && once && r.edges.load() == want_edges &&
+                    r.work.load() == 0;
+    if (!ok)
+        printf("part7: %s N=%u L=%u F=%u workers=%u chunk=%u: %u entries, %zu distinct listed, %zu reachable, "
+               "all expanded once %u, edges %llu of %llu, work %llu, error %u WRONG\n",
+               m.broom ? "broom" : "cyclic", m.N, m.L, m.F, nw, chunk, n, got.size(), want.size(), once,
+               (unsigned long long)r.edges.load(), (unsigned long long)want_edges, (unsigned long long)r.work.load(),
+               r.error.load());
+    return ok ? 0 : 1;
+}
+
+int part7() {
+    const AsyncModel models[] = {{false, 1, 700, 0}, {false, 2, 30, 0}, {false, 3, 9, 0}, {false, 4, 6, 0},
+                                 {false, 5, 4, 0},   {false, 6, 3, 0},  {true, 0, 40, 60}, {true, 0, 3, 200}};
+    const uint32_t workers[] = {1, 3, 6};
+    unsigned bad = 0, runs = 0, early = 0;
+    // the kernel's proportions (16-entry chunks, a buffer of three chunks,
+    // passes of a chunk), then 1-entry chunks with an append after every
+    // pass of 2 successors: appends in the middle of tiles whose entries
+    // other workers expand at once
+    const uint32_t shapes[][3] = {{16, 48, 16}, {1, 2, 2}};
+    for (const auto &sh : shapes)
+        for (const AsyncModel &m : models)
+            for (uint32_t nw : workers) {
+                bool e = false;
+                bad += async_run(m, nw, sh[0], sh[1], sh[2], e);
+                early += e;
+                ++runs;
+            }
+    // the broom's fan again, many times: a worker that expands a state
+    // appended in the middle of another's tile must never drive the work
+    // count to zero while that tile is still open
+    for (int rep = 0; rep < 40; ++rep)
+        for (uint32_t nw : {3u, 6u}) {
+            bool e = false;
+            bad += async_run(models[7], nw, 1, 2, 2, e);
+            early += e;
+            ++runs;
+        }
+    printf("part7: %u explorations without levels, %u with a worker that left early, errors %u\n", runs, early,
+           bad);
+    return (int)(bad + early);
+}
+
 }  // namespace
 
-int main() {
+int main(int argc, char **argv) {
+    if (argc == 3 && std::strcmp(argv[1], "part7") == 0) {
+        // part 7 alone, repeated (built without a sanitizer, its threads
+        // interleave far more finely)
+        int bad = 0;
+        for (int i = 0, n = std::atoi(argv[2]); i < n; ++i)
+            bad += part7();
+        printf("errors %d\n", bad);
+        return bad ? 1 : 0;
+    }
     const int a = part1();
     const int b = part2();
     const int c = part3();
     const int d = part4();
     const int e = part5();
     const int f = part6();
-    printf("errors %d\n", a + b + c + d + e + f);
-    return a + b + c + d + e + f ? 1 : 0;
+    const int g = part7();
+    printf("errors %d\n", a + b + c + d + e + f + g);
+    return a + b + c + d + e + f + g ? 1 : 0;
 }

@@ -1,8 +1,9 @@
 """Host code under sanitizers (no GPU): the multi-core lockless CPU table
 under ThreadSanitizer, a CPU-thread model of the GPU kernels' protocols under
-ThreadSanitizer (with planted ordering mistakes it must catch), and the
-tuning-file reader under AddressSanitizer and UndefinedBehaviorSanitizer with
-mutated inputs."""
+ThreadSanitizer (with planted ordering mistakes it must catch) and, for the
+exploration without level barriers, also built without a sanitizer and run
+many times, and the tuning-file reader under AddressSanitizer and
+UndefinedBehaviorSanitizer with mutated inputs."""
 import os
 import shutil
 import subprocess
@@ -64,10 +65,39 @@ def test_gpu_protocol_model_under_thread_sanitizer(tmp_path):
     (10, "another lane's successor read without the pass barrier"),
     (11, "a flush placed past the end of its segment"),
     (12, "abort raised on the workgroup's own estimate, without the cursors"),
+    (13, "a queue entry written without release"),
+    (14, "held-back states counted as open only once appended"),
 ])
 def test_gpu_protocol_model_catches_planted_mistakes(tmp_path, plant, what):
     r = _protocol_model(tmp_path, plant)
     assert "ThreadSanitizer: data race" in r.stderr or r.returncode != 0, f"not caught: {what}"
+
+
+def _exploration_stress(tmp_path, plant):
+    exe = str(tmp_path / f"gpu_protocol_model_o2_{plant}")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-pthread", f"-DPLANT={plant}",
+                           os.path.join(HERE, "gpu_protocol_model.cpp"), "-o", exe])
+    return subprocess.run([exe, "part7", "20"], capture_output=True, text=True, timeout=600)
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_exploration_without_levels_stress(tmp_path):
+    """The exploration without level barriers, 20 x 128 runs without a
+    sanitizer (threads interleave finely): every run lists the reachable set
+    once, expands every entry once and ends with no open state, and no
+    worker leaves while states are still to be found."""
+    r = _exploration_stress(tmp_path, 0)
+    assert r.returncode == 0 and r.stdout.strip().endswith("errors 0"), r.stdout[-3000:]
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_exploration_stress_catches_late_count(tmp_path):
+    """Planted: states appended in the middle of a tile enter the work count
+    only when the tile ends.  A workgroup that expands them first can take
+    the count to zero while the tile is open; idle workgroups then leave with
+    chunks that later states land in, and those states are never expanded."""
+    r = _exploration_stress(tmp_path, 15)
+    assert r.returncode != 0 and "WRONG" in r.stdout
 
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
