@@ -90,6 +90,27 @@ __device__ __forceinline__ bool queue_failed(QueueState *qs) {
     return ld_coherent(&qs->error) != 0u;
 }
 
+// Append one item (one thread): reserve a position on the tail, wait for
+// its cell to be free (bounded, as the finaliser's enqueue), fill it, and
+// publish it once the fill and everything the caller wrote before have
+// completed.
+__device__ inline void enqueue_item(QueueState *qs, QCell *ring, uint32_t model, uint32_t tile) {
+    const unsigned long long pos = atomicAdd(&qs->tail, 1ull);
+    QCell *c = ring + (pos & qs->mask);
+    uint32_t spins = 0;
+    while (ld_coherent(&c->seq) != pos) {
+        if (++spins > kBarrierSpinLimit || queue_failed(qs)) {
+            atomicCAS(&qs->error, 0u, (uint32_t)LHS_ESTALL);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    st_coherent(&c->model, model);
+    st_coherent(&c->tile, tile);
+    wait_vm_complete();
+    st_coherent(&c->seq, pos + 1ull);
+}
+
 // Tile size of a level.  Once at most kFewModels models remain and at least
 // half the workgroups wait on the queue with nothing to take, a level of at
 // most kSmallLevel states is cut into tiles of down to kMinTileRows states,

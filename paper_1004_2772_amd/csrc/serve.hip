@@ -181,7 +181,8 @@ __global__ __launch_bounds__(kExpandBlock) void k_step(BatchSlot *slots, uint32_
 //    its s0 in roots[slot], its table emptied) with copies and a clearing
 //    kernel on its upload stream, then appends the slot to box->admit_slot
 //    and raises box->admit_tail, also by copies, in that order.  An idle
-//    workgroup takes the admission, inserts s0 and expands level 0 itself.
+//    workgroup takes the admission, inserts s0 and queues level 0's tile
+//    (it holds a queue position, so it keeps no tile for itself).
 //  * Completion.  The workgroup that finishes a query posts (slot, error) to
 //    a ring of records in pinned host memory (system scope, the sequence
 //    word last, after the query's progress and level counts are complete).
@@ -425,8 +426,14 @@ __global__ __launch_bounds__(kExpandBlock) void k_serve(const ModelState *ms, Mo
             if (tid == 0)
                 s_M_slot = i;
             admit_query<LS>(s_M, mp, lv, i, roots);
-            kept = true;
-            kept_slot = i;
+            // Tile 0 of the new query goes to the work queue like any other
+            // tile.  This workgroup still holds the queue position it
+            // reserved before admitting: were it to keep tiles for itself
+            // now, the item that lands in that position would wait for its
+            // whole chain of levels, and once the ring wrapped onto that
+            // cell every producer would wait for it too (LHS_ESTALL).
+            if (tid == 0)
+                enqueue_item(qs, ring, i, 0u);
             continue;
         }
         kept = false;

@@ -33,7 +33,9 @@
 // Part 4, the persistent server: a host thread posts queries (a slot's
 // constants and table, then an admission entry, then the admission tail)
 // to running workers and collects completion records; workers hold one ring
-// position each (fetch-and-add) and take admissions between polls; the
+// position each (fetch-and-add) and take admissions between polls, queueing
+// the admitted query's first tile (a worker keeps tiles for itself only
+// when it holds no position); the
 // launch ends when its workers leave after a quiet spell, or early when the
 // host asks it to drain, and the host starts another for queries posted too
 // late.  Leaving and admitting announce themselves before each looks at the
@@ -93,6 +95,10 @@
 //                                                only once they are appended
 //  15 count states appended in the middle of a tile only when the tile ends
 //     (caught by the unsanitized repeated run of part 7: `model part7 N`)
+//  16 a worker that admits a query keeps its first tile while it still holds
+//     a ring position (part 4; unsanitized repeated runs, `model part4 N`,
+//     stop with a producer waiting on that position's cell in about 1 run
+//     of 20 to 500, depending on how busy the host is)
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -794,7 +800,19 @@ void serve_worker(Server &S) {
             m.lv.tiles_total = 1;
             m.lv.tile_rows = kTileRows;
             m.lv.tiles_done.store(0, std::memory_order_relaxed);
+#if PLANT == 16
             kept = true;
+#else
+            // tile 0 goes to the queue like any other tile: this worker still
+            // holds the position it reserved before admitting, and a worker
+            // that keeps tiles for itself while holding one leaves the item
+            // that lands there waiting for its whole chain of levels, until
+            // the ring wraps onto that cell and every producer stops
+            if (!ring_put(q, q.tail.fetch_add(1, std::memory_order_relaxed), mi, 0)) {
+                q.error.store(2, std::memory_order_relaxed);
+                break;
+            }
+#endif
             continue;
         }
         expand_tile(m, tile, q);
@@ -1509,12 +1527,13 @@ int part7() {
 }  // namespace
 
 int main(int argc, char **argv) {
-    if (argc == 3 && std::strcmp(argv[1], "part7") == 0) {
-        // part 7 alone, repeated (built without a sanitizer, its threads
+    if (argc == 3 && (std::strcmp(argv[1], "part4") == 0 || std::strcmp(argv[1], "part7") == 0)) {
+        // part 4 or 7 alone, repeated (built without a sanitizer, threads
         // interleave far more finely)
+        const bool four = argv[1][4] == '4';
         int bad = 0;
         for (int i = 0, n = std::atoi(argv[2]); i < n; ++i)
-            bad += part7();
+            bad += four ? part4() : part7();
         printf("errors %d\n", bad);
         return bad ? 1 : 0;
     }

@@ -73,11 +73,26 @@ def test_gpu_protocol_model_catches_planted_mistakes(tmp_path, plant, what):
     assert "ThreadSanitizer: data race" in r.stderr or r.returncode != 0, f"not caught: {what}"
 
 
-def _exploration_stress(tmp_path, plant):
+def _stress(tmp_path, plant, part, reps):
     exe = str(tmp_path / f"gpu_protocol_model_o2_{plant}")
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-pthread", f"-DPLANT={plant}",
                            os.path.join(HERE, "gpu_protocol_model.cpp"), "-o", exe])
-    return subprocess.run([exe, "part7", "20"], capture_output=True, text=True, timeout=600)
+    return subprocess.run([exe, part, str(reps)], capture_output=True, text=True, timeout=600)
+
+
+def _exploration_stress(tmp_path, plant):
+    return _stress(tmp_path, plant, "part7", 20)
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_persistent_server_stress(tmp_path):
+    """The persistent server, 200 runs of 160 queries without a sanitizer:
+    every query's result equals a sequential BFS and no producer waits for
+    a cell that is never freed.  (Keeping an admitted query's first tile
+    while holding a ring position, an earlier rule, stops here in about one
+    run of 20 to 500.)"""
+    r = _stress(tmp_path, 0, "part4", 200)
+    assert r.returncode == 0 and r.stdout.strip().endswith("errors 0"), r.stdout[-3000:]
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
