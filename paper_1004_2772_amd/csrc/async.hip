@@ -33,9 +33,9 @@
 // makes visible (another workgroup may expand them, and subtract them,
 // before the tile ends).  So work only reaches 0 when no state is open
 // anywhere (queued, buffered or in a tile in flight); then no state can be
-// discovered again and every workgroup leaves.  The order of expansion varies from run to run, so
-// per-level counts are not defined; the reachable set, edges and deadlocks
-// are (they do not depend on the order).
+// discovered again and every workgroup leaves.  The order of expansion
+// varies from run to run, so per-level counts are not defined; the
+// reachable set, edges and deadlocks are (they do not depend on the order).
 #include <algorithm>
 #include <cstring>
 
