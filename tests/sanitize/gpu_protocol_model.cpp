@@ -78,7 +78,10 @@
 // count is zero.
 // Checked per run: the queue lists the reachable set of a sequential BFS
 // exactly once, every entry is expanded exactly once, the edges are all
-// counted and the work count ends at zero.
+// counted and the work count ends at zero.  With a cap inside the state
+// space the append that passes it stops every worker (at its next tile, or
+// in a wait for an entry), and then every stored state is listed once and
+// is reachable.
 //
 // Planted mistakes (compile with -DPLANT=n) remove one ordering or check
 // each; the test expects TSan (or a result check) to catch every one:
@@ -1300,6 +1303,8 @@ struct AsyncRun {
     std::unique_ptr<std::atomic<uint8_t>[]> expanded;     // per entry, for the check
     std::atomic<uint32_t> n_next{1}, chunk{0}, error{0};
     std::atomic<uint64_t> work{1}, edges{0};
+    uint32_t limit = 0xFFFFFFFFu;          // states stored before the run stops (the cap)
+    std::atomic<uint32_t> abort{0};        // set by the append that passed it
     // the smallest cursor a leaving worker saw after deciding to leave: below
     // the final cursor, a worker left while states were still to be found
     std::atomic<uint32_t> left_at_min{0xFFFFFFFFu};
@@ -1330,6 +1335,8 @@ void async_worker(AsyncRun &r) {
         }
 #endif
         const uint32_t at = r.n_next.fetch_add((uint32_t)nbuf.size(), std::memory_order_relaxed);
+        if ((uint64_t)at + nbuf.size() > r.limit)
+            r.abort.store(1, std::memory_order_relaxed);   // past the cap: every worker stops
         for (uint32_t i = 0; i < nbuf.size(); ++i)
 #if PLANT == 13
             r.queue[at + i].store(nbuf[i], std::memory_order_relaxed);
@@ -1367,7 +1374,8 @@ void async_worker(AsyncRun &r) {
                 act = kPublish;   // this chunk is dry: hold nothing back
                 break;
             }
-            if (r.work.load(std::memory_order_relaxed) == 0 || r.error.load(std::memory_order_relaxed))
+            if (r.work.load(std::memory_order_relaxed) == 0 || r.abort.load(std::memory_order_relaxed) ||
+                r.error.load(std::memory_order_relaxed))
                 break;
             if (tl != last_tail) {
                 last_tail = tl;
@@ -1391,8 +1399,11 @@ void async_worker(AsyncRun &r) {
             flush();
             continue;
         }
+        if (r.abort.load(std::memory_order_relaxed))
+            break;   // the tile's start: the run has passed its cap
         uint64_t edges = 0;
-        for (uint64_t e = from; e < from + take; ++e) {
+        bool stop = false;
+        for (uint64_t e = from; e < from + take && !stop; ++e) {
             // the entry is below the cursor but may still be in flight
             uint32_t slot, spins = 0;
             while ((slot = r.queue[e].load(std::memory_order_acquire)) == kNoEntryM) {
@@ -1400,8 +1411,14 @@ void async_worker(AsyncRun &r) {
                     r.error.store(4, std::memory_order_relaxed);
                     return;
                 }
+                if ((spins & 63u) == 0 && r.abort.load(std::memory_order_relaxed)) {
+                    stop = true;   // the writer may have stopped
+                    break;
+                }
                 std::this_thread::yield();
             }
+            if (stop)
+                break;
             r.expanded[e].fetch_add(1, std::memory_order_relaxed);
             std::memcpy(row.data(), &r.t.data[(size_t)slot * W], W * 4u);   // the row (payload)
             r.m.successors(row.data(), succ);
@@ -1427,7 +1444,13 @@ void async_worker(AsyncRun &r) {
 #endif
         r.work.fetch_add((uint64_t)(now - found) - (uint64_t)take, std::memory_order_relaxed);
         found = now;
+        if (stop)
+            break;
     }
+    // the end of the launch: states still held back are listed too (every
+    // stored state is in the queue)
+    if (!nbuf.empty())
+        flush();
 }
 
 // Sequential BFS of the model: the reachable set and the edge count.
@@ -1449,7 +1472,8 @@ void async_reference(const AsyncModel &m, std::set<std::vector<uint32_t>> &seen,
 
 // One exploration; returns 1 on a wrong result, and sets `early` when a
 // worker left while states were still to be found.
-int async_run(const AsyncModel &m, uint32_t nw, uint32_t chunk, uint32_t buf, uint32_t pass, bool &early) {
+int async_run(const AsyncModel &m, uint32_t nw, uint32_t chunk, uint32_t buf, uint32_t pass, bool &early,
+              uint32_t limit = 0xFFFFFFFFu) {
     std::set<std::vector<uint32_t>> want;
     uint64_t want_edges = 0;
     async_reference(m, want, want_edges);
@@ -1457,6 +1481,7 @@ int async_run(const AsyncModel &m, uint32_t nw, uint32_t chunk, uint32_t buf, ui
     while (cap < 4 * want.size())
         cap <<= 1;
     AsyncRun r(m, nw, chunk, buf, pass, cap);
+    r.limit = limit;
     const uint32_t W = m.W();
     // s0 is entry 0, inserted before the launch
     std::vector<uint32_t> s0(W, 0);
@@ -1480,8 +1505,20 @@ int async_run(const AsyncModel &m, uint32_t nw, uint32_t chunk, uint32_t buf, ui
         once &= r.expanded[e].load() == 1;
     }
     early = r.left_at_min.load() < n;
-    const bool ok = r.error.load() == 0 && n == want.size() && got == want && once && r.edges.load() == want_edges &&
-                    r.work.load() == 0;
+    bool ok;
+    if (want.size() <= limit) {
+        ok = r.error.load() == 0 && !r.abort.load() && n == want.size() && got == want && once &&
+             r.edges.load() == want_edges && r.work.load() == 0;
+    } else {
+        // past the cap: the run stopped; everything stored is listed once
+        // and is reachable
+        uint32_t stored = 0;
+        for (uint32_t s = 0; s < r.t.capacity(); ++s)
+            stored += (r.t.slot[s].load() & kDone) != 0;
+        ok = r.error.load() == 0 && r.abort.load() && n > limit && got.size() == n && stored == n &&
+             std::includes(want.begin(), want.end(), got.begin(), got.end());
+        early = false;   // leaving at the cap is the point
+    }
     if (!ok)
         printf("part7: %s N=%u L=%u F=%u workers=%u chunk=%u: %u entries, %zu distinct listed, %zu reachable, "
                "all expanded once %u, edges %llu of %llu, work %llu, error %u WRONG\n",
@@ -1507,6 +1544,16 @@ int part7() {
                 bool e = false;
                 bad += async_run(m, nw, sh[0], sh[1], sh[2], e);
                 early += e;
+                ++runs;
+            }
+    // with a cap inside the state space: every worker stops, nothing
+    // unreachable is listed, and every stored state is listed
+    for (const auto &sh : shapes)
+        for (uint32_t nw : workers)
+            for (const auto &mc : {std::make_pair(models[0], 100u), std::make_pair(models[2], 300u),
+                                   std::make_pair(models[6], 50u), std::make_pair(models[7], 120u)}) {
+                bool e = false;
+                bad += async_run(mc.first, nw, sh[0], sh[1], sh[2], e, mc.second);
                 ++runs;
             }
     // the broom's fan again, many times: a worker that expands a state
