@@ -28,9 +28,13 @@ constexpr uint32_t kBarrierSpinLimit = 1u << 24;   // bound on every queue wait
 //
 // The workgroups need not all be resident at once (the launch is a plain
 // one, sized to what fits): a workgroup only ever waits for a cell that a
-// running workgroup fills (a finaliser, which itself waits only for free
-// cells, and the ring holds one full level of every model), so one that
-// starts late takes its first item, or finds the batch finished, and leaves.
+// running workgroup fills (a finaliser, or in the server the workgroup that
+// admits a query, each of which waits only for free cells, and the ring
+// holds one full level of every model), so one that starts late takes its
+// first item, or finds the batch finished, and leaves.  A workgroup runs a
+// tile that is not a queue item (a finaliser's tile 0 of the next level)
+// only when it holds no queue position: an item filled into a position its
+// holder is not polling would wait, and the ring could wrap onto it.
 
 struct QCell {
     unsigned long long seq;
